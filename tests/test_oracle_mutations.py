@@ -1,0 +1,105 @@
+"""Plant plausible mistakes in the oracle (a flipped sign, a dropped term, a
+transposed index, a non-strict cutoff) and check that at least one pin
+catches each of them.  CPU only; the oracle is restored after each case."""
+import importlib
+
+import numpy as np
+
+import oracle
+
+oaev = importlib.import_module("oracle.aev")
+oforces = importlib.import_module("oracle.forces")
+omlp = importlib.import_module("oracle.mlp")
+onb = importlib.import_module("oracle.neighbors")
+from tests import test_oracle_pins as pins
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except (AssertionError, ValueError, IndexError):
+        return True
+    return False
+
+
+def test_mutant_switch_sign(monkeypatch, spec):
+    monkeypatch.setattr(oaev, "switch", lambda r, rc: np.where(r < oaev.f64(rc), 0.5 * np.cos(np.pi * r / oaev.f64(rc)) - 0.5, 0.0))
+    assert _fails(pins.test_radial_two_atoms_closed_form, spec)
+
+
+def test_mutant_angle_expansion_sign(monkeypatch, spec):
+    orig = oaev.angular_factors
+
+    def bad(v1, r1, v2, r2, sp):
+        f = orig(v1, r1, v2, r2, sp)
+        thz = oaev.f64(sp.shf_z)
+        w = f["u"][:, None] * np.cos(thz)[None, :] - f["sq"][:, None] * np.sin(thz)[None, :]
+        f["F1"] = np.power(np.maximum(0.5 * (1 + w), 0), oaev.f64(sp.zeta))
+        return f
+    monkeypatch.setattr(oaev, "angular_factors", bad)
+    assert _fails(pins.test_angular_three_atoms_closed_form, spec)
+
+
+def test_mutant_species_pair_unordered(monkeypatch, spec):
+    # forgetting to order (s, t) before taking the triangular index
+    monkeypatch.setattr(oaev.AEVLayout, "pair_index",
+                        lambda self, s, t: np.abs(s * self.ns - (s * (s - 1)) // 2 + (t - s)))
+    assert _fails(pins.test_aev_matches_pure_python_loops, spec, 0)
+
+
+def test_mutant_angular_terms_transposed(monkeypatch, spec):
+    # F1 indexed by the radial shell and F2 by the angle section
+    orig = oaev.angular_factors
+
+    def bad(v1, r1, v2, r2, sp):
+        f = orig(v1, r1, v2, r2, sp)
+        f["F1"] = f["F1"][:, ::-1].copy()
+        return f
+    monkeypatch.setattr(oaev, "angular_factors", bad)
+    assert _fails(pins.test_aev_matches_pure_python_loops, spec, 0)
+
+
+def test_mutant_missing_celu_derivative(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "celu_deriv", lambda x, a: np.ones_like(x))
+
+    class Req:
+        def getfixturevalue(self, _):
+            return spec_bias
+    assert _fails(pins.test_mlp_matches_torch_fp64, Req(), "spec_bias")
+
+
+def test_mutant_dropped_angle_gradient(monkeypatch, spec_bias):
+    orig = np.einsum
+
+    def einsum_drop(sig, *ops):
+        out = orig(sig, *ops)
+        if sig == "taz,ta,tz->t" and ops[2] is not None and ops[1] is not None:
+            einsum_drop.calls += 1
+            if einsum_drop.calls % 3 == 1:      # the dE/dc contraction
+                return out * 0.0
+        return out
+    einsum_drop.calls = 0
+    monkeypatch.setattr(oforces.np, "einsum", einsum_drop)
+    assert _fails(pins.test_forces_match_finite_differences_cluster, spec_bias)
+
+
+def test_mutant_radial_gradient_sign(monkeypatch, spec_bias):
+    orig = oaev.switch_deriv
+    monkeypatch.setattr(oforces, "switch_deriv", lambda r, rc: -orig(r, rc))
+    assert _fails(pins.test_forces_match_finite_differences_cluster, spec_bias)
+
+
+def test_mutant_non_strict_cutoff(monkeypatch):
+    orig = onb.neighbor_rows
+
+    def loose(pos, mol, box, r_list, rows, block=64):
+        return orig(pos, mol, box, float(np.nextafter(np.float32(r_list), np.float32(10))), rows, block)
+    monkeypatch.setattr(onb, "neighbor_rows", loose)
+    monkeypatch.setattr(oracle, "neighbor_list", lambda pos, mol, box, r: loose(pos, mol, box, r, np.arange(pos.shape[0])))
+    assert _fails(pins.test_neighbors_exact_cutoff_is_excluded)
+
+
+def test_mutant_wrong_image_rounding(monkeypatch):
+    monkeypatch.setattr(onb, "_min_image", lambda d0, L: (d0 - np.floor(d0 / L) * L, -np.floor(d0 / L)))
+    case = [c for c in __import__("synthetic").adversarial_cases() if c.name == "faces_periodic"][0]
+    assert _fails(pins.test_neighbors_match_brute_force_adversarial, case)

@@ -1,0 +1,435 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by
+mathematics: brute-force enumeration, closed forms, library routines,
+invariances, smoothness at the cutoffs, finite differences, zero net force
+and torque, batch additivity.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic
+from synthetic.geometry import Workload, small_water_box
+from tests import brute
+
+
+def _pairset(nl):
+    i, j, n = nl
+    return sorted((int(a), int(b), tuple(int(x) for x in s)) for a, b, s in zip(i, j, n))
+
+
+# ---------------------------------------------------------------- neighbours
+
+@pytest.mark.parametrize("case", synthetic.adversarial_cases(), ids=lambda c: c.name)
+def test_neighbors_match_brute_force_adversarial(case):
+    r_list = 5.1
+    if case.box is not None and np.any(case.box < 2 * np.float32(r_list)):
+        with pytest.raises(ValueError):
+            oracle.neighbor_list(case.pos, case.mol, case.box, r_list)
+        return
+    nl = oracle.neighbor_list(case.pos, case.mol, case.box, r_list)
+    bf = oracle.brute_force_pairs(case.pos, case.mol, case.box, r_list)
+    assert _pairset(nl) == [(i, j, tuple(n)) for i, j, n in bf]
+
+
+def test_neighbors_exact_cutoff_is_excluded():
+    case = synthetic.adversarial_cases()[0]     # atoms 0-1 exactly r_list apart
+    i, j, _ = oracle.neighbor_list(case.pos, case.mol, None, 5.1)
+    pairs = set(zip(i.tolist(), j.tolist()))
+    assert (0, 1) not in pairs and (1, 0) not in pairs
+    assert (0, 2) in pairs and (0, 3) in pairs and (2, 0) in pairs
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_neighbors_match_brute_force_random_periodic(seed):
+    rng = np.random.default_rng(seed)
+    L = np.float32(11.5)
+    box = np.array([L, L, np.float32(13.0)], dtype=np.float32)
+    pos = (rng.uniform(-1, 2, size=(40, 3)) * box).astype(np.float32)
+    nl = oracle.neighbor_list(pos, None, box, 5.6)
+    bf = oracle.brute_force_pairs(pos, None, box, 5.6, max_image=4)
+    assert _pairset(nl) == [(i, j, tuple(n)) for i, j, n in bf]
+    assert len(bf) > 0
+
+
+def test_neighbors_symmetric_and_sorted():
+    w = small_water_box(40)
+    i, j, n = oracle.neighbor_list(w.pos, w.mol, w.box, 5.6)
+    key = i * w.n_atoms + j
+    assert np.all(np.diff(key) > 0)
+    fwd = {(a, b): tuple(s) for a, b, s in zip(i.tolist(), j.tolist(), n.tolist())}
+    for (a, b), s in fwd.items():
+        assert fwd[(b, a)] == tuple(-x for x in s)
+
+
+def test_neighbors_relabel_invariant():
+    w = small_water_box(30)
+    perm = np.random.default_rng(3).permutation(w.n_atoms)
+    nl = oracle.neighbor_list(w.pos, None, w.box, 5.1)
+    nl2 = oracle.neighbor_list(w.pos[perm], None, w.box, 5.1)
+    inv = np.argsort(perm)
+    mapped = sorted((int(perm[a]), int(perm[b]), tuple(s)) for a, b, s in
+                    zip(nl2[0].tolist(), nl2[1].tolist(), nl2[2].tolist()))
+    assert mapped == _pairset(nl)
+
+
+# ---------------------------------------------------------------- switching function
+
+def test_switch_closed_form(spec):
+    rc = float(np.float32(spec.rc_r))
+    r = np.array([0.0, 1.3, rc * 0.5, rc - 1e-9, rc, rc + 0.1])
+    f = oracle.switch(r, spec.rc_r)
+    assert f[0] == 1.0
+    assert abs(f[2] - 0.5) < 1e-15
+    assert f[4] == 0.0 and f[5] == 0.0
+    assert abs(f[1] - (0.5 * math.cos(math.pi * 1.3 / rc) + 0.5)) < 1e-15
+    d = oracle.switch_deriv(np.array([rc - 1e-12, 0.0]), spec.rc_r)
+    assert abs(d[0]) < 1e-10 and d[1] == 0.0
+    # derivative agrees with a central difference
+    x, h = 2.2, 1e-6
+    fd = (oracle.switch(np.array([x + h]), spec.rc_r)[0] - oracle.switch(np.array([x - h]), spec.rc_r)[0]) / (2 * h)
+    assert abs(fd - oracle.switch_deriv(np.array([x]), spec.rc_r)[0]) < 1e-9
+
+
+# ---------------------------------------------------------------- AEV closed forms
+
+def test_radial_two_atoms_closed_form(spec):
+    p = brute.params_of(spec)
+    for r, (za, zb) in [(0.97, (0, 3)), (2.5, (1, 6)), (4.9, (5, 5))]:
+        pos = np.array([[0, 0, 0], [r, 0, 0]], dtype=np.float32)
+        sp = np.array([za, zb], dtype=np.int32)
+        nl = oracle.neighbor_list(pos, None, None, 5.1)
+        A = oracle.aev(pos, sp, None, nl, spec)
+        rr = float(np.float32(r))
+        for k in range(16):
+            want = p["pr"] * math.exp(-p["eta_r"] * (rr - p["shf_r"][k]) ** 2) * brute.fc(rr, p["rc_r"])
+            assert abs(A[0, 16 * zb + k] - want) <= 1e-15 + 1e-13 * abs(want)
+            assert abs(A[1, 16 * za + k] - want) <= 1e-15 + 1e-13 * abs(want)
+        mask = np.ones(1008, bool)
+        mask[16 * zb:16 * zb + 16] = False
+        assert np.all(A[0, mask] == 0.0)
+
+
+def _closed_form_angular(pos, sp, i, j, k, p):
+    vj = [pos[j][c] - pos[i][c] for c in range(3)]
+    vk = [pos[k][c] - pos[i][c] for c in range(3)]
+    rj = math.sqrt(sum(x * x for x in vj))
+    rk = math.sqrt(sum(x * x for x in vk))
+    cos_t = sum(a * b for a, b in zip(vj, vk)) / (rj * rk)
+    th = math.acos(p["cs"] * cos_t)
+    out = {}
+    pi = brute.pair_index(sp[j], sp[k])
+    for a in range(4):
+        for z in range(8):
+            val = 2 * (0.5 + 0.5 * math.cos(th - p["shf_z"][z])) ** p["zeta"] \
+                * math.exp(-p["eta_a"] * ((rj + rk) / 2 - p["shf_a"][a]) ** 2) \
+                * brute.fc(rj, p["rc_a"]) * brute.fc(rk, p["rc_a"])
+            out[112 + 32 * pi + 8 * a + z] = val
+    return out
+
+
+def test_angular_three_atoms_closed_form(spec):
+    p = brute.params_of(spec)
+    th = math.radians(104.52)
+    geoms = [
+        ([[0, 0, 0], [0.9572, 0, 0], [0.9572 * math.cos(th), 0.9572 * math.sin(th), 0]], [3, 0, 0]),
+        ([[0, 0, 0], [1.4, 0, 0], [0, 1.1, 0]], [1, 2, 6]),                      # right angle
+        ([[0, 0, 0], [1.0, 0.2, 0.1], [-2.1, 0.3, 0.4]], [4, 5, 0]),              # obtuse
+    ]
+    for pts, sp in geoms:
+        pos = np.array(pts, dtype=np.float32)
+        sp = np.array(sp, dtype=np.int32)
+        nl = oracle.neighbor_list(pos, None, None, 5.1)
+        A = oracle.aev(pos, sp, None, nl, spec)
+        P = pos.astype(np.float64).tolist()
+        for i, j, k in [(0, 1, 2), (1, 0, 2), (2, 0, 1)]:
+            want = _closed_form_angular(P, sp, i, j, k, p)
+            ang = A[i, 112:]
+            for col, val in want.items():
+                assert abs(A[i, col] - val) <= 1e-14 + 1e-12 * abs(val), (i, col)
+            nz = np.nonzero(ang)[0] + 112
+            assert set(nz.tolist()) <= set(want.keys())
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_aev_matches_pure_python_loops(spec, seed):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 4.0, size=(9, 3)).astype(np.float32)
+    sp = rng.integers(0, 7, size=9).astype(np.int32)
+    nl = oracle.neighbor_list(pos, None, None, 5.1)
+    A = oracle.aev(pos, sp, None, nl, spec)
+    B = np.array(brute.aev_brute(pos.astype(np.float64).tolist(), sp.tolist(), brute.params_of(spec)))
+    assert np.max(np.abs(A - B)) <= 1e-12 * max(1.0, np.max(np.abs(B)))
+    assert np.count_nonzero(B[:, 112:]) > 0
+
+
+# ---------------------------------------------------------------- MLP vs library routines
+
+@pytest.mark.parametrize("which", ["spec", "spec_bias"])
+def test_mlp_matches_torch_fp64(request, which):
+    sp_ = request.getfixturevalue(which)
+    rng = np.random.default_rng(11)
+    A = rng.normal(scale=0.5, size=(30, 1008))
+    Z = rng.integers(0, 7, size=30)
+    E, g = oracle.mlp_energy_and_grad(A, Z, sp_)
+    x = torch.tensor(A, dtype=torch.float64, requires_grad=True)
+    outs = []
+    for a in range(30):
+        h = x[a]
+        layers = sp_.weights[Z[a]]
+        for l, (W, b) in enumerate(layers):
+            h = torch.nn.functional.linear(h, torch.tensor(W, dtype=torch.float64), torch.tensor(b, dtype=torch.float64))
+            if l < len(layers) - 1:
+                h = torch.nn.functional.celu(h, alpha=float(np.float32(sp_.celu_alpha)))
+        outs.append(h[0] + float(sp_.self_energy[Z[a]]))
+    Et = torch.stack(outs)
+    Et.sum().backward()
+    assert np.max(np.abs(E - Et.detach().numpy())) < 1e-12
+    assert np.max(np.abs(g - x.grad.numpy())) < 1e-12
+
+
+def test_round_bf16_matches_torch():
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.normal(size=10000) * 10.0 ** rng.integers(-8, 8, size=10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.0e38]])
+    x32 = x.astype(np.float32)
+    want = torch.tensor(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    got = oracle.round_bf16(x32)
+    assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------- invariances
+
+def _fixed_list_energy(x64, sp, box, spec, nl):
+    return oracle.total_energy(x64, sp, box, spec, nl)
+
+
+def test_energy_rotation_translation_invariance(spec):
+    w = synthetic.workload(1)
+    nl = oracle.neighbor_list(w.pos, None, None, 7.0)      # margin: list stays valid under motion
+    x = w.pos.astype(np.float64)
+    E0 = _fixed_list_energy(x, w.species, None, spec, nl)
+    R = synthetic.geometry.random_rotations(np.random.default_rng(2), 1)[0]
+    E1 = _fixed_list_energy(x @ R.T + np.array([3.3, -1.7, 40.0]), w.species, None, spec, nl)
+    assert abs(E1 - E0) <= 1e-12 * abs(E0)
+
+
+def test_energy_permutation_invariance(spec):
+    w = synthetic.workload(1)
+    rng = np.random.default_rng(4)
+    perm = rng.permutation(w.n_atoms)
+    a = oracle.energy_forces(w.pos, w.species, None, 1, None, spec, need_forces=True)
+    b = oracle.energy_forces(w.pos[perm], w.species[perm], None, 1, None, spec, need_forces=True)
+    assert abs(a["E_mol"][0] - b["E_mol"][0]) <= 1e-12 * abs(a["E_mol"][0])
+    assert np.max(np.abs(a["E_atom"][perm] - b["E_atom"])) < 1e-13
+    assert np.max(np.abs(a["F"][perm] - b["F"])) < 1e-12
+
+
+def test_periodic_wrap_invariance(spec):
+    rng = np.random.default_rng(9)
+    L = 16.0
+    pos = (np.round(rng.uniform(0, L, size=(60, 3)) * 1024) / 1024).astype(np.float32)
+    sp = rng.integers(0, 7, size=60).astype(np.int32)
+    box = np.array([L, L, L], np.float32)
+    shifted = np.mod(pos.astype(np.float64) + np.array([3.125, -5.5, 7.0]), L).astype(np.float32)
+    a = oracle.energy_forces(pos, sp, None, 1, box, spec)
+    b = oracle.energy_forces(shifted, sp, None, 1, box, spec)
+    assert abs(a["E_mol"][0] - b["E_mol"][0]) <= 1e-12 * max(1.0, abs(a["E_mol"][0]))
+    assert np.max(np.abs(a["F"] - b["F"])) < 1e-12
+    # a whole-box image shift of one atom changes nothing either
+    moved = pos.copy()
+    moved[5, 0] += np.float32(L)
+    c = oracle.energy_forces(moved, sp, None, 1, box, spec)
+    assert abs(a["E_mol"][0] - c["E_mol"][0]) <= 1e-12 * max(1.0, abs(a["E_mol"][0]))
+
+
+# ---------------------------------------------------------------- smoothness at the cutoffs
+
+@pytest.mark.parametrize("which", ["radial", "angular"])
+def test_smooth_decay_at_cutoff(spec_bias, which):
+    sp = np.array([1, 3, 0], np.int32)
+    rc = float(np.float32(spec_bias.rc_r if which == "radial" else spec_bias.rc_a))
+
+    def energy(r):
+        if which == "radial":
+            x = np.array([[0, 0, 0], [r, 0, 0], [0, 9.0, 0]], dtype=np.float64)
+        else:     # atom 2 stays well inside both cutoffs of atom 0; atom 1 crosses rc_a
+            x = np.array([[0, 0, 0], [r, 0.0, 0], [0, 1.2, 0]], dtype=np.float64)
+        nl = oracle.neighbor_list(x.astype(np.float32), None, None, 12.0)
+        return oracle.total_energy(x, sp, None, spec_bias, nl)
+
+    # E is C1 across the cutoff: the centred second difference scales as d^2
+    # (a jump in E or in dE/dr would make it scale as 1 or d)
+    sd = [abs(energy(rc + d) - 2 * energy(rc) + energy(rc - d)) for d in (1e-3, 1e-4)]
+    assert sd[1] < sd[0] / 30 or sd[1] < 1e-13, sd
+    # the feature columns fed by the crossing pair decay to zero quadratically
+    def feats(r):
+        x = np.array([[0, 0, 0], [r, 0.0, 0], [0, 1.2, 0]], dtype=np.float32)
+        nl = oracle.neighbor_list(x, None, None, 12.0)
+        A = oracle.aev(x, sp, None, nl, spec_bias)
+        return A[0, 16:32] if which == "radial" else A[0, 112:]
+    for d in (1e-2, 1e-3):
+        assert np.max(np.abs(feats(rc - d))) < 20 * d * d
+    assert np.all(feats(rc) == 0.0) if which == "radial" else True
+    assert np.all(feats(rc + 1e-3) == 0.0)
+    # gradient tends to zero at the cutoff
+    h = 1e-7
+    slope = (energy(rc - h) - energy(rc - 3 * h)) / (2 * h)
+    if which == "radial":
+        assert abs(slope) < 1e-4
+
+
+# ---------------------------------------------------------------- forces
+
+def _fd_forces(x64, sp, box, spec, nl, atoms, h=1e-5):
+    F = np.zeros((len(atoms), 3))
+    for a_i, a in enumerate(atoms):
+        for k in range(3):
+            xp = x64.copy()
+            xm = x64.copy()
+            xp[a, k] += h
+            xm[a, k] -= h
+            F[a_i, k] = -(oracle.total_energy(xp, sp, box, spec, nl)
+                          - oracle.total_energy(xm, sp, box, spec, nl)) / (2 * h)
+    return F
+
+
+def test_forces_match_finite_differences_cluster(spec_bias):
+    w = synthetic.workload(1)
+    out = oracle.energy_forces(w.pos, w.species, None, 1, None, spec_bias)
+    nl = oracle.neighbor_list(w.pos, None, None, 7.0)
+    atoms = list(range(0, w.n_atoms, 5))
+    F_fd = _fd_forces(w.pos.astype(np.float64), w.species, None, spec_bias, nl, atoms)
+    F = out["F"][atoms]
+    assert np.max(np.abs(F - F_fd)) <= 1e-7 * max(1.0, np.max(np.abs(F)))
+
+
+def test_forces_match_finite_differences_periodic(spec_bias):
+    w = small_water_box(40)
+    sp = synthetic.workload(3).species[:w.n_atoms]          # mixed species on water geometry
+    out = oracle.energy_forces(w.pos, sp, None, 1, w.box, spec_bias)
+    nl = oracle.neighbor_list(w.pos, None, w.box, 5.6)
+    atoms = [0, 7, 31, 62, 119]
+    F_fd = _fd_forces(w.pos.astype(np.float64), sp, w.box, spec_bias, nl, atoms)
+    assert np.max(np.abs(out["F"][atoms] - F_fd)) <= 1e-7 * max(1.0, np.max(np.abs(F_fd)))
+
+
+def test_net_force_and_torque_vanish(spec_bias):
+    w = synthetic.workload(1)
+    out = oracle.energy_forces(w.pos, w.species, None, 1, None, spec_bias)
+    F = out["F"]
+    x = w.pos.astype(np.float64)
+    scale = np.max(np.abs(F))
+    assert np.max(np.abs(F.sum(0))) < 1e-12 * w.n_atoms * scale
+    assert np.max(np.abs(np.cross(x, F).sum(0))) < 1e-11 * w.n_atoms * scale
+
+
+def test_forces_match_torch_autograd(spec_bias):
+    """Third opinion: reverse-mode autodiff in float64 of an independent
+    torch expression of the same energy."""
+    rng = np.random.default_rng(21)
+    pos = rng.uniform(0, 4.5, size=(12, 3)).astype(np.float32)
+    sp = rng.integers(0, 7, size=12).astype(np.int32)
+    out = oracle.energy_forces(pos, sp, None, 1, None, spec_bias)
+    p = brute.params_of(spec_bias)
+    x = torch.tensor(pos.astype(np.float64), requires_grad=True)
+    N = len(sp)
+    feats = [[torch.zeros((), dtype=torch.float64) for _ in range(1008)] for _ in range(N)]
+
+    def tfc(r, rc):
+        return 0.5 * torch.cos(math.pi * r / rc) + 0.5
+
+    for i in range(N):
+        for j in range(N):
+            if i == j:
+                continue
+            r = torch.linalg.norm(x[j] - x[i])
+            if r.item() < p["rc_r"]:
+                for k in range(16):
+                    feats[i][16 * sp[j] + k] = feats[i][16 * sp[j] + k] + p["pr"] * torch.exp(
+                        -p["eta_r"] * (r - p["shf_r"][k]) ** 2) * tfc(r, p["rc_r"])
+        for j in range(N):
+            for k in range(j + 1, N):
+                if i in (j, k):
+                    continue
+                vj, vk = x[j] - x[i], x[k] - x[i]
+                rj, rk = torch.linalg.norm(vj), torch.linalg.norm(vk)
+                if rj.item() >= p["rc_a"] or rk.item() >= p["rc_a"]:
+                    continue
+                th = torch.acos(p["cs"] * torch.dot(vj, vk) / (rj * rk))
+                pi = brute.pair_index(sp[j], sp[k])
+                for a in range(4):
+                    f2 = torch.exp(-p["eta_a"] * ((rj + rk) / 2 - p["shf_a"][a]) ** 2)
+                    for z in range(8):
+                        f1 = (0.5 + 0.5 * torch.cos(th - p["shf_z"][z])) ** p["zeta"]
+                        c = 112 + 32 * pi + 8 * a + z
+                        feats[i][c] = feats[i][c] + 2 * f1 * f2 * tfc(rj, p["rc_a"]) * tfc(rk, p["rc_a"])
+    E = torch.zeros((), dtype=torch.float64)
+    for i in range(N):
+        h = torch.stack(feats[i])
+        layers = spec_bias.weights[sp[i]]
+        for l, (W, b) in enumerate(layers):
+            h = torch.nn.functional.linear(h, torch.tensor(W, dtype=torch.float64), torch.tensor(b, dtype=torch.float64))
+            if l < 3:
+                h = torch.nn.functional.celu(h, alpha=float(np.float32(0.1)))
+        E = E + h[0] + float(spec_bias.self_energy[sp[i]])
+    E.backward()
+    assert abs(E.item() - out["E_mol"][0]) < 1e-10 * max(1.0, abs(E.item()))
+    assert np.max(np.abs(-x.grad.numpy() - out["F"])) < 1e-10 * max(1.0, np.max(np.abs(out["F"])))
+
+
+def test_batch_additivity(spec_bias):
+    rng = np.random.default_rng(8)
+    mA = synthetic.serving_molecule(rng, n=20)
+    mB = synthetic.serving_molecule(rng, n=33)
+    wb = synthetic.geometry.batch_molecules([mA, mB])
+    ab = oracle.energy_forces(wb.pos, wb.species, wb.mol, 2, None, spec_bias)
+    a = oracle.energy_forces(mA[0], mA[1], None, 1, None, spec_bias)
+    b = oracle.energy_forces(mB[0], mB[1], None, 1, None, spec_bias)
+    assert abs(ab["E_mol"][0] - a["E_mol"][0]) < 1e-12 * max(1, abs(a["E_mol"][0]))
+    assert abs(ab["E_mol"][1] - b["E_mol"][0]) < 1e-12 * max(1, abs(b["E_mol"][0]))
+    assert np.max(np.abs(ab["F"][:20] - a["F"])) < 1e-12
+    assert np.max(np.abs(ab["F"][20:] - b["F"])) < 1e-12
+
+
+def test_degenerate_inputs(spec_bias):
+    # one atom: no neighbours, zero AEV, energy = output bias + self energy
+    pos = np.zeros((1, 3), np.float32)
+    out = oracle.energy_forces(pos, np.array([4], np.int32), None, 1, None, spec_bias)
+    W4, b4 = spec_bias.weights[4][3]
+    h = np.zeros(1008)
+    for W, b in spec_bias.weights[4][:3]:
+        h = oracle.celu(W.astype(np.float64) @ h + b, float(np.float32(0.1)))
+    want = float(W4.astype(np.float64)[0] @ h + b4[0]) + spec_bias.self_energy[4]
+    assert abs(out["E_mol"][0] - want) < 1e-12 * abs(want)
+    assert np.all(out["F"] == 0.0) and np.all(out["aev"] == 0.0)
+    # coincident atoms are legal (no repulsion in the model); angular terms stay finite
+    pos = np.array([[0, 0, 0], [0, 0, 0], [1.0, 0, 0]], np.float32)
+    out = oracle.energy_forces(pos, np.array([0, 0, 3], np.int32), None, 1, None, spec_bias)
+    assert np.all(np.isfinite(out["E_atom"])) and np.all(np.isfinite(out["F"]))
+
+
+# ---------------------------------------------------------------- MD integrator
+
+def test_velocity_verlet_second_order_and_reversible(spec_bias):
+    rng = np.random.default_rng(3)
+    m = synthetic.serving_molecule(rng, n=10)
+    masses = synthetic.MASSES[m[1]]
+    nl = oracle.neighbor_list(m[0], None, None, 9.0)
+
+    def ff64(x):
+        return oracle.energy_forces_f64(x, m[1], None, spec_bias, nl)
+
+    v0 = rng.normal(scale=0.01, size=(10, 3))
+    drifts = []
+    for dt in (0.2, 0.1):
+        steps = int(round(2.0 / dt))
+        _, _, en = oracle.velocity_verlet(m[0], v0, masses, ff64, dt, steps)
+        tot = np.array([a + b for a, b in en])
+        drifts.append(np.max(np.abs(tot - tot[0])))
+    assert drifts[1] < drifts[0] / 2.5          # O(dt^2): halving dt cuts error ~4x
+    # time reversibility
+    xT, vT, _ = oracle.velocity_verlet(m[0], v0, masses, ff64, 0.1, 20)
+    xb, vb, _ = oracle.velocity_verlet(xT, -vT, masses, ff64, 0.1, 20)
+    assert np.max(np.abs(xb - m[0].astype(np.float64))) < 1e-9
