@@ -1,0 +1,230 @@
+/*
+ * nnp.h -- C ABI of the MI355X (gfx950) AEV neural-network potential.
+ *
+ * The library evaluates energy and forces of a symmetry-function atomic
+ * environment vector (AEV) potential with one multi-layer perceptron per
+ * chemical species -- the ANI-2x-shaped model the FeNNol paper benchmarks
+ * (Sec. 5, "Performance benchmarks"; model flow of Sec. 2.4: AEV, species
+ * network, per-structure energy sum, forces by differentiation).
+ *
+ * Conventions for every entry point:
+ *   - extern "C", C99 types, no exceptions cross the boundary; every call
+ *     returns an nnp_status (or a size / pointer as documented).
+ *   - "device" pointers are GPU memory owned by the caller (for example
+ *     torch tensors); "host" pointers are CPU memory owned by the caller.
+ *     The library owns only what a model or server allocates for itself.
+ *   - Streams are passed as an opaque `void*` holding a hipStream_t
+ *     (NULL = the default stream).  Work is enqueued on that stream only.
+ *   - Units: Angstrom, eV, eV/Angstrom, femtosecond, amu.
+ *   - Species are indices 0..n_species-1 (for ANI-2x: H, C, N, O, F, S, Cl).
+ *   - Atoms of one structure are contiguous and `mol` (the structure index
+ *     of every atom, Sec. 2.1: concatenated atoms plus a batch index) is
+ *     non-decreasing; mol == NULL means every atom belongs to structure 0.
+ *   - Argument errors detected on the host return immediately.  Errors only
+ *     visible on the device (species out of range, a neighbour row longer
+ *     than the kernels support, non-finite coordinates, a non-monotonic
+ *     `mol`) set sticky flags in the model; they are reported by the next
+ *     call that synchronises (nnp_neighbors, nnp_check) and cleared then.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NNP_OK = 0,
+    NNP_E_ARG = 1,        /* invalid argument (host-checked or device flag)       */
+    NNP_E_CAPACITY = 2,   /* neighbour-list capacity too small; size reported     */
+    NNP_E_BOX = 3,        /* a box side is below twice the list cutoff            */
+    NNP_E_NONFINITE = 4,  /* NaN or Inf coordinates                               */
+    NNP_E_NOMEM = 5,      /* device or host allocation failed / arena full        */
+    NNP_E_BUSY = 6,       /* serving: no free request slot                        */
+    NNP_E_PENDING = 7,    /* serving: the request has not completed yet           */
+    NNP_E_HIP = 8,        /* a HIP runtime call failed                            */
+    NNP_E_ROW = 9         /* an atom has more neighbours than the kernels support */
+} nnp_status;
+
+typedef enum {
+    NNP_FP32 = 0,         /* every stage in float32 (MLP on FP32 MFMA)            */
+    NNP_BF16_MLP = 1      /* MLP matrix products take bfloat16 inputs on MFMA with
+                             float32 accumulation; AEV, cutoffs, edge gradients and
+                             forces stay float32; structure energies float64      */
+} nnp_precision;
+
+/* Device error flags (bit set), as returned by nnp_check. */
+#define NNP_FLAG_SPECIES   0x1u   /* species index out of range                  */
+#define NNP_FLAG_ROW       0x2u   /* neighbour row longer than NNP_MAX_ROW        */
+#define NNP_FLAG_NONFINITE 0x4u   /* non-finite coordinate                        */
+#define NNP_FLAG_MOL       0x8u   /* mol not non-decreasing or out of [0, n_mol) */
+#define NNP_FLAG_SHIFT     0x10u  /* periodic image shift outside int8 range      */
+
+/* Largest neighbour-row length (pairs within the list cutoff of one atom) the
+ * AEV kernels accept.  Longer rows set NNP_FLAG_ROW and contribute nothing. */
+#define NNP_MAX_ROW 256
+/* Largest number of neighbours within the angular cutoff of one atom. */
+#define NNP_MAX_ANGULAR 96
+
+typedef struct nnp_model nnp_model;     /* opaque: AEV parameters + packed weights */
+typedef struct nnp_server nnp_server;   /* opaque: serving arena and scheduler     */
+
+/* AEV hyper-parameters (Sec. 2.1 cosine switching function; Sec. 2.2 Gaussian
+ * radial basis; App. A ANI angular basis).  Arrays are host memory, copied. */
+typedef struct {
+    int32_t n_species;        /* number of species (<= 8)                          */
+    float rc_r;               /* radial cutoff Rc_R (5.1)                          */
+    float eta_r;              /* radial Gaussian width eta_R (19.7)                */
+    int32_t n_shf_r;          /* number of radial shells (16)                      */
+    const float* shf_r;       /* [n_shf_r] radial shell centres R_k                */
+    float rc_a;               /* angular cutoff Rc_A (3.5), rc_a <= rc_r           */
+    float eta_a;              /* angular radial width eta_A (12.5)                 */
+    float zeta;               /* angular exponent zeta (14.1)                      */
+    int32_t n_shf_a;          /* number of angular radial shells (4)               */
+    int32_t n_shf_z;          /* number of angle sections (8)                      */
+    const float* shf_a;       /* [n_shf_a] angular radial shell centres R_a        */
+    const float* shf_z;       /* [n_shf_z] angle section centres theta_z           */
+    float radial_prefactor;   /* factor on every radial term (0.25)                */
+    float cos_scale;          /* cos(theta) is scaled by this before arccos (0.95) */
+} nnp_aev_params;
+
+/* Per-species MLP (Sec. 2.2, "Neural Networks": fully species-dependent
+ * parameters).  widths[0] must equal the AEV length; widths[n_layers] must
+ * be 1.  W[s*n_layers + l] is host float32 row-major [widths[l+1]][widths[l]];
+ * b[s*n_layers + l] is [widths[l+1]].  Copied at model creation. */
+typedef struct {
+    int32_t n_layers;           /* 4 for 1008-256-192-160-1                        */
+    const int32_t* widths;      /* [n_layers + 1]                                  */
+    const float* const* W;      /* [n_species * n_layers]                          */
+    const float* const* b;      /* [n_species * n_layers]                          */
+    float celu_alpha;           /* CELU alpha (0.1)                                */
+    const double* self_energy;  /* [n_species] added to every atomic energy, or NULL */
+} nnp_mlp_params;
+
+/* Caller-owned neighbour list (device memory): directed pairs i -> j of the
+ * same structure with |v_ij| < r_list, v_ij = x_j + shift * box - x_i
+ * (minimum image for periodic boxes).  Row i is col[row_ptr[i] ..
+ * row_ptr[i+1]) sorted by ascending j.  rev[p] is the index of the reverse
+ * pair j -> i.  Sec. 2.1, "Preprocessing Modules". */
+typedef struct {
+    int32_t* row_ptr;         /* [n_atoms + 1]                                     */
+    int32_t* col;             /* [capacity]                                        */
+    int8_t* shift;            /* [capacity][3] image shift in box vectors          */
+    int32_t* rev;             /* [capacity]                                        */
+    int64_t capacity;         /* entries available in col / shift / rev            */
+    float r_list;             /* cutoff the list was built with (set by nnp_neighbors) */
+    int32_t n_atoms;          /* set by nnp_neighbors                              */
+    int64_t n_pairs;          /* set by nnp_neighbors                              */
+} nnp_nlist;
+
+/* ---------------------------------------------------------------- model */
+
+/* Create a model on the current HIP device: validates the parameters, packs
+ * the weights (float32 and bfloat16 copies, padded for MFMA tiles) into
+ * device memory owned by the model.  *out receives the handle. */
+nnp_status nnp_model_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
+                            nnp_precision precision, nnp_model** out);
+void nnp_model_destroy(nnp_model* model);
+/* Switch the precision form used by later nnp_energy_forces calls. */
+nnp_status nnp_model_set_precision(nnp_model* model, nnp_precision precision);
+const char* nnp_status_str(nnp_status status);
+/* Number of AEV features (1008 for ANI-2x) and padded row stride used by
+ * nnp_aev (1024). */
+int32_t nnp_aev_dim(const nnp_model* model);
+
+/* Synchronise `stream`, read and clear the model's sticky device flags.
+ * Returns NNP_OK if none is set, else the status of the first flag; *flags
+ * (if non-NULL) receives the raw bit set. */
+nnp_status nnp_check(nnp_model* model, void* stream, uint32_t* flags);
+
+/* ---------------------------------------------------------------- neighbours */
+
+/* Device workspace (bytes) nnp_neighbors needs for this system. */
+size_t nnp_neighbors_workspace_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host,
+                                     float r_list);
+
+/* Build the neighbour list of Sec. 2.1 with an integer cell list (periodic
+ * box) or an all-pairs scan inside each structure (open boundaries).
+ *   pos      device float32 [n_atoms][3]
+ *   mol      device int32 [n_atoms] or NULL
+ *   box_host host float32 [3] orthorhombic box sides, or NULL (open)
+ *   r_list   list cutoff (model cutoff plus any skin)
+ * The pair predicate is exact: coordinates are widened to float64,
+ * d0 = x_j - x_i, n = -rint(d0 / L), d = d0 + n L, d2 = (dx^2 + dy^2) + dz^2
+ * with every operation rounded (no fused multiply-add), pair kept iff
+ * d2 < r_list^2 (r_list widened to float64).  The resulting pair set is
+ * therefore identical bit for bit on any conforming implementation.
+ * Synchronises `stream` once, to read the pair count: if it exceeds
+ * nl->capacity the call returns NNP_E_CAPACITY, *n_pairs_host receives the
+ * required size and the list contents are undefined (regrow and call again).
+ * Returns NNP_E_BOX if any box side is below 2 r_list, NNP_E_NONFINITE for
+ * non-finite coordinates, NNP_E_ARG for a bad `mol`. */
+nnp_status nnp_neighbors(nnp_model* model, int32_t n_atoms, const float* pos, const int32_t* mol,
+                         int32_t n_mol, const float* box_host, float r_list, nnp_nlist* nl,
+                         int64_t* n_pairs_host, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- energy and forces */
+
+/* Device workspace (bytes) nnp_energy_forces / nnp_aev need for n_atoms
+ * atoms and a neighbour list of pair_capacity entries. */
+size_t nnp_workspace_bytes(const nnp_model* model, int32_t n_atoms, int64_t pair_capacity);
+
+/* Energy and forces (Sec. 2.4): AEV of every atom from the list, species
+ * network per atom, float64 sum of atomic energies per structure (ascending
+ * atom order), forces F = -dE/dx through a hand-written adjoint of the
+ * network, the AEV and the pair geometry.
+ *   pos      device float32 [n_atoms][3]
+ *   species  device int32 [n_atoms]
+ *   mol      device int32 [n_atoms] or NULL; n_mol structures
+ *   box_host host float32 [3] or NULL; must be the box the list was built for
+ *   nl       list built by nnp_neighbors for these positions (a list built
+ *            with a larger r_list, e.g. with a skin, is valid while no pair
+ *            has moved inside the model cutoff unseen)
+ *   e_mol    device float64 [n_mol]          (written)
+ *   e_atom   device float32 [n_atoms] or NULL (written)
+ *   forces   device float32 [n_atoms][3] or NULL (written)
+ * Fully asynchronous on `stream`; never synchronises. */
+nnp_status nnp_energy_forces(nnp_model* model, int32_t n_atoms, const float* pos,
+                             const int32_t* species, const int32_t* mol, int32_t n_mol,
+                             const float* box_host, const nnp_nlist* nl, double* e_mol,
+                             float* e_atom, float* forces, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* The AEV alone (the radial and angular features of Sec. 2.2 / App. A):
+ * writes aev_out, device float32 [n_atoms][aev_stride] (aev_stride =
+ * nnp_aev_dim rounded up to 1024; padding columns are zero), rows in atom
+ * order.  Asynchronous. */
+nnp_status nnp_aev(nnp_model* model, int32_t n_atoms, const float* pos, const int32_t* species,
+                   const float* box_host, const nnp_nlist* nl, float* aev_out, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* The species networks alone on given features (Sec. 2.2): aev_in device
+ * float32 [n_atoms][aev_stride]; writes e_atom [n_atoms] (float32, self
+ * energy included) and, if non-NULL, daev_out [n_atoms][aev_stride] =
+ * dE_i/dAEV_i.  Asynchronous. */
+nnp_status nnp_mlp(nnp_model* model, int32_t n_atoms, const int32_t* species, const float* aev_in,
+                   float* e_atom, float* daev_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- molecular dynamics */
+
+/* Velocity Verlet (the NVE integrator of the paper's native engine, Sec. 5.4):
+ * first half: v += dt/2 * F * inv_mass * 9.648533212e-3; x += dt * v.  All
+ * device float32: pos/vel/forces [n_atoms][3], inv_mass [n_atoms] (1/amu).
+ * If ref_pos is non-NULL, the largest squared displacement from ref_pos is
+ * folded into *max_disp2 (device float32, caller clears it). */
+nnp_status nnp_md_kick_drift(int32_t n_atoms, float* pos, float* vel, const float* forces,
+                             const float* inv_mass, float dt, const float* ref_pos,
+                             float* max_disp2, void* stream);
+/* Second half: v += dt/2 * F * inv_mass * 9.648533212e-3. */
+nnp_status nnp_md_kick(int32_t n_atoms, float* vel, const float* forces, const float* inv_mass,
+                       float dt, void* stream);
+/* Wrap positions into [0, L) per dimension (periodic boxes, before a rebuild). */
+nnp_status nnp_md_wrap(int32_t n_atoms, float* pos, const float* box_host, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNP_H */

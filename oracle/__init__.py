@@ -16,8 +16,8 @@ float64 with numpy:
   (0.5 + 0.5 cos(theta - theta_n))^zeta (App. A, angular resources), as
   defined by the ANI reference the paper cites for its ANI_AEV module;
 * one species-specialised MLP per chemical species (Sec. 2.2, "Neural
-  Networks"), atomic energies summed per structure (Sec. 2.5, ANI flow);
-* forces as minus the gradient of the total energy (Sec. 2.5), evaluated by
+  Networks"), atomic energies summed per structure (Sec. 2.4, ANI flow);
+* forces as minus the gradient of the total energy (Sec. 2.4), evaluated by
   an explicit chain rule through MLP, AEV and pair geometry.
 
 Pins (in the tests marked "not gpu"): brute-force enumeration on tiny inputs,

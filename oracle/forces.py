@@ -1,4 +1,4 @@
-"""Oracle energies and forces (Sec. 2.5: per-structure sum of atomic
+"""Oracle energies and forces (Sec. 2.4: per-structure sum of atomic
 energies; forces are minus the gradient of the total energy).
 
 Chain rule, written out:

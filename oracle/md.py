@@ -1,4 +1,4 @@
-"""Oracle velocity-Verlet integrator (Sec. 4 of the MD part: the native
+"""Oracle velocity-Verlet integrator (Sec. 5.4, "Native MD engine": the native
 engine reverts to velocity Verlet for NVE dynamics).
 
     v(t + dt/2) = v(t) + dt/2 a(t)

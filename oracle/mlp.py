@@ -1,5 +1,5 @@
 """Oracle species-specialised MLP (Sec. 2.2, "Neural Networks": fully
-species-dependent network parameters; Sec. 2.5: ChemicalNet maps each atom's
+species-dependent network parameters; Sec. 2.4: ChemicalNet maps each atom's
 AEV to its atomic energy).
 
 For an atom of species s with feature vector a:

@@ -1,0 +1,385 @@
+// extern "C" entry points of libnnp (declared in include/nnp.h): argument
+// checks, workspace carving, weight packing and kernel sequencing.  Every
+// step of the computation runs in the HIP kernels of this library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "nnp_internal.hpp"
+
+using namespace nnp;
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+std::mutex g_stage_mutex;
+
+struct EfWs {
+    MlpWs mw;
+    int32_t* mstart;
+    int32_t* mend;
+    void* aev;          // [rows_max][stride] fp32-sized (aliased by g)
+    float* g;
+    float* h[kMaxLayers];
+    float* E_row;
+    float* Gx;
+    float* Gy;
+    float* Gz;
+    size_t end;
+};
+
+EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
+    EfWs W;
+    std::memset(&W, 0, sizeof(W));
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return base ? (void*)(base + r) : nullptr; };
+    const int nn = n > 0 ? n : 1;
+    const int nb = ceil_div(nn, 1024);
+    const int rows_max = round_up(nn, kTileM) + m->aev.ns * kTileM;
+    W.mw.rows_max = rows_max;
+    W.mw.bcount = (int32_t*)take(sizeof(int32_t) * nb * kMaxSpecies);
+    W.mw.boff = (int32_t*)take(sizeof(int32_t) * nb * kMaxSpecies);
+    W.mw.meta = (int32_t*)take(sizeof(int32_t) * 32);
+    W.mw.prow = (int32_t*)take(sizeof(int32_t) * nn);
+    W.mw.row_atom = (int32_t*)take(sizeof(int32_t) * rows_max);
+    W.mstart = (int32_t*)take(sizeof(int32_t) * (nn + 1));
+    W.mend = (int32_t*)take(sizeof(int32_t) * (nn + 1));
+    W.aev = take(sizeof(float) * (size_t)rows_max * m->aev.stride);
+    W.g = (float*)W.aev;
+    for (int l = 0; l + 1 < m->n_layers; ++l) W.h[l] = (float*)take(sizeof(float) * (size_t)rows_max * m->wpad[l + 1]);
+    W.E_row = (float*)take(sizeof(float) * rows_max);
+    const int64_t c = cap > 0 ? cap : 1;
+    W.Gx = (float*)take(sizeof(float) * c);
+    W.Gy = (float*)take(sizeof(float) * c);
+    W.Gz = (float*)take(sizeof(float) * c);
+    W.end = o;
+    return W;
+}
+
+BoxConst box_const(const float* box_host) {
+    BoxConst b;
+    b.periodic = box_host != nullptr;
+    for (int k = 0; k < 3; ++k) b.L[k] = box_host ? box_host[k] : 0.f;
+    return b;
+}
+
+SelfE self_e(const nnp_model* m) {
+    SelfE s;
+    for (int k = 0; k < kMaxSpecies; ++k) s.e[k] = m->self_energy[k];
+    return s;
+}
+
+nnp_status hip_status(hipError_t e) { return e == hipSuccess ? NNP_OK : NNP_E_HIP; }
+
+}  // namespace
+
+namespace nnp {
+
+nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev, int64_t* total_host) {
+    std::lock_guard<std::mutex> lock(g_stage_mutex);
+    char* st = (char*)m->host_stage;
+    if (hipMemcpyAsync(st, m->flags, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess) return NNP_E_HIP;
+    if (total_dev && hipMemcpyAsync(st + 8, total_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return NNP_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return NNP_E_HIP;
+    uint32_t fl;
+    std::memcpy(&fl, st, 4);
+    if (total_dev && total_host) std::memcpy(total_host, st + 8, 8);
+    if (fl) {
+        if (hipMemsetAsync(m->flags, 0, sizeof(unsigned), s) != hipSuccess) return NNP_E_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return NNP_E_HIP;
+    }
+    if (out) *out = fl;
+    return NNP_OK;
+}
+
+}  // namespace nnp
+
+extern "C" {
+
+const char* nnp_status_str(nnp_status s) {
+    switch (s) {
+        case NNP_OK: return "ok";
+        case NNP_E_ARG: return "invalid argument";
+        case NNP_E_CAPACITY: return "neighbour-list capacity too small";
+        case NNP_E_BOX: return "box side below twice the list cutoff";
+        case NNP_E_NONFINITE: return "non-finite coordinates";
+        case NNP_E_NOMEM: return "out of memory";
+        case NNP_E_BUSY: return "no free request slot";
+        case NNP_E_PENDING: return "request pending";
+        case NNP_E_HIP: return "HIP runtime error";
+        case NNP_E_ROW: return "neighbour row longer than supported";
+    }
+    return "unknown status";
+}
+
+nnp_status nnp_model_create(const nnp_aev_params* a, const nnp_mlp_params* p, nnp_precision precision,
+                            nnp_model** out) {
+    if (!a || !p || !out) return NNP_E_ARG;
+    *out = nullptr;
+    if (a->n_species < 1 || a->n_species > kMaxSpecies) return NNP_E_ARG;
+    if (a->n_shf_r != kNr || a->n_shf_a != kNa || a->n_shf_z != kNz) return NNP_E_ARG;
+    if (!a->shf_r || !a->shf_a || !a->shf_z) return NNP_E_ARG;
+    if (!(a->rc_r > 0.f) || !(a->rc_a > 0.f) || a->rc_a > a->rc_r) return NNP_E_ARG;
+    if (precision != NNP_FP32 && precision != NNP_BF16_MLP) return NNP_E_ARG;
+    const int ns = a->n_species;
+    const int L = p->n_layers;
+    if (L < 2 || L > kMaxLayers || !p->widths || !p->W || !p->b) return NNP_E_ARG;
+    const int dim = ns * kNr + ns * (ns + 1) / 2 * kNa * kNz;
+    if (p->widths[0] != dim || p->widths[L] != 1) return NNP_E_ARG;
+    for (int l = 1; l < L; ++l)
+        if (p->widths[l] < 1 || p->widths[l] > 4096) return NNP_E_ARG;
+    if (!(p->celu_alpha > 0.f)) return NNP_E_ARG;
+
+    nnp_model* m = new nnp_model;
+    std::memset(m, 0, sizeof(*m));
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return NNP_E_HIP;
+    }
+    m->precision = precision;
+    AevConst& P = m->aev;
+    P.ns = ns;
+    P.radial_dim = ns * kNr;
+    P.dim = dim;
+    P.stride = round_up(dim, 64);
+    P.rc_r = a->rc_r;
+    P.eta_r = a->eta_r;
+    P.rc_a = a->rc_a;
+    P.eta_a = a->eta_a;
+    P.zeta = a->zeta;
+    P.pr = a->radial_prefactor;
+    P.cs = a->cos_scale;
+    P.pi_rc_r = (float)(M_PI / (double)a->rc_r);
+    P.pi_rc_a = (float)(M_PI / (double)a->rc_a);
+    for (int k = 0; k < kNr; ++k) P.shf_r[k] = a->shf_r[k];
+    for (int k = 0; k < kNa; ++k) P.shf_a[k] = a->shf_a[k];
+    for (int k = 0; k < kNz; ++k) {
+        P.cos_z[k] = (float)std::cos((double)a->shf_z[k]);
+        P.sin_z[k] = (float)std::sin((double)a->shf_z[k]);
+    }
+    m->n_layers = L;
+    for (int l = 0; l <= L; ++l) {
+        m->widths[l] = p->widths[l];
+        m->wpad[l] = l == L ? 1 : round_up(p->widths[l], 64);
+    }
+    m->wpad[0] = P.stride;
+    m->celu_alpha = p->celu_alpha;
+    for (int s = 0; s < kMaxSpecies; ++s) m->self_energy[s] = (p->self_energy && s < ns) ? p->self_energy[s] : 0.0;
+
+    // pack weights: per species, per hidden layer: W [Np][Kp], WT [Kp][Np] (fp32 + bf16), bias [Np];
+    // head: w [Kp_last]
+    std::vector<size_t> offW(ns * L), offWT(ns * L), offWb(ns * L), offWTb(ns * L), offB(ns * L), offH(ns);
+    size_t o = 0;
+    for (int s = 0; s < ns; ++s) {
+        for (int l = 0; l + 1 < L; ++l) {
+            const size_t nk = (size_t)m->wpad[l] * m->wpad[l + 1];
+            offW[s * L + l] = o; o = align256(o + 4 * nk);
+            offWT[s * L + l] = o; o = align256(o + 4 * nk);
+            offWb[s * L + l] = o; o = align256(o + 2 * nk);
+            offWTb[s * L + l] = o; o = align256(o + 2 * nk);
+            offB[s * L + l] = o; o = align256(o + 4 * (size_t)m->wpad[l + 1]);
+        }
+        offH[s] = o; o = align256(o + 4 * (size_t)m->wpad[L - 1]);
+    }
+    std::vector<char> host(o, 0);
+    for (int s = 0; s < ns; ++s) {
+        for (int l = 0; l + 1 < L; ++l) {
+            const int K = m->widths[l], N = m->widths[l + 1];
+            const int Kp = m->wpad[l], Np = m->wpad[l + 1];
+            const float* Wsrc = p->W[s * L + l];
+            const float* bsrc = p->b[s * L + l];
+            if (!Wsrc || !bsrc) { delete m; return NNP_E_ARG; }
+            float* W = (float*)(host.data() + offW[s * L + l]);
+            float* WT = (float*)(host.data() + offWT[s * L + l]);
+            uint16_t* Wb = (uint16_t*)(host.data() + offWb[s * L + l]);
+            uint16_t* WTb = (uint16_t*)(host.data() + offWTb[s * L + l]);
+            float* B = (float*)(host.data() + offB[s * L + l]);
+            for (int nI = 0; nI < N; ++nI) {
+                for (int k = 0; k < K; ++k) {
+                    const float v = Wsrc[(size_t)nI * K + k];
+                    W[(size_t)nI * Kp + k] = v;
+                    WT[(size_t)k * Np + nI] = v;
+                    Wb[(size_t)nI * Kp + k] = host_bf16(v);
+                    WTb[(size_t)k * Np + nI] = host_bf16(v);
+                }
+                B[nI] = bsrc[nI];
+            }
+        }
+        const float* wh = p->W[s * L + L - 1];
+        const float* bh = p->b[s * L + L - 1];
+        if (!wh || !bh) { delete m; return NNP_E_ARG; }
+        float* H = (float*)(host.data() + offH[s]);
+        for (int k = 0; k < m->widths[L - 1]; ++k) H[k] = wh[k];
+        m->ptrs.head_b[s] = bh[0];
+    }
+    if (hipMalloc(&m->dev_weights, o) != hipSuccess) { delete m; return NNP_E_NOMEM; }
+    m->dev_weights_bytes = o;
+    if (hipMemcpy(m->dev_weights, host.data(), o, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(m->dev_weights);
+        delete m;
+        return NNP_E_HIP;
+    }
+    char* d = (char*)m->dev_weights;
+    for (int s = 0; s < ns; ++s) {
+        for (int l = 0; l + 1 < L; ++l) {
+            m->ptrs.W[s][l] = (const float*)(d + offW[s * L + l]);
+            m->ptrs.WT[s][l] = (const float*)(d + offWT[s * L + l]);
+            m->ptrs.Wb[s][l] = (const uint16_t*)(d + offWb[s * L + l]);
+            m->ptrs.WTb[s][l] = (const uint16_t*)(d + offWTb[s * L + l]);
+            m->ptrs.b[s][l] = (const float*)(d + offB[s * L + l]);
+        }
+        m->ptrs.head_w[s] = (const float*)(d + offH[s]);
+    }
+    if (hipMalloc(&m->flags, 256) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
+    if (hipMemset(m->flags, 0, 256) != hipSuccess) { nnp_model_destroy(m); return NNP_E_HIP; }
+    if (hipHostMalloc(&m->host_stage, 256, 0) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
+    *out = m;
+    return NNP_OK;
+}
+
+void nnp_model_destroy(nnp_model* m) {
+    if (!m) return;
+    if (m->dev_weights) (void)hipFree(m->dev_weights);
+    if (m->flags) (void)hipFree(m->flags);
+    if (m->host_stage) (void)hipHostFree(m->host_stage);
+    delete m;
+}
+
+nnp_status nnp_model_set_precision(nnp_model* m, nnp_precision p) {
+    if (!m || (p != NNP_FP32 && p != NNP_BF16_MLP)) return NNP_E_ARG;
+    m->precision = p;
+    return NNP_OK;
+}
+
+int32_t nnp_aev_dim(const nnp_model* m) { return m ? m->aev.dim : 0; }
+
+nnp_status nnp_check(nnp_model* m, void* stream, uint32_t* flags) {
+    if (!m) return NNP_E_ARG;
+    uint32_t fl = 0;
+    nnp_status st = read_and_clear_flags(m, (hipStream_t)stream, &fl, nullptr, nullptr);
+    if (st != NNP_OK) return st;
+    if (flags) *flags = fl;
+    if (!fl) return NNP_OK;
+    if (fl & NNP_FLAG_NONFINITE) return NNP_E_NONFINITE;
+    if (fl & NNP_FLAG_ROW) return NNP_E_ROW;
+    return NNP_E_ARG;
+}
+
+size_t nnp_neighbors_workspace_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list) {
+    if (n_atoms < 0) return 0;
+    return neighbors_ws_bytes(n_atoms, n_mol, box_host, r_list);
+}
+
+nnp_status nnp_neighbors(nnp_model* m, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
+                         const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host, void* ws,
+                         size_t ws_bytes, void* stream) {
+    if (!m || !nl || n < 0 || (n > 0 && !pos) || !nl->row_ptr) return NNP_E_ARG;
+    if (!(r_list > 0.f) || !std::isfinite(r_list)) return NNP_E_ARG;
+    if (mol && n_mol < 1) return NNP_E_ARG;
+    if (nl->capacity > 0 && (!nl->col || !nl->shift || !nl->rev)) return NNP_E_ARG;
+    return build_neighbors(m, n, pos, mol, mol ? n_mol : 1, box_host, r_list, nl, n_pairs_host, ws, ws_bytes,
+                           (hipStream_t)stream);
+}
+
+size_t nnp_workspace_bytes(const nnp_model* m, int32_t n_atoms, int64_t pair_capacity) {
+    if (!m || n_atoms < 0) return 0;
+    return ef_layout(m, n_atoms, pair_capacity, nullptr).end;
+}
+
+nnp_status nnp_energy_forces(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
+                             int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,
+                             float* forces, void* ws, size_t ws_bytes, void* stream) {
+    if (!m || !nl || n < 0) return NNP_E_ARG;
+    if (n > 0 && (!pos || !species)) return NNP_E_ARG;
+    if (n_mol < 0 || (n > 0 && n_mol < 1) || n_mol > (n > 0 ? n : 1)) return NNP_E_ARG;
+    if (n_mol > 0 && !e_mol) return NNP_E_ARG;
+    if (nl->n_atoms != n || nl->n_pairs > nl->capacity) return NNP_E_ARG;
+    if (box_host && (nl->r_list * 2.f > box_host[0] || nl->r_list * 2.f > box_host[1] || nl->r_list * 2.f > box_host[2]))
+        return NNP_E_BOX;
+    if (nl->r_list < m->aev.rc_r) return NNP_E_ARG;
+    const EfWs need = ef_layout(m, n, nl->capacity, nullptr);
+    if (!ws || ws_bytes < need.end) return NNP_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const EfWs W = ef_layout(m, n, nl->capacity, (char*)ws);
+    const BoxConst bx = box_const(box_host);
+    const bool bf = m->precision == NNP_BF16_MLP;
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = launch_species_group(m, n, species, W.mw, s);
+        if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, bf, s);
+        if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.aev, bf, m->flags, s);
+        if (e == hipSuccess)
+            e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, s);
+    }
+    if (e == hipSuccess)
+        e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_row, e_mol, e_atom, m->flags,
+                          s);
+    if (e == hipSuccess && forces && n > 0) {
+        e = launch_aev_bwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, m->flags, s);
+        if (e == hipSuccess) e = launch_force_gather(n, nl, W.Gx, W.Gy, W.Gz, forces, s);
+    }
+    return hip_status(e);
+}
+
+nnp_status nnp_aev(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const float* box_host,
+                   const nnp_nlist* nl, float* aev_out, void* ws, size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!m || !nl || n < 0 || (n > 0 && (!pos || !species || !aev_out))) return NNP_E_ARG;
+    if (nl->n_atoms != n) return NNP_E_ARG;
+    return hip_status(launch_aev_fwd(m->aev, n, pos, species, box_const(box_host), nl, nullptr, aev_out, false,
+                                     m->flags, (hipStream_t)stream));
+}
+
+nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float* aev_in, float* e_atom,
+                   float* daev_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!m || n < 0 || (n > 0 && (!species || !aev_in || !e_atom))) return NNP_E_ARG;
+    const EfWs need = ef_layout(m, n, 0, nullptr);
+    if (!ws || ws_bytes < need.end) return NNP_E_ARG;
+    if (n == 0) return NNP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const EfWs W = ef_layout(m, n, 0, (char*)ws);
+    hipError_t e = launch_species_group(m, n, species, W.mw, s);
+    if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, false, s);
+    if (e == hipSuccess) e = launch_permute_rows(true, W.mw.prow, n, m->aev.stride, aev_in, (float*)W.aev, s);
+    if (e == hipSuccess) e = launch_mlp(m, W.mw, W.aev, false, W.h, daev_out ? W.g : nullptr, W.E_row, s);
+    if (e == hipSuccess) e = launch_gather_e(W.mw.prow, n, species, self_e(m), W.E_row, e_atom, s);
+    if (e == hipSuccess && daev_out) e = launch_permute_rows(false, W.mw.prow, n, m->aev.stride, W.g, daev_out, s);
+    return hip_status(e);
+}
+
+nnp_status nnp_md_kick_drift(int32_t n, float* pos, float* vel, const float* forces, const float* inv_mass, float dt,
+                             const float* ref_pos, float* max_disp2, void* stream) {
+    if (n < 0 || (n > 0 && (!pos || !vel || !forces || !inv_mass)) || (ref_pos && !max_disp2)) return NNP_E_ARG;
+    return hip_status(launch_kick_drift(n, pos, vel, forces, inv_mass, dt, ref_pos, max_disp2, (hipStream_t)stream));
+}
+
+nnp_status nnp_md_kick(int32_t n, float* vel, const float* forces, const float* inv_mass, float dt, void* stream) {
+    if (n < 0 || (n > 0 && (!vel || !forces || !inv_mass))) return NNP_E_ARG;
+    return hip_status(launch_kick(n, vel, forces, inv_mass, dt, (hipStream_t)stream));
+}
+
+nnp_status nnp_md_wrap(int32_t n, float* pos, const float* box_host, void* stream) {
+    if (n < 0 || (n > 0 && !pos) || !box_host) return NNP_E_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!(box_host[k] > 0.f)) return NNP_E_ARG;
+    return hip_status(launch_wrap(n, pos, box_host, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Forces from edge gradients, and the velocity-Verlet kernels.
+//
+// With G_ij = dE_i/dv_ij and v_ij = x_j + n L - x_i, the force on atom a is
+//   F_a = -dE/dx_a = sum_{j in N(a)} (G_aj - G_ja),
+// where G_ja sits at rev[p] of the pair a -> j (the list is symmetric).  Each
+// atom's sum runs over its own row in a fixed order (16 lanes per atom, then
+// a fixed butterfly), so no atomics are involved (Sec. 2.4: forces as the
+// gradient of the total energy).
+#include "nnp_internal.hpp"
+
+namespace nnp {
+namespace {
+
+constexpr int kLanesPerAtom = 16;
+
+__global__ __launch_bounds__(256) void k_force_gather(int n, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ rev, const float* __restrict__ Gx,
+                                                     const float* __restrict__ Gy, const float* __restrict__ Gz,
+                                                     float* __restrict__ F) {
+    const int a = (blockIdx.x * blockDim.x + threadIdx.x) / kLanesPerAtom;
+    const int sub = threadIdx.x % kLanesPerAtom;
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    if (a < n) {
+        const int b = row_ptr[a], e = row_ptr[a + 1];
+        for (int p = b + sub; p < e; p += kLanesPerAtom) {
+            const int q = rev[p];
+            fx += Gx[p] - Gx[q];
+            fy += Gy[p] - Gy[q];
+            fz += Gz[p] - Gz[q];
+        }
+    }
+#pragma unroll
+    for (int m = kLanesPerAtom / 2; m >= 1; m >>= 1) {
+        fx += shfl_xor(fx, m);
+        fy += shfl_xor(fy, m);
+        fz += shfl_xor(fz, m);
+    }
+    if (a < n && sub == 0) {
+        F[3 * a] = fx;
+        F[3 * a + 1] = fy;
+        F[3 * a + 2] = fz;
+    }
+}
+
+__global__ void k_kick_drift(int n, float* pos, float* vel, const float* F, const float* inv_mass, float dt,
+                             const float* ref, float* max_d2) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    float d2 = 0.f;
+    if (a < n) {
+        const float c = 0.5f * dt * kAccUnit * inv_mass[a];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float v = vel[3 * a + k] + c * F[3 * a + k];
+            vel[3 * a + k] = v;
+            const float x = pos[3 * a + k] + dt * v;
+            pos[3 * a + k] = x;
+            if (ref) {
+                const float d = x - ref[3 * a + k];
+                d2 += d * d;
+            }
+        }
+    }
+    if (ref) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
+        if (lane_id() == 0 && d2 > 0.f) atomicMax((unsigned*)max_d2, __float_as_uint(d2));
+    }
+}
+
+__global__ void k_kick(int n, float* vel, const float* F, const float* inv_mass, float dt) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const float c = 0.5f * dt * kAccUnit * inv_mass[a];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) vel[3 * a + k] += c * F[3 * a + k];
+}
+
+__global__ void k_wrap(int n, float* pos, float Lx, float Ly, float Lz) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const float L[3] = {Lx, Ly, Lz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float x = pos[3 * a + k];
+        x -= L[k] * floorf(x / L[k]);
+        if (x >= L[k]) x -= L[k];
+        if (x < 0.f) x = 0.f;
+        pos[3 * a + k] = x;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_force_gather(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_force_gather<<<ceil_div((long)n * kLanesPerAtom, 256), 256, 0, s>>>(n, nl->row_ptr, nl->rev, Gx, Gy, Gz, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(int n, float* pos, float* vel, const float* F, const float* inv_mass, float dt,
+                             const float* ref, float* max_d2, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_kick_drift<<<ceil_div(n, 256), 256, 0, s>>>(n, pos, vel, F, inv_mass, dt, ref, max_d2);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick(int n, float* vel, const float* F, const float* inv_mass, float dt, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_kick<<<ceil_div(n, 256), 256, 0, s>>>(n, vel, F, inv_mass, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_wrap(int n, float* pos, const float* L, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_wrap<<<ceil_div(n, 256), 256, 0, s>>>(n, pos, L[0], L[1], L[2]);
+    return hipGetLastError();
+}
+
+}  // namespace nnp

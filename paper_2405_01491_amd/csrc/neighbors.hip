@@ -1,0 +1,417 @@
+// Neighbour list (Sec. 2.1, "Preprocessing Modules"): directed pairs of atoms
+// of the same structure closer than the list cutoff, minimum image in an
+// orthorhombic box, rows sorted by neighbour index, plus the reverse index.
+//
+// Periodic systems use an integer cell list (cells at least r_list wide, a
+// 27-cell stencil, or every cell along a dimension with fewer than 3 cells);
+// open systems scan all atoms of the same structure.  Candidates of one row
+// are streamed across the 64 lanes of a wave and compacted with ballots; the
+// row is rank-sorted in LDS before it is written, so the output does not
+// depend on the (atomic) order in which atoms were binned.
+//
+// The pair predicate is evaluated in float64 with every operation rounded
+// (floating-point contraction is disabled in that function), so the pair set
+// is reproducible bit for bit by any IEEE implementation.
+#include "nnp_internal.hpp"
+
+namespace nnp {
+namespace {
+
+constexpr int kRowsPerBlock = 4;              // one wave per row
+constexpr int kRowLds = 1024;                 // longest row the builder handles
+constexpr int kMaxCellsPerDim = 128;
+
+struct Grid {
+    int periodic;
+    int nc[3];          // cells per dimension
+    int ns[3];          // stencil width per dimension (min(3, nc))
+    double L[3];        // box sides (float32 widened)
+    double inv_cs[3];   // nc / L
+};
+
+struct PairOut {
+    bool keep;
+    int packed_shift;
+};
+
+// Exact predicate.  No contraction: each +, -, *, / is rounded on its own.
+__device__ __forceinline__ PairOut pair_predicate(float3 xi, float3 xj, const Grid g, double r2) {
+#pragma clang fp contract(off)
+    double d[3], n[3];
+    const double a[3] = {(double)xi.x, (double)xi.y, (double)xi.z};
+    const double b[3] = {(double)xj.x, (double)xj.y, (double)xj.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double d0 = b[k] - a[k];
+        if (g.periodic) {
+            n[k] = -rint(d0 / g.L[k]);
+            double nl = n[k] * g.L[k];
+            d[k] = d0 + nl;
+        } else {
+            n[k] = 0.0;
+            d[k] = d0;
+        }
+    }
+    double sx = d[0] * d[0];
+    double sy = d[1] * d[1];
+    double sz = d[2] * d[2];
+    double d2 = (sx + sy) + sz;
+    PairOut o;
+    o.keep = d2 < r2;
+    int ix = (int)n[0], iy = (int)n[1], iz = (int)n[2];
+    o.packed_shift = (ix & 0xff) | ((iy & 0xff) << 8) | ((iz & 0xff) << 16);
+    if (o.keep && (n[0] < -127.0 || n[0] > 127.0 || n[1] < -127.0 || n[1] > 127.0 || n[2] < -127.0 ||
+                   n[2] > 127.0))
+        o.packed_shift = -1;   // caller flags it
+    return o;
+}
+
+__device__ __forceinline__ float3 load_pos(const float* pos, int i) {
+    return make_float3(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+}
+
+__device__ __forceinline__ bool finite3(float3 p) {
+    return isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
+}
+
+__device__ __forceinline__ int cell_coord(float x, double L, double inv_cs, int nc) {
+    double xd = (double)x;
+    double w = xd - L * floor(xd / L);
+    int c = (int)(w * inv_cs);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+// structure ranges for contiguous molecules; validates mol
+__global__ void k_mol_ranges(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end,
+                             unsigned* flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = mol[i];
+    if (m < 0 || m >= n_mol) {
+        set_flag(flags, NNP_FLAG_MOL);
+        return;
+    }
+    const int prev = i > 0 ? mol[i - 1] : -1;
+    const int next = i + 1 < n ? mol[i + 1] : -1;
+    if (i > 0 && prev > m) set_flag(flags, NNP_FLAG_MOL);
+    if (prev != m) start[m] = i;
+    if (next != m) end[m] = i + 1;
+}
+
+__global__ void k_bin(const float* pos, int n, const Grid g, int32_t* cell_of, int32_t* cell_slot,
+                      int32_t* cell_count, unsigned* flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float3 p = load_pos(pos, i);
+    if (!finite3(p)) {
+        set_flag(flags, NNP_FLAG_NONFINITE);
+        cell_of[i] = -1;
+        return;
+    }
+    const int cx = cell_coord(p.x, g.L[0], g.inv_cs[0], g.nc[0]);
+    const int cy = cell_coord(p.y, g.L[1], g.inv_cs[1], g.nc[1]);
+    const int cz = cell_coord(p.z, g.L[2], g.inv_cs[2], g.nc[2]);
+    const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+    cell_of[i] = c;
+    cell_slot[i] = atomicAdd(&cell_count[c], 1);
+}
+
+__global__ void k_scatter(int n, const int32_t* cell_of, const int32_t* cell_slot, const int32_t* cell_start,
+                          int32_t* cell_atoms) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell_of[i];
+    if (c >= 0) cell_atoms[cell_start[c] + cell_slot[i]] = i;
+}
+
+__global__ void k_finite(const float* pos, int n, unsigned* flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!finite3(load_pos(pos, i))) set_flag(flags, NNP_FLAG_NONFINITE);
+}
+
+// One wave per row.  Mode 0: count into row_count.  Mode 1: write the
+// sorted row at row_ptr[i].
+template <int kMode>
+__global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
+    const float* pos, int n, const int32_t* mol, int n_mol, const Grid g, double r2, const int32_t* cell_of,
+    const int32_t* cell_start, const int32_t* cell_atoms, const int32_t* mol_start, const int32_t* mol_end,
+    int32_t* row_count, const int32_t* row_ptr, int32_t* col, int8_t* shift, unsigned* flags) {
+    __shared__ int s_off[kRowsPerBlock][28];
+    __shared__ int s_beg[kRowsPerBlock][28];
+    __shared__ int s_col[kMode ? kRowsPerBlock : 1][kMode ? kRowLds : 1];
+    __shared__ int s_sh[kMode ? kRowsPerBlock : 1][kMode ? kRowLds : 1];
+    const int w = threadIdx.x / kWave;
+    const int l = lane_id();
+    const int i = blockIdx.x * kRowsPerBlock + w;
+    if (i >= n) return;
+    const float3 xi = load_pos(pos, i);
+    const int mi = mol ? mol[i] : 0;
+    int n_src = 0;
+    if (g.periodic) {
+        const int ci = cell_of[i];
+        if (ci < 0) {
+            if (kMode == 0 && l == 0) row_count[i] = 0;
+            return;
+        }
+        const int cz = ci % g.nc[2];
+        const int cy = (ci / g.nc[2]) % g.nc[1];
+        const int cx = ci / (g.nc[2] * g.nc[1]);
+        n_src = g.ns[0] * g.ns[1] * g.ns[2];
+        int beg = 0, cnt = 0;
+        if (l < n_src) {
+            const int a = l / (g.ns[1] * g.ns[2]);
+            const int b = (l / g.ns[2]) % g.ns[1];
+            const int c = l % g.ns[2];
+            // stencil: offsets -1..1 when nc >= 3, else every cell of the dimension
+            const int ox = g.nc[0] >= 3 ? (cx + a - 1 + g.nc[0]) % g.nc[0] : a;
+            const int oy = g.nc[1] >= 3 ? (cy + b - 1 + g.nc[1]) % g.nc[1] : b;
+            const int oz = g.nc[2] >= 3 ? (cz + c - 1 + g.nc[2]) % g.nc[2] : c;
+            const int cell = (ox * g.nc[1] + oy) * g.nc[2] + oz;
+            beg = cell_start[cell];
+            cnt = cell_start[cell + 1] - beg;
+        }
+        // inclusive scan of counts over the first n_src lanes
+        int inc = cnt;
+        for (int d = 1; d < 32; d <<= 1) {
+            int u = __shfl_up(inc, d, kWave);
+            if (l >= d) inc += u;
+        }
+        if (l < n_src) {
+            s_off[w][l] = inc - cnt;
+            s_beg[w][l] = beg;
+        }
+        if (l == n_src - 1) s_off[w][n_src] = inc;
+    } else {
+        n_src = 1;
+        if (l == 0) {
+            int b = 0, e = n;
+            if (mol) {
+                if (mi >= 0 && mi < n_mol) {
+                    b = mol_start[mi];
+                    e = mol_end[mi];
+                } else {
+                    b = e = 0;
+                }
+            }
+            s_off[w][0] = 0;
+            s_beg[w][0] = b;
+            s_off[w][1] = e > b ? e - b : 0;
+        }
+    }
+    wave_sync();
+    const int total = s_off[w][n_src];
+    int count = 0;
+    bool overflow = false;
+    for (int base = 0; base < total; base += kWave) {
+        const int t = base + l;
+        bool keep = false;
+        int j = -1, sh = 0;
+        if (t < total) {
+            // last source k with s_off[k] <= t (s_off[n_src] = total > t)
+            int lo = 0, hi = n_src;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[w][mid] <= t) lo = mid; else hi = mid;
+            }
+            const int k = lo;
+            const int idx = s_beg[w][k] + (t - s_off[w][k]);
+            j = g.periodic ? cell_atoms[idx] : idx;
+            if (j != i && (!mol || mol[j] == mi)) {
+                const float3 xj = load_pos(pos, j);
+                PairOut o = pair_predicate(xi, xj, g, r2);
+                keep = o.keep;
+                sh = o.packed_shift;
+                if (keep && sh == -1) {
+                    set_flag(flags, NNP_FLAG_SHIFT);
+                    sh = 0;
+                }
+            }
+        }
+        const unsigned long long m = ballot(keep);
+        if (kMode == 1 && keep) {
+            const int pos_in_row = count + rank_below(m);
+            if (pos_in_row < kRowLds) {
+                s_col[w][pos_in_row] = j;
+                s_sh[w][pos_in_row] = sh;
+            } else {
+                overflow = true;
+            }
+        }
+        count += __popcll(m);
+    }
+    if (kMode == 0) {
+        if (l == 0) row_count[i] = count;
+        if (count > kRowLds && l == 0) set_flag(flags, NNP_FLAG_ROW);
+        return;
+    }
+    if (overflow || count > kRowLds) return;   // reported in count mode
+    // rank sort by neighbour index (indices in a row are distinct)
+    const int base_out = row_ptr[i];
+    for (int e = l; e < count; e += kWave) {
+        const int je = s_col[w][e];
+        int rank = 0;
+        for (int f = 0; f < count; ++f) rank += s_col[w][f] < je;
+        col[base_out + rank] = je;
+        const int sh = s_sh[w][e];
+        shift[3 * (base_out + rank) + 0] = (int8_t)(sh & 0xff);
+        shift[3 * (base_out + rank) + 1] = (int8_t)((sh >> 8) & 0xff);
+        shift[3 * (base_out + rank) + 2] = (int8_t)((sh >> 16) & 0xff);
+    }
+}
+
+// reverse index: rev[p] = slot of (j -> i) in row j
+__global__ void k_rev(int n, const int32_t* row_ptr, const int32_t* col, int32_t* rev) {
+    const int w = threadIdx.x / kWave;
+    const int l = lane_id();
+    const int i = blockIdx.x * (blockDim.x / kWave) + w;
+    if (i >= n) return;
+    const int b = row_ptr[i], e = row_ptr[i + 1];
+    for (int p = b + l; p < e; p += kWave) {
+        const int j = col[p];
+        int lo = row_ptr[j], hi = row_ptr[j + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (col[mid] < i) lo = mid + 1; else hi = mid;
+        }
+        rev[p] = (lo < row_ptr[j + 1] && col[lo] == i) ? lo : p;
+    }
+}
+
+struct WsLayout {
+    size_t cell_count, cell_start, cell_of, cell_slot, cell_atoms, row_count, mol_start, mol_end,
+        scan_tmp, totals, end;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(int n, int n_mol, long n_cells) {
+    WsLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    const int nn = n > 0 ? n : 1;
+    L.cell_count = take(sizeof(int32_t) * (n_cells + 1));
+    L.cell_start = take(sizeof(int32_t) * (n_cells + 1));
+    L.cell_of = take(sizeof(int32_t) * nn);
+    L.cell_slot = take(sizeof(int32_t) * nn);
+    L.cell_atoms = take(sizeof(int32_t) * nn);
+    L.row_count = take(sizeof(int32_t) * nn);
+    L.mol_start = take(sizeof(int32_t) * (n_mol > 0 ? n_mol : 1));
+    L.mol_end = take(sizeof(int32_t) * (n_mol > 0 ? n_mol : 1));
+    const long sn = n_cells > nn ? n_cells : nn;
+    L.scan_tmp = take(sizeof(int64_t) * scan_tmp_elems((int)sn));
+    L.totals = take(sizeof(int64_t) * 4);
+    L.end = o;
+    return L;
+}
+
+nnp_status make_grid(const float* box_host, float r_list, Grid* g) {
+    g->periodic = box_host != nullptr;
+    for (int k = 0; k < 3; ++k) {
+        g->nc[k] = 1;
+        g->ns[k] = 1;
+        g->L[k] = 1.0;
+        g->inv_cs[k] = 0.0;
+    }
+    if (!box_host) return NNP_OK;
+    const double r = (double)r_list;
+    for (int k = 0; k < 3; ++k) {
+        const double L = (double)box_host[k];
+        if (!(L > 0.0) || !std::isfinite(L)) return NNP_E_ARG;
+        if (L < 2.0 * r) return NNP_E_BOX;
+        long nc = (long)std::floor(L / (r * (1.0 + 1e-9)));
+        if (nc < 1) nc = 1;
+        if (nc > kMaxCellsPerDim) nc = kMaxCellsPerDim;
+        g->nc[k] = (int)nc;
+        g->ns[k] = nc >= 3 ? 3 : (int)nc;
+        g->L[k] = L;
+        g->inv_cs[k] = (double)nc / L;
+    }
+    return NNP_OK;
+}
+
+}  // namespace
+
+size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list) {
+    Grid g;
+    if (make_grid(box_host, r_list, &g) != NNP_OK) return 0;
+    const long n_cells = g.periodic ? (long)g.nc[0] * g.nc[1] * g.nc[2] : 1;
+    return ws_layout(n_atoms, n_mol, n_cells).end;
+}
+
+nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev,
+                                int64_t* total_host);
+
+nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
+                           const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host,
+                           void* ws, size_t ws_bytes, hipStream_t s) {
+    Grid g;
+    nnp_status st = make_grid(box_host, r_list, &g);
+    if (st != NNP_OK) return st;
+    const long n_cells = g.periodic ? (long)g.nc[0] * g.nc[1] * g.nc[2] : 1;
+    const WsLayout L = ws_layout(n, n_mol, n_cells);
+    if (!ws || ws_bytes < L.end) return NNP_E_ARG;
+    char* base = (char*)ws;
+    int32_t* cell_count = (int32_t*)(base + L.cell_count);
+    int32_t* cell_start = (int32_t*)(base + L.cell_start);
+    int32_t* cell_of = (int32_t*)(base + L.cell_of);
+    int32_t* cell_slot = (int32_t*)(base + L.cell_slot);
+    int32_t* cell_atoms = (int32_t*)(base + L.cell_atoms);
+    int32_t* row_count = (int32_t*)(base + L.row_count);
+    int32_t* mol_start = (int32_t*)(base + L.mol_start);
+    int32_t* mol_end = (int32_t*)(base + L.mol_end);
+    int64_t* scan_tmp = (int64_t*)(base + L.scan_tmp);
+    int64_t* totals = (int64_t*)(base + L.totals);
+    unsigned* flags = model->flags;
+    const double rl = (double)r_list;
+    const double r2 = rl * rl;
+    const int tb = 256;
+    const int nb = ceil_div(n > 0 ? n : 1, tb);
+
+    hipError_t he = hipSuccess;
+    auto chk = [&](hipError_t x) { if (he == hipSuccess) he = x; };
+    if (n > 0) {
+        if (mol) {
+            chk(hipMemsetAsync(mol_start, 0, sizeof(int32_t) * n_mol, s));
+            chk(hipMemsetAsync(mol_end, 0, sizeof(int32_t) * n_mol, s));
+            k_mol_ranges<<<nb, tb, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags);
+        }
+        if (g.periodic) {
+            chk(hipMemsetAsync(cell_count, 0, sizeof(int32_t) * (n_cells + 1), s));
+            k_bin<<<nb, tb, 0, s>>>(pos, n, g, cell_of, cell_slot, cell_count, flags);
+            chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s));
+            k_scatter<<<nb, tb, 0, s>>>(n, cell_of, cell_slot, cell_start, cell_atoms);
+        } else {
+            k_finite<<<nb, tb, 0, s>>>(pos, n, flags);
+        }
+        k_rows<0><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
+            pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count, nullptr, nullptr,
+            nullptr, flags);
+    }
+    chk(launch_exclusive_scan_i32(row_count, nl->row_ptr, totals, n, scan_tmp, s));
+    chk(hipGetLastError());
+    if (he != hipSuccess) return NNP_E_HIP;
+    int64_t total = 0;
+    uint32_t fl = 0;
+    st = read_and_clear_flags(model, s, &fl, totals, &total);
+    if (st != NNP_OK) return st;
+    if (n_pairs_host) *n_pairs_host = total;
+    nl->n_atoms = n;
+    nl->r_list = r_list;
+    nl->n_pairs = total;
+    if (fl) {
+        if (fl & NNP_FLAG_NONFINITE) return NNP_E_NONFINITE;
+        if (fl & NNP_FLAG_ROW) return NNP_E_ROW;
+        return NNP_E_ARG;
+    }
+    if (total > nl->capacity || total > 0x7fffffffLL) return NNP_E_CAPACITY;
+    if (n > 0 && total > 0) {
+        k_rows<1><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
+            pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, nullptr, nl->row_ptr,
+            nl->col, nl->shift, flags);
+        k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev);
+    }
+    return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
+}
+
+}  // namespace nnp

@@ -1,0 +1,169 @@
+// Internal declarations shared by the HIP translation units of libnnp.
+// gfx950 (CDNA4) only: wave64, MFMA, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nnp.h"
+
+namespace nnp {
+
+constexpr int kWave = 64;
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxLayers = 8;
+constexpr int kTileM = 64;          // rows per MLP tile (atoms of one species)
+constexpr int kNr = 16;             // radial shells the AEV kernels are written for
+constexpr int kNa = 4;              // angular radial shells
+constexpr int kNz = 8;              // angle sections
+constexpr float kAccUnit = 9.648533212e-3f;   // eV / (A amu) -> A / fs^2
+
+// AEV hyper-parameters as kernels see them (passed by value).
+struct AevConst {
+    int ns;              // species
+    int radial_dim;      // ns * 16
+    int dim;             // radial_dim + ns(ns+1)/2 * 32
+    int stride;          // dim rounded up to a multiple of 64
+    float rc_r, eta_r, rc_a, eta_a, zeta, pr, cs;
+    float pi_rc_r, pi_rc_a;   // pi / Rc
+    float shf_r[kNr];
+    float shf_a[kNa];
+    float cos_z[kNz];
+    float sin_z[kNz];
+};
+
+// Orthorhombic box as kernels see it (periodic == 0: open boundaries).
+struct BoxConst {
+    int periodic;
+    float L[3];
+};
+
+// Per-species, per-layer weight pointers for the MLP kernels.
+struct MlpPtrs {
+    const float* W[kMaxSpecies][kMaxLayers];        // [Np][Kp]  (out x in), fp32, padded
+    const float* WT[kMaxSpecies][kMaxLayers];       // [Kp][Np]  (in x out), fp32, padded
+    const uint16_t* Wb[kMaxSpecies][kMaxLayers];    // bf16 copies
+    const uint16_t* WTb[kMaxSpecies][kMaxLayers];
+    const float* b[kMaxSpecies][kMaxLayers];        // [Np]
+    const float* head_w[kMaxSpecies];               // last layer weights [Kp_last]
+    float head_b[kMaxSpecies];                      // last bias + self energy (fp32)
+};
+
+}  // namespace nnp
+
+struct nnp_model {
+    int device;
+    nnp_precision precision;
+    nnp::AevConst aev;
+    int n_layers;                     // including the 1-wide head
+    int widths[nnp::kMaxLayers + 1];
+    int wpad[nnp::kMaxLayers + 1];    // widths padded to multiples of 64 (head: 1)
+    float celu_alpha;
+    double self_energy[nnp::kMaxSpecies];
+    double head_bias64[nnp::kMaxSpecies];
+    void* dev_weights;                // one allocation for every packed weight
+    size_t dev_weights_bytes;
+    nnp::MlpPtrs ptrs;
+    unsigned* flags;                  // device sticky error flags
+    void* host_stage;                 // pinned host staging for synchronous reads
+};
+
+namespace nnp {
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+
+// number of set lanes below the calling lane in mask
+__device__ __forceinline__ int rank_below(unsigned long long mask) {
+    return __popcll(mask & ((1ull << lane_id()) - 1ull));
+}
+
+__device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, kWave); }
+__device__ __forceinline__ int shfl(int v, int src) { return __shfl(v, src, kWave); }
+__device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ __forceinline__ double shfl_xor(double v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ __forceinline__ int shfl_xor(int v, int m) { return __shfl_xor(v, m, kWave); }
+
+// Make LDS writes of this wave visible to its other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void set_flag(unsigned* flags, unsigned bit) {
+    atomicOr(flags, bit);
+}
+
+// Round-to-nearest-even float32 -> bfloat16 bits.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace nnp
+
+// ---------------------------------------------------------------- launchers (host)
+
+namespace nnp {
+
+struct SelfE {
+    double e[kMaxSpecies];
+};
+
+struct MlpWs {
+    int32_t* bcount;     // [blocks][8]
+    int32_t* boff;       // [blocks][8]
+    int32_t* meta;       // [32]: counts[8], padded offsets[9]
+    int32_t* prow;       // [n] atom -> grouped row
+    int32_t* row_atom;   // [rows_max] grouped row -> atom (-1: padding)
+    int rows_max;
+};
+
+hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
+                                     int64_t* block_tmp, hipStream_t s);
+size_t scan_tmp_elems(int n);
+
+size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list);
+nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
+                           const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host, void* ws,
+                           size_t ws_bytes, hipStream_t s);
+nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev,
+                                int64_t* total_host);
+
+hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
+                          const nnp_nlist* nl, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
+                          hipStream_t s);
+hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
+                          const nnp_nlist* nl, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
+                          unsigned* flags, hipStream_t s);
+
+hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, hipStream_t s);
+hipError_t launch_zero_pad_rows(const MlpWs& W, int stride, void* aev, bool bf16, hipStream_t s);
+hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool aev_bf16, float* const* h,
+                      float* g_out, float* E_row, hipStream_t s);
+hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
+                         int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_row, double* e_mol,
+                         float* e_atom, unsigned* flags, hipStream_t s);
+hipError_t launch_permute_rows(bool to_grouped, const int32_t* prow, int n, int stride, const float* src, float* dst,
+                               hipStream_t s);
+hipError_t launch_gather_e(const int32_t* prow, int n, const int32_t* species, const SelfE& se, const float* E_row,
+                           float* e_atom, hipStream_t s);
+
+hipError_t launch_force_gather(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
+                               hipStream_t s);
+hipError_t launch_kick_drift(int n, float* pos, float* vel, const float* F, const float* inv_mass, float dt,
+                             const float* ref, float* max_d2, hipStream_t s);
+hipError_t launch_kick(int n, float* vel, const float* F, const float* inv_mass, float dt, hipStream_t s);
+hipError_t launch_wrap(int n, float* pos, const float* L, hipStream_t s);
+
+}  // namespace nnp

@@ -1,0 +1,103 @@
+// Device-wide exclusive prefix sum of int32 counts (three passes: block
+// sums, scan of the block sums, block-local scan plus offset).  Used for
+// cell starts and neighbour-row pointers.  Totals are carried in int64 so an
+// overflowing pair count is detected rather than wrapped.
+#include "nnp_internal.hpp"
+
+namespace nnp {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+// inclusive scan of v across the wave
+__device__ __forceinline__ long long wave_inclusive(long long v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        long long u = __shfl_up(v, d, kWave);
+        if (l >= d) v += u;
+    }
+    return v;
+}
+
+// exclusive block scan of one value per thread; returns block total via *tot
+__device__ long long block_exclusive(long long v, long long* tot) {
+    __shared__ long long wsum[kScanThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    long long inc = wave_inclusive(v);
+    if (lane_id() == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    long long off = 0, all = 0;
+    for (int i = 0; i < kScanThreads / kWave; ++i) {
+        if (i < w) off += wsum[i];
+        all += wsum[i];
+    }
+    __syncthreads();
+    *tot = all;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_block_sums(const int32_t* in, int n, int64_t* bsum) {
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    long long tot;
+    block_exclusive(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t* bsum, int nb, int64_t* total,
+                                                            int32_t* out_last) {
+    long long carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += kScanThreads) {
+        const int i = c0 + threadIdx.x;
+        long long v = i < nb ? bsum[i] : 0;
+        long long tot;
+        long long ex = block_exclusive(v, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        *total = carry;
+        *out_last = carry > 0x7fffffffLL ? 0x7fffffff : (int32_t)carry;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_block_scan(const int32_t* in, int n, const int64_t* boff,
+                                                             int32_t* out) {
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    long long tot;
+    long long ex = block_exclusive(s, &tot) + boff[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = ex > 0x7fffffffLL ? 0x7fffffff : (int32_t)ex;
+        ex += v[k];
+    }
+}
+
+}  // namespace
+
+size_t scan_tmp_elems(int n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanBlock) + 1; }
+
+// out has n + 1 entries; out[n] = total (saturated to int32); *total_out (device) = exact total.
+hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
+                                     int64_t* block_tmp, hipStream_t s) {
+    const int nb = ceil_div(n > 0 ? n : 1, kScanBlock);
+    k_block_sums<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp);
+    k_scan_sums<<<1, kScanThreads, 0, s>>>(block_tmp, nb, total_out, out + n);
+    k_block_scan<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp, out);
+    return hipGetLastError();
+}
+
+}  // namespace nnp

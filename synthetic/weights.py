@@ -2,7 +2,7 @@
 
 Drawn from numpy's PCG64 generator in a fixed order: species, then layer,
 then W (row-major [out][in]) followed by b.  The seed plays the role of the
-paper's model-initialisation key (Sec. 2, "Building a FeNNix model").
+paper's model-initialisation key (Sec. 2.4, "Building a FeNNix model").
 Weights are float32 values; both implementations receive the same numbers.
 """
 import numpy as np
