@@ -224,6 +224,65 @@ nnp_status nnp_md_kick(int32_t n_atoms, float* vel, const float* forces, const f
 /* Wrap positions into [0, L) per dimension (periodic boxes, before a rebuild). */
 nnp_status nnp_md_wrap(int32_t n_atoms, float* pos, const float* box_host, void* stream);
 
+/* ---------------------------------------------------------------- serving */
+
+/* Continuous-batching server over one model (the model must outlive it).
+ * Requests are single open-boundary structures of 1..256 atoms (Sec. 2.1:
+ * structures of a batch never interact; Sec. 2.4: a batch is the
+ * concatenation of its structures' atoms).  A request is admitted when a
+ * slot is free and its inputs fit in the request arena; a scheduler thread
+ * gathers every queued request (FIFO, up to 16384 atoms) into the next
+ * launch as soon as one of `max_inflight` launch contexts is free, so
+ * requests arriving while others are on the GPU join the next launch and
+ * launches overlap on the device, each on its own stream with persistent
+ * device buffers.
+ *   arena_bytes  pinned host bytes for queued request inputs (16 B per atom)
+ *   max_slots    most requests admitted and not yet polled to completion
+ *   max_inflight launch contexts (1..4); each holds ~170 MB of device memory */
+nnp_status nnp_server_create(nnp_model* model, size_t arena_bytes, int32_t max_slots,
+                             int32_t max_inflight, nnp_server** out);
+/* Admit one request: host species [n_atoms] and float32 positions
+ * [n_atoms][3] are copied (the caller may reuse its buffers on return);
+ * *ticket receives a monotonically increasing id.  NNP_E_BUSY if no slot or
+ * arena memory is free now (retry later); NNP_E_ARG for a request that can
+ * never be served (size, species), NNP_E_NONFINITE for NaN/Inf positions. */
+nnp_status nnp_submit(nnp_server* server, int32_t n_atoms, const int32_t* species,
+                      const float* pos, uint64_t* ticket);
+/* Non-blocking: NNP_E_PENDING until the request has completed; then copies
+ * the float64 energy and float32 forces [n_atoms][3] (forces may be NULL)
+ * to host memory and frees the slot (a ticket can be polled to completion
+ * once; an unknown or already collected ticket gives NNP_E_ARG).  A request
+ * whose launch raised a device flag completes with that flag's status. */
+nnp_status nnp_poll(nnp_server* server, uint64_t ticket, double* energy, float* forces);
+/* Counters: completed requests, launches issued, requests summed over launches. */
+nnp_status nnp_server_stats(nnp_server* server, uint64_t* completed, uint64_t* launches,
+                            uint64_t* batched_requests);
+void nnp_server_destroy(nnp_server* server);
+
+/* ---------------------------------------------------------------- stage timing */
+
+/* Stages of nnp_neighbors / nnp_energy_forces / the MD kernels, for timing. */
+enum {
+    NNP_STAGE_NEIGHBORS = 0,   /* cell binning, row count, row fill + sort, reverse index */
+    NNP_STAGE_GROUP = 1,       /* species grouping                                      */
+    NNP_STAGE_AEV = 2,         /* AEV forward (one kernel)                               */
+    NNP_STAGE_MLP = 3,         /* species networks, forward and adjoint                  */
+    NNP_STAGE_ENERGY = 4,      /* float64 structure energies                            */
+    NNP_STAGE_AEV_ADJ = 5,     /* AEV adjoint -> edge gradients (one kernel)             */
+    NNP_STAGE_FORCES = 6,      /* force gather (one kernel)                              */
+    NNP_N_STAGES = 7
+};
+
+/* Enable (1) or disable (0) per-stage timing: while enabled, the library
+ * records a pair of HIP events on the call's stream around every stage it
+ * enqueues (a few microseconds of host overhead per stage; intended for one
+ * stream at a time).  Enabling clears the accumulated times. */
+nnp_status nnp_profile_enable(nnp_model* model, int enable);
+/* Wait for the recorded events, add their elapsed times to the running
+ * totals and return them: ms[NNP_N_STAGES] (milliseconds summed over
+ * launches) and count[NNP_N_STAGES] (number of timed stage executions). */
+nnp_status nnp_profile_read(nnp_model* model, double* ms, int64_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ STATUS_NAMES = ["NNP_OK", "NNP_E_ARG", "NNP_E_CAPACITY", "NNP_E_BOX", "NNP_E_NON
                 "NNP_E_NOMEM", "NNP_E_BUSY", "NNP_E_PENDING", "NNP_E_HIP", "NNP_E_ROW"]
 NNP_MAX_ROW = 256
 NNP_MAX_ANGULAR = 96
+STAGES = ["neighbors", "group", "aev", "mlp", "energy", "aev_adjoint", "forces"]
 
 # symbol -> (restype, argtypes)
 SIGNATURES = {
@@ -41,6 +42,15 @@ SIGNATURES = {
                                          c_void_p, c_void_p, c_void_p]),
     "nnp_md_kick": (ctypes.c_int, [ctypes.c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p]),
     "nnp_md_wrap": (ctypes.c_int, [ctypes.c_int32, c_void_p, c_void_p, c_void_p]),
+    "nnp_server_create": (ctypes.c_int, [c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(c_void_p)]),
+    "nnp_submit": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "nnp_poll": (ctypes.c_int, [c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), c_void_p]),
+    "nnp_server_stats": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "nnp_server_destroy": (None, [c_void_p]),
+    "nnp_profile_enable": (ctypes.c_int, [c_void_p, ctypes.c_int]),
+    "nnp_profile_read": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 
 

@@ -29,6 +29,79 @@ uint16_t host_bf16(float f) {
 
 std::mutex g_stage_mutex;
 
+}  // namespace
+
+struct nnp_prof {
+    bool enabled = false;
+    std::mutex mu;
+    std::vector<hipEvent_t> free_events;
+    struct Pair { hipEvent_t a, b; int stage; };
+    std::vector<Pair> pending;
+    hipEvent_t open[NNP_N_STAGES] = {};
+    double ms[NNP_N_STAGES] = {};
+    int64_t cnt[NNP_N_STAGES] = {};
+
+    hipEvent_t take() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void drain() {
+        for (auto& p : pending) {
+            float t = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+                ms[p.stage] += t;
+                cnt[p.stage] += 1;
+            }
+            free_events.push_back(p.a);
+            free_events.push_back(p.b);
+        }
+        pending.clear();
+    }
+    ~nnp_prof() {
+        drain();
+        for (auto e : free_events) (void)hipEventDestroy(e);
+        for (auto e : open)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace nnp {
+
+void prof_begin(nnp_model* m, int stage, hipStream_t s) {
+    nnp_prof* p = m->prof;
+    if (!p || !p->enabled) return;
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (p->pending.size() > 16384) p->drain();
+    hipEvent_t e = p->take();
+    if (!e) return;
+    if (p->open[stage]) p->free_events.push_back(p->open[stage]);
+    p->open[stage] = e;
+    (void)hipEventRecord(e, s);
+}
+
+void prof_end(nnp_model* m, int stage, hipStream_t s) {
+    nnp_prof* p = m->prof;
+    if (!p || !p->enabled) return;
+    std::lock_guard<std::mutex> lock(p->mu);
+    hipEvent_t a = p->open[stage];
+    if (!a) return;
+    hipEvent_t b = p->take();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    p->pending.push_back({a, b, stage});
+    p->open[stage] = nullptr;
+}
+
+}  // namespace nnp
+
+namespace {
+
 struct EfWs {
     MlpWs mw;
     int32_t* mstart;
@@ -37,6 +110,7 @@ struct EfWs {
     float* g;
     float* h[kMaxLayers];
     float* E_row;
+    float* E_at;        // network energies in atom order
     float* Gx;
     float* Gy;
     float* Gz;
@@ -63,6 +137,7 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.g = (float*)W.aev;
     for (int l = 0; l + 1 < m->n_layers; ++l) W.h[l] = (float*)take(sizeof(float) * (size_t)rows_max * m->wpad[l + 1]);
     W.E_row = (float*)take(sizeof(float) * rows_max);
+    W.E_at = (float*)take(sizeof(float) * nn);
     const int64_t c = cap > 0 ? cap : 1;
     W.Gx = (float*)take(sizeof(float) * c);
     W.Gy = (float*)take(sizeof(float) * c);
@@ -109,6 +184,54 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 }
 
 }  // namespace nnp
+
+nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species,
+                                   const int32_t* mol, int32_t n_mol, const float* box_host, const nnp_nlist* nl,
+                                   double* e_mol, float* e_atom, float* forces, void* ws, size_t ws_bytes,
+                                   hipStream_t s, unsigned* flags) {
+    if (!m || !nl || n < 0) return NNP_E_ARG;
+    if (n > 0 && (!pos || !species)) return NNP_E_ARG;
+    if (n_mol < 0 || (n > 0 && n_mol < 1) || n_mol > (n > 0 ? n : 1)) return NNP_E_ARG;
+    if (n_mol > 0 && !e_mol) return NNP_E_ARG;
+    if (nl->n_atoms != n) return NNP_E_ARG;
+    if (box_host && (nl->r_list * 2.f > box_host[0] || nl->r_list * 2.f > box_host[1] || nl->r_list * 2.f > box_host[2]))
+        return NNP_E_BOX;
+    if (nl->r_list < m->aev.rc_r) return NNP_E_ARG;
+    const EfWs need = ef_layout(m, n, nl->capacity, nullptr);
+    if (!ws || ws_bytes < need.end) return NNP_E_ARG;
+    const EfWs W = ef_layout(m, n, nl->capacity, (char*)ws);
+    const BoxConst bx = box_const(box_host);
+    const bool bf = m->precision == NNP_BF16_MLP;
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        prof_begin(m, NNP_STAGE_GROUP, s);
+        e = launch_species_group(m, n, species, W.mw, flags, s);
+        if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, bf, s);
+        prof_end(m, NNP_STAGE_GROUP, s);
+        prof_begin(m, NNP_STAGE_AEV, s);
+        if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.aev, bf, flags, s);
+        prof_end(m, NNP_STAGE_AEV, s);
+        prof_begin(m, NNP_STAGE_MLP, s);
+        if (e == hipSuccess)
+            e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, W.E_at, s);
+        prof_end(m, NNP_STAGE_MLP, s);
+    }
+    prof_begin(m, NNP_STAGE_ENERGY, s);
+    if (e == hipSuccess)
+        e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at, e_mol, e_atom, flags,
+                          s);
+    prof_end(m, NNP_STAGE_ENERGY, s);
+    if (e == hipSuccess && forces && n > 0) {
+        prof_begin(m, NNP_STAGE_AEV_ADJ, s);
+        e = launch_aev_bwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, flags, s);
+        prof_end(m, NNP_STAGE_AEV_ADJ, s);
+        prof_begin(m, NNP_STAGE_FORCES, s);
+        if (e == hipSuccess) e = launch_force_gather(n, nl, W.Gx, W.Gy, W.Gz, forces, s);
+        prof_end(m, NNP_STAGE_FORCES, s);
+    }
+    return hip_status(e);
+}
+
 
 extern "C" {
 
@@ -258,6 +381,7 @@ void nnp_model_destroy(nnp_model* m) {
     if (m->dev_weights) (void)hipFree(m->dev_weights);
     if (m->flags) (void)hipFree(m->flags);
     if (m->host_stage) (void)hipHostFree(m->host_stage);
+    delete m->prof;
     delete m;
 }
 
@@ -306,35 +430,9 @@ nnp_status nnp_energy_forces(nnp_model* m, int32_t n, const float* pos, const in
                              int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,
                              float* forces, void* ws, size_t ws_bytes, void* stream) {
     if (!m || !nl || n < 0) return NNP_E_ARG;
-    if (n > 0 && (!pos || !species)) return NNP_E_ARG;
-    if (n_mol < 0 || (n > 0 && n_mol < 1) || n_mol > (n > 0 ? n : 1)) return NNP_E_ARG;
-    if (n_mol > 0 && !e_mol) return NNP_E_ARG;
     if (nl->n_atoms != n || nl->n_pairs > nl->capacity) return NNP_E_ARG;
-    if (box_host && (nl->r_list * 2.f > box_host[0] || nl->r_list * 2.f > box_host[1] || nl->r_list * 2.f > box_host[2]))
-        return NNP_E_BOX;
-    if (nl->r_list < m->aev.rc_r) return NNP_E_ARG;
-    const EfWs need = ef_layout(m, n, nl->capacity, nullptr);
-    if (!ws || ws_bytes < need.end) return NNP_E_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    const EfWs W = ef_layout(m, n, nl->capacity, (char*)ws);
-    const BoxConst bx = box_const(box_host);
-    const bool bf = m->precision == NNP_BF16_MLP;
-    hipError_t e = hipSuccess;
-    if (n > 0) {
-        e = launch_species_group(m, n, species, W.mw, s);
-        if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, bf, s);
-        if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.aev, bf, m->flags, s);
-        if (e == hipSuccess)
-            e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, s);
-    }
-    if (e == hipSuccess)
-        e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_row, e_mol, e_atom, m->flags,
-                          s);
-    if (e == hipSuccess && forces && n > 0) {
-        e = launch_aev_bwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, m->flags, s);
-        if (e == hipSuccess) e = launch_force_gather(n, nl, W.Gx, W.Gy, W.Gz, forces, s);
-    }
-    return hip_status(e);
+    return energy_forces_impl(m, n, pos, species, mol, n_mol, box_host, nl, e_mol, e_atom, forces, ws, ws_bytes,
+                              (hipStream_t)stream, m->flags);
 }
 
 nnp_status nnp_aev(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const float* box_host,
@@ -355,10 +453,10 @@ nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float*
     if (n == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
     const EfWs W = ef_layout(m, n, 0, (char*)ws);
-    hipError_t e = launch_species_group(m, n, species, W.mw, s);
+    hipError_t e = launch_species_group(m, n, species, W.mw, m->flags, s);
     if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, false, s);
     if (e == hipSuccess) e = launch_permute_rows(true, W.mw.prow, n, m->aev.stride, aev_in, (float*)W.aev, s);
-    if (e == hipSuccess) e = launch_mlp(m, W.mw, W.aev, false, W.h, daev_out ? W.g : nullptr, W.E_row, s);
+    if (e == hipSuccess) e = launch_mlp(m, W.mw, W.aev, false, W.h, daev_out ? W.g : nullptr, W.E_row, nullptr, s);
     if (e == hipSuccess) e = launch_gather_e(W.mw.prow, n, species, self_e(m), W.E_row, e_atom, s);
     if (e == hipSuccess && daev_out) e = launch_permute_rows(false, W.mw.prow, n, m->aev.stride, W.g, daev_out, s);
     return hip_status(e);
@@ -380,6 +478,30 @@ nnp_status nnp_md_wrap(int32_t n, float* pos, const float* box_host, void* strea
     for (int k = 0; k < 3; ++k)
         if (!(box_host[k] > 0.f)) return NNP_E_ARG;
     return hip_status(launch_wrap(n, pos, box_host, (hipStream_t)stream));
+}
+
+nnp_status nnp_profile_enable(nnp_model* m, int enable) {
+    if (!m) return NNP_E_ARG;
+    if (!m->prof) m->prof = new nnp_prof;
+    std::lock_guard<std::mutex> lock(m->prof->mu);
+    m->prof->drain();
+    for (int k = 0; k < NNP_N_STAGES; ++k) {
+        m->prof->ms[k] = 0.0;
+        m->prof->cnt[k] = 0;
+    }
+    m->prof->enabled = enable != 0;
+    return NNP_OK;
+}
+
+nnp_status nnp_profile_read(nnp_model* m, double* ms, int64_t* count) {
+    if (!m || !m->prof) return NNP_E_ARG;
+    std::lock_guard<std::mutex> lock(m->prof->mu);
+    m->prof->drain();
+    for (int k = 0; k < NNP_N_STAGES; ++k) {
+        if (ms) ms[k] = m->prof->ms[k];
+        if (count) count[k] = m->prof->cnt[k];
+    }
+    return NNP_OK;
 }
 
 }  // extern "C"

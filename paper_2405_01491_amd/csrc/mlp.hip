@@ -291,7 +291,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmArgs g) {
 
 // one wave per padded row: E = w . h + b; d = w * CELU'(h) in place
 __global__ __launch_bounds__(256) void k_head(const int32_t* meta, int ns, const int32_t* row_atom, int rows_max,
-                                             const MlpPtrs P, int K, int ld, float alpha, float* H, float* E_row) {
+                                             const MlpPtrs P, int K, int ld, float alpha, float* H, float* E_row,
+                                             float* E_atomo) {
     const int r = blockIdx.x * 4 + threadIdx.x / kWave;
     const int l = lane_id();
     if (r >= rows_max || r >= meta[8 + ns]) return;
@@ -307,28 +308,35 @@ __global__ __launch_bounds__(256) void k_head(const int32_t* meta, int ns, const
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) acc += shfl_xor(acc, m);
-    if (l == 0) E_row[r] = acc + P.head_b[s];
+    if (l == 0) {
+        E_row[r] = acc + P.head_b[s];
+        const int a = row_atom[r];
+        if (a >= 0 && E_atomo) E_atomo[a] = acc + P.head_b[s];
+    }
 }
 
 // float64 structure energies: per-thread partial sums in ascending atom
-// order, then a fixed tree.  Self energies are added in float64 per atom.
-__global__ __launch_bounds__(256) void k_energy(int n_mol, const int32_t* mstart, const int32_t* mend,
-                                               const int32_t* prow, const int32_t* species, const SelfE se,
-                                               const float* E_row, double* e_mol, float* e_atom) {
-    __shared__ double part[256];
+// order (energies already in atom order), then a fixed tree.  Self energies
+// are added in float64 per atom.  Atoms without a network energy (invalid
+// species, flagged) contribute zero.
+template <int kThreads>
+__global__ __launch_bounds__(kThreads) void k_energy(int n_mol, const int32_t* mstart, const int32_t* mend,
+                                                    const int32_t* prow, const int32_t* species, const SelfE se,
+                                                    const float* E_at, double* e_mol, float* e_atom) {
+    __shared__ double part[kThreads];
     const int m = blockIdx.x;
     if (m >= n_mol) return;
     const int b = mstart[m], e = mend[m];
     double acc = 0.0;
-    for (int a = b + threadIdx.x; a < e; a += 256) {
-        const int r = prow[a];
-        const double v = r >= 0 ? (double)E_row[r] + se.e[species[a]] : 0.0;
+    for (int a = b + threadIdx.x; a < e; a += kThreads) {
+        const bool ok = prow[a] >= 0;
+        const double v = ok ? (double)E_at[a] + se.e[species[a]] : 0.0;
         if (e_atom) e_atom[a] = (float)v;
         acc += v;
     }
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int st = 128; st >= 1; st >>= 1) {
+    for (int st = kThreads / 2; st >= 1; st >>= 1) {
         if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
         __syncthreads();
     }
@@ -348,6 +356,13 @@ __global__ void k_mol_ranges2(const int32_t* mol, int n, int n_mol, int32_t* sta
     if (i > 0 && prev > m) set_flag(flags, NNP_FLAG_MOL);
     if (prev != m) start[m] = i;
     if (next != m) end[m] = i + 1;
+}
+
+__global__ void k_atom_e(const int32_t* prow, int n, const int32_t* species, const SelfE se, const float* E_at,
+                         float* e_atom) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    e_atom[a] = prow[a] >= 0 ? (float)((double)E_at[a] + se.e[species[a]]) : 0.f;
 }
 
 // scatter/gather of rows between atom order and grouped order
@@ -374,11 +389,12 @@ __global__ void k_gather_e(const int32_t* prow, int n, const int32_t* species, c
 
 // ---------------------------------------------------------------- host side
 
-hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, hipStream_t s) {
+hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, unsigned* flags,
+                                hipStream_t s) {
     const int ns = m->aev.ns;
     const int nb = ceil_div(n > 0 ? n : 1, kGroupBlock);
     k_fill_i32<<<ceil_div(W.rows_max, 256), 256, 0, s>>>(W.row_atom, W.rows_max, -1);
-    k_species_count<<<nb, 256, 0, s>>>(species, n, ns, W.bcount, m->flags);
+    k_species_count<<<nb, 256, 0, s>>>(species, n, ns, W.bcount, flags);
     k_species_scan<<<1, 64, 0, s>>>(W.bcount, nb, ns, W.boff, W.meta);
     k_species_rank<<<nb, 256, 0, s>>>(species, n, ns, W.boff, W.meta, W.prow, W.row_atom);
     return hipGetLastError();
@@ -397,7 +413,7 @@ hipError_t launch_zero_pad_rows(const MlpWs& W, int stride, void* aev, bool bf16
 // bf16 for the BF16 form); h[l]: fp32 activation buffers [rows_max][wpad[l+1]];
 // g_out: fp32 [rows_max][stride]; E_row: [rows_max].
 hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool aev_bf16, float* const* h,
-                      float* g_out, float* E_row, hipStream_t s) {
+                      float* g_out, float* E_row, float* E_atomo, hipStream_t s) {
     const int ns = m->aev.ns;
     const int L = m->n_layers;      // includes head
     const int tiles = ceil_div(W.rows_max, kTileM);
@@ -429,7 +445,7 @@ hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool 
     }
     // head: energy and d_L (in place in h[L-2])
     k_head<<<ceil_div(W.rows_max, 4), 256, 0, s>>>(W.meta, ns, W.row_atom, W.rows_max, m->ptrs, m->widths[L - 1],
-                                                  m->wpad[L - 1], m->celu_alpha, h[L - 2], E_row);
+                                                  m->wpad[L - 1], m->celu_alpha, h[L - 2], E_row, E_atomo);
     if (!g_out) return hipGetLastError();
     // adjoint: d_{l-1} = (W_l^T d_l) * CELU'(h_{l-1}), l = L-2 .. 1; then g = W_0^T d_0
     for (int l = L - 2; l >= 0; --l) {
@@ -457,15 +473,18 @@ hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool 
 }
 
 hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
-                         int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_row, double* e_mol,
+                         int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_at, double* e_mol,
                          float* e_atom, unsigned* flags, hipStream_t s) {
     if (n_mol > 0) {
         k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mstart, n_mol, 0);
         k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mend, n_mol, 0);
         if (n > 0) k_mol_ranges2<<<ceil_div(n, 256), 256, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
-        k_energy<<<n_mol, 256, 0, s>>>(n_mol, mstart, mend, W.prow, species, se, E_row, e_mol, e_atom);
+        if (n_mol == 1)
+            k_energy<1024><<<1, 1024, 0, s>>>(n_mol, mstart, mend, W.prow, species, se, E_at, e_mol, e_atom);
+        else
+            k_energy<128><<<n_mol, 128, 0, s>>>(n_mol, mstart, mend, W.prow, species, se, E_at, e_mol, e_atom);
     } else if (e_atom && n > 0) {
-        k_gather_e<<<ceil_div(n, 256), 256, 0, s>>>(W.prow, n, species, se, E_row, e_atom);
+        k_atom_e<<<ceil_div(n, 256), 256, 0, s>>>(W.prow, n, species, se, E_at, e_atom);
     }
     return hipGetLastError();
 }

@@ -344,7 +344,7 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host,
-                           void* ws, size_t ws_bytes, hipStream_t s) {
+                           void* ws, size_t ws_bytes, hipStream_t s, bool sync, unsigned* flags_override) {
     Grid g;
     nnp_status st = make_grid(box_host, r_list, &g);
     if (st != NNP_OK) return st;
@@ -362,7 +362,7 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     int32_t* mol_end = (int32_t*)(base + L.mol_end);
     int64_t* scan_tmp = (int64_t*)(base + L.scan_tmp);
     int64_t* totals = (int64_t*)(base + L.totals);
-    unsigned* flags = model->flags;
+    unsigned* flags = flags_override ? flags_override : model->flags;
     const double rl = (double)r_list;
     const double r2 = rl * rl;
     const int tb = 256;
@@ -370,6 +370,7 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
 
     hipError_t he = hipSuccess;
     auto chk = [&](hipError_t x) { if (he == hipSuccess) he = x; };
+    prof_begin(model, NNP_STAGE_NEIGHBORS, s);
     if (n > 0) {
         if (mol) {
             chk(hipMemsetAsync(mol_start, 0, sizeof(int32_t) * n_mol, s));
@@ -390,15 +391,36 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     }
     chk(launch_exclusive_scan_i32(row_count, nl->row_ptr, totals, n, scan_tmp, s));
     chk(hipGetLastError());
-    if (he != hipSuccess) return NNP_E_HIP;
+    if (he != hipSuccess) {
+        prof_end(model, NNP_STAGE_NEIGHBORS, s);
+        return NNP_E_HIP;
+    }
     int64_t total = 0;
     uint32_t fl = 0;
+    if (!sync) {
+        // caller guarantees the capacity (e.g. all pairs of every structure) and checks flags itself
+        nl->n_atoms = n;
+        nl->r_list = r_list;
+        nl->n_pairs = -1;
+        if (n > 0) {
+            k_rows<1><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
+                pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, nullptr, nl->row_ptr,
+                nl->col, nl->shift, flags);
+            k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev);
+        }
+        prof_end(model, NNP_STAGE_NEIGHBORS, s);
+        return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
+    }
     st = read_and_clear_flags(model, s, &fl, totals, &total);
-    if (st != NNP_OK) return st;
+    if (st != NNP_OK) {
+        prof_end(model, NNP_STAGE_NEIGHBORS, s);
+        return st;
+    }
     if (n_pairs_host) *n_pairs_host = total;
     nl->n_atoms = n;
     nl->r_list = r_list;
     nl->n_pairs = total;
+    if (fl || total > nl->capacity || total > 0x7fffffffLL) prof_end(model, NNP_STAGE_NEIGHBORS, s);
     if (fl) {
         if (fl & NNP_FLAG_NONFINITE) return NNP_E_NONFINITE;
         if (fl & NNP_FLAG_ROW) return NNP_E_ROW;
@@ -411,6 +433,7 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
             nl->col, nl->shift, flags);
         k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev);
     }
+    prof_end(model, NNP_STAGE_NEIGHBORS, s);
     return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
 }
 

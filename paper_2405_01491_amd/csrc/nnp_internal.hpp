@@ -66,6 +66,7 @@ struct nnp_model {
     nnp::MlpPtrs ptrs;
     unsigned* flags;                  // device sticky error flags
     void* host_stage;                 // pinned host staging for synchronous reads
+    struct nnp_prof* prof;            // per-stage event timing (host side)
 };
 
 namespace nnp {
@@ -129,14 +130,24 @@ struct MlpWs {
     int rows_max;
 };
 
+// Per-stage timing hooks (no-ops unless nnp_profile_enable(model, 1)).
+void prof_begin(nnp_model* m, int stage, hipStream_t s);
+void prof_end(nnp_model* m, int stage, hipStream_t s);
+
 hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
                                      int64_t* block_tmp, hipStream_t s);
 size_t scan_tmp_elems(int n);
 
 size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list);
+// sync == false: no pair-count readback (the caller guarantees the capacity),
+// device flags go to flags_override (or the model's flags if null).
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host, void* ws,
-                           size_t ws_bytes, hipStream_t s);
+                           size_t ws_bytes, hipStream_t s, bool sync = true, unsigned* flags_override = nullptr);
+// nnp_energy_forces with an explicit device flags word (n_pairs of nl is not checked)
+nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
+                              int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,
+                              float* forces, void* ws, size_t ws_bytes, hipStream_t s, unsigned* flags);
 nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev,
                                 int64_t* total_host);
 
@@ -147,12 +158,13 @@ hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int3
                           const nnp_nlist* nl, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
                           unsigned* flags, hipStream_t s);
 
-hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, hipStream_t s);
+hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, unsigned* flags,
+                                hipStream_t s);
 hipError_t launch_zero_pad_rows(const MlpWs& W, int stride, void* aev, bool bf16, hipStream_t s);
 hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool aev_bf16, float* const* h,
-                      float* g_out, float* E_row, hipStream_t s);
+                      float* g_out, float* E_row, float* E_atomo, hipStream_t s);
 hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
-                         int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_row, double* e_mol,
+                         int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_at, double* e_mol,
                          float* e_atom, unsigned* flags, hipStream_t s);
 hipError_t launch_permute_rows(bool to_grouped, const int32_t* prow, int n, int stride, const float* src, float* dst,
                                hipStream_t s);

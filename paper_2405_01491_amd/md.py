@@ -1,0 +1,127 @@
+"""GPU-resident NVE molecular dynamics over the C ABI (Sec. 5.4, "Native MD
+engine": velocity Verlet for NVE, state kept on the GPU, host only enqueues).
+
+Per step:  kick + drift (nnp_md_kick_drift) -> neighbour rebuild when due
+(wrap into the box, nnp_neighbors) -> energy and forces (nnp_energy_forces)
+-> kick (nnp_md_kick).  With a skin (Sec. 5.5: a buffer and a rebuild every
+few steps), the list is rebuilt every ``rebuild_every`` steps, and earlier if
+the largest displacement since the last build exceeds ``trigger * skin / 2``;
+that displacement is folded on the device each step and read back through
+pinned memory one step late, so the loop never waits for it.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib, nnp_energy_forces, nnp_neighbors
+from ._lib import check, lib
+
+KB_EV = 8.617333262e-5       # eV / K
+ACC_UNIT = 9.648533212e-3    # (eV / A / amu) -> A / fs^2
+
+
+def maxwell_boltzmann(masses, temperature, seed):
+    """Velocities (A/fs) at the given temperature, zero total momentum."""
+    rng = np.random.default_rng(seed)
+    m = np.asarray(masses, dtype=np.float64)
+    sigma = np.sqrt(KB_EV * temperature / m * ACC_UNIT)
+    v = rng.normal(size=(len(m), 3)) * sigma[:, None]
+    v -= (m[:, None] * v).sum(0) / m.sum()
+    return v.astype(np.float32)
+
+
+def _s(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class VelocityVerlet:
+    def __init__(self, model, pos, vel, species, masses, box=None, mol=None, n_mol=1, dt=0.5, skin=0.0,
+                 rebuild_every=1, trigger=0.8):
+        self.model = model
+        self.dev = pos.device
+        self.pos = pos.contiguous()
+        self.vel = vel.contiguous()
+        self.species = species
+        self.mol = mol
+        self.n_mol = n_mol
+        self.box = None if box is None else np.asarray(box, dtype=np.float32)
+        self._box_c = None if box is None else (ctypes.c_float * 3)(*self.box.tolist())
+        self.inv_mass = (1.0 / torch.as_tensor(masses, dtype=torch.float32)).to(self.dev)
+        self.dt = float(dt)
+        self.skin = float(skin)
+        self.r_list = float(model.spec.rc_r) + self.skin
+        self.rebuild_every = max(1, int(rebuild_every))
+        self.trigger2 = (trigger * 0.5 * self.skin) ** 2 if self.skin > 0 else None
+        self.ref = torch.empty_like(self.pos)
+        self.max_d2 = torch.zeros(1, dtype=torch.float32, device=self.dev)
+        self._host_d2 = torch.zeros(1, dtype=torch.float32).pin_memory()
+        self._d2_event = None
+        self.out = {}
+        self.nl = None
+        self.steps = 0
+        self.since_build = 0
+        self.rebuilds = 0
+        self.early_rebuilds = 0
+        self._rebuild()
+        self.e_mol, _, self.forces = nnp_energy_forces(model, self.pos, species, mol, n_mol, self.box, self.nl,
+                                                       out=self.out)
+
+    def _rebuild(self):
+        L = lib()
+        if self._box_c is not None:
+            check(L.nnp_md_wrap(self.pos.shape[0], ctypes.c_void_p(self.pos.data_ptr()), self._box_c, _s(self.dev)),
+                  "nnp_md_wrap")
+        self.nl = nnp_neighbors(self.model, self.pos, self.mol, self.n_mol, self.box, self.r_list, nl=self.nl)
+        self.ref.copy_(self.pos)
+        self.max_d2.zero_()
+        self._d2_event = None
+        self.since_build = 0
+        self.rebuilds += 1
+
+    def step(self):
+        L = lib()
+        n = self.pos.shape[0]
+        track = self.trigger2 is not None
+        check(L.nnp_md_kick_drift(n, ctypes.c_void_p(self.pos.data_ptr()), ctypes.c_void_p(self.vel.data_ptr()),
+                                  ctypes.c_void_p(self.forces.data_ptr()), ctypes.c_void_p(self.inv_mass.data_ptr()),
+                                  ctypes.c_float(self.dt),
+                                  ctypes.c_void_p(self.ref.data_ptr()) if track else None,
+                                  ctypes.c_void_p(self.max_d2.data_ptr()) if track else None, _s(self.dev)),
+              "nnp_md_kick_drift")
+        self.since_build += 1
+        due = self.since_build >= self.rebuild_every
+        if not due and track and self._d2_event is not None and self._d2_event.query():
+            if float(self._host_d2[0]) > self.trigger2:
+                due = True
+                self.early_rebuilds += 1
+        if due:
+            self._rebuild()
+        elif track:
+            self._host_d2.copy_(self.max_d2, non_blocking=True)
+            self._d2_event = torch.cuda.Event()
+            self._d2_event.record()
+        self.e_mol, _, self.forces = nnp_energy_forces(self.model, self.pos, self.species, self.mol, self.n_mol,
+                                                       self.box, self.nl, out=self.out)
+        check(L.nnp_md_kick(n, ctypes.c_void_p(self.vel.data_ptr()), ctypes.c_void_p(self.forces.data_ptr()),
+                            ctypes.c_void_p(self.inv_mass.data_ptr()), ctypes.c_float(self.dt), _s(self.dev)),
+              "nnp_md_kick")
+        self.steps += 1
+
+    def kinetic_energy(self):
+        m = 1.0 / self.inv_mass.double()
+        return float(0.5 * (m[:, None] * self.vel.double() ** 2).sum() / ACC_UNIT)
+
+    def total_energy(self):
+        return float(self.e_mol.sum()) + self.kinetic_energy()
+
+
+def profile_enable(model, enable=True):
+    check(lib().nnp_profile_enable(model.handle, 1 if enable else 0), "nnp_profile_enable")
+
+
+def profile_read(model):
+    ms = (ctypes.c_double * len(_lib.STAGES))()
+    cnt = (ctypes.c_int64 * len(_lib.STAGES))()
+    check(lib().nnp_profile_read(model.handle, ms, cnt), "nnp_profile_read")
+    return {name: (ms[k], cnt[k]) for k, name in enumerate(_lib.STAGES)}

@@ -186,26 +186,25 @@ def serving_molecule(rng, n=None, lo=8, hi=150):
         n = min(max(n, lo), hi)
     probs = np.array([f for _, f in ORGANIC_MIX])
     species = rng.choice(np.array([s for s, _ in ORGANIC_MIX], dtype=np.int32), size=n, p=probs)
-    pts = [np.zeros(3)]
-    while len(pts) < n:
+    pts = np.zeros((n, 3))
+    k = 1
+    while k < n:
         placed = False
         for _attempt in range(200):
-            parent = len(pts) - 1 - int(rng.integers(0, min(4, len(pts))))
+            parent = k - 1 - int(rng.integers(0, min(4, k)))
             d = rng.normal(size=3)
             d /= np.linalg.norm(d)
             cand = pts[parent] + rng.uniform(0.95, 1.6) * d
-            ok = True
-            for q, p in enumerate(pts):
-                if q != parent and np.sum((p - cand) ** 2) < 1.5 * 1.5:
-                    ok = False
-                    break
-            if ok:
-                pts.append(cand)
+            d2 = np.sum((pts[:k] - cand) ** 2, axis=1)
+            d2[parent] = np.inf
+            if np.all(d2 >= 1.5 * 1.5):
+                pts[k] = cand
+                k += 1
                 placed = True
                 break
         if not placed:      # crowded tail: restart the growth from scratch
-            pts = [np.zeros(3)]
-    pos = np.array(pts)
+            k = 1
+    pos = pts
     pos -= pos.mean(axis=0)
     return pos.astype(np.float32), species.astype(np.int32)
 

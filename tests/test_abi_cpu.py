@@ -25,7 +25,7 @@ def test_library_built():
 def test_exports_every_declared_symbol():
     L = _lib.lib()
     names = declared_functions()
-    assert len(names) >= 15
+    assert len(names) >= 22
     for name in names:
         assert hasattr(L, name), name
         assert name in _lib.SIGNATURES, name
