@@ -11,185 +11,30 @@
 //   with cos(theta' - theta_z) = u cos(theta_z) + sqrt(1 - u^2) sin(theta_z),
 //   u = cos_scale * cos(theta_ijk).
 //
-// Layout of the work: a wave owns one centre atom.  It streams the atom's
-// neighbour row (CSR, sorted by j) across its 64 lanes, computes edge
-// vectors in float32, and stores the neighbours within each cutoff in LDS
-// grouped by species (stable in j).  Radial sums use lanes as (shell k,
-// quarter q); angular sums evaluate one neighbour pair per lane (8 angle
-// factors + 4 radial factors, 32 products) into an LDS pair tile and reduce
-// it per species-pair segment with lanes as (a, z) columns.  Every sum is
-// taken in a fixed order, so results do not depend on scheduling.
-//
-// The adjoint recomputes the same neighbourhood, reads dE/dAEV of the atom
-// into LDS and produces G_ij = dE_i / dv_ij for every slot of the row: the
-// radial part per neighbour lane, the angular part per pair lane, gathered
-// per neighbour in a fixed order (no atomics).
+// Work layout.  A wave owns one centre atom.  Each lane holds up to four
+// slots of the atom's CSR row in registers (loaded once: one dependent-load
+// chain per row), computes the float32 edge vectors, and the neighbours
+// within each cutoff are grouped by species in LDS with a stable ballot sort.
+//   forward:  radial sums with lanes as (shell k, quarter q) over each species
+//             segment; angular sums per species-pair bin, one neighbour pair
+//             per lane (8 angle factors, 4 radial factors) into a 64-pair LDS
+//             tile, reduced by lanes as (a, z) columns in two halves.
+//   adjoint:  radial gradient by the lane that holds the slot; angular pair
+//             gradients one pair per lane into an LDS tile, gathered per
+//             neighbour in a fixed order.
+// Every sum runs in a fixed order (no atomics), so results do not depend on
+// scheduling or on the other atoms of a batch.
 #include "nnp_internal.hpp"
 
 namespace nnp {
 namespace {
 
-constexpr int kMaxR = NNP_MAX_ROW;        // neighbours within the list cutoff per atom
+constexpr int kMaxR = NNP_MAX_ROW;        // CSR slots per row
+constexpr int kQ = kMaxR / kWave;         // slots per lane
 constexpr int kMaxA = NNP_MAX_ANGULAR;    // neighbours within the angular cutoff
-constexpr int kWavesFwd = 2;
-constexpr int kWavesBwd = 2;
-constexpr int kPairStride = 33;           // 32 products + 1 pad (conflict-free)
+constexpr int kWaves = 4;                 // waves (atoms) per block
 
-struct Hood {
-    // radial list (r < Rc_R), species-sorted
-    float rr[kMaxR];
-    float rfc[kMaxR];
-    int rzs[kMaxR];        // species | (row slot offset << 8)
-    // angular list (r < Rc_A), species-sorted, subset of the radial list
-    float ax[kMaxA], ay[kMaxA], az[kMaxA];   // unit vectors
-    float ar[kMaxA];
-    float afc[kMaxA];
-    int azs[kMaxA];        // species | (radial list index << 8)
-    int sel[kMaxR];        // per row slot: species | in_r << 8 | in_a << 9 (decided once)
-    int seg_r[kMaxSpecies + 1];
-    int seg_a[kMaxSpecies + 1];
-    int n_r, n_a, ok;
-};
-
-__device__ __forceinline__ float cutoff_fc(float r, float pi_rc) {
-    return 0.5f * __cosf(pi_rc * r) + 0.5f;
-}
-
-// Stable species-grouped lists of the neighbours of atom i within the two
-// cutoffs.  Returns false (and flags) if the row is longer than supported.
-template <bool kBwd>
-__device__ bool build_hood(Hood& H, const AevConst& P, int i, const float* pos, const int32_t* species,
-                           const BoxConst bx, const int32_t* row_ptr, const int32_t* col, const int8_t* shift,
-                           float* rux, float* ruy, float* ruz, float* rdfc, float* adfc, unsigned* flags) {
-    const int l = lane_id();
-    const int b = row_ptr[i], e = row_ptr[i + 1];
-    const float xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-    const float rc_r2 = P.rc_r * P.rc_r;
-    const float rc_a2 = P.rc_a * P.rc_a;
-    const bool periodic = bx.periodic != 0;
-    const float Lx = bx.L[0], Ly = bx.L[1], Lz = bx.L[2];
-    int cnt_r[kMaxSpecies], cnt_a[kMaxSpecies];
-#pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) cnt_r[s] = cnt_a[s] = 0;
-    if (e - b > kMaxR) {
-        if (l == 0) set_flag(flags, NNP_FLAG_ROW);
-        return false;
-    }
-    // pass 1: decide membership once per slot, count per species
-    for (int t0 = b; t0 < e; t0 += kWave) {
-        const int p = t0 + l;
-        bool in_r = false, in_a = false;
-        int z = 0;
-        if (p < e) {
-            const int j = col[p];
-            z = species[j];
-            float vx = pos[3 * j] - xi, vy = pos[3 * j + 1] - yi, vz = pos[3 * j + 2] - zi;
-            if (periodic) {
-                vx += (float)shift[3 * p] * Lx;
-                vy += (float)shift[3 * p + 1] * Ly;
-                vz += (float)shift[3 * p + 2] * Lz;
-            }
-            const float r2 = vx * vx + vy * vy + vz * vz;
-            if (z < 0 || z >= P.ns) {
-                set_flag(flags, NNP_FLAG_SPECIES);
-                z = 0;
-            } else {
-                in_r = r2 < rc_r2;
-                in_a = in_r && r2 < rc_a2;
-            }
-            H.sel[p - b] = z | (in_r ? 0x100 : 0) | (in_a ? 0x200 : 0);
-        }
-#pragma unroll
-        for (int s = 0; s < kMaxSpecies; ++s) {
-            cnt_r[s] += __popcll(ballot(in_r && z == s));
-            cnt_a[s] += __popcll(ballot(in_a && z == s));
-        }
-    }
-    wave_sync();
-    int off_r[kMaxSpecies], off_a[kMaxSpecies];
-    int accr = 0, acca = 0;
-#pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) {
-        off_r[s] = accr;
-        off_a[s] = acca;
-        accr += cnt_r[s];
-        acca += cnt_a[s];
-    }
-    if (acca > kMaxA) {
-        if (l == 0) set_flag(flags, NNP_FLAG_ROW);
-        return false;
-    }
-    if (l <= kMaxSpecies) {
-        int vr = accr, va = acca;
-#pragma unroll
-        for (int s = 0; s < kMaxSpecies; ++s)
-            if (l == s) { vr = off_r[s]; va = off_a[s]; }
-        H.seg_r[l] = vr;
-        H.seg_a[l] = va;
-    }
-    if (l == 0) {
-        H.n_r = accr;
-        H.n_a = acca;
-    }
-    // pass 2: scatter into species-sorted positions (stable in j)
-    for (int t0 = b; t0 < e; t0 += kWave) {
-        const int p = t0 + l;
-        bool in_r = false, in_a = false;
-        int z = 0;
-        float vx = 0.f, vy = 0.f, vz = 0.f, r = 0.f;
-        if (p < e) {
-            const int sl = H.sel[p - b];
-            z = sl & 0xff;
-            in_r = (sl & 0x100) != 0;
-            in_a = (sl & 0x200) != 0;
-            const int j = col[p];
-            vx = pos[3 * j] - xi;
-            vy = pos[3 * j + 1] - yi;
-            vz = pos[3 * j + 2] - zi;
-            if (periodic) {
-                vx += (float)shift[3 * p] * Lx;
-                vy += (float)shift[3 * p + 1] * Ly;
-                vz += (float)shift[3 * p + 2] * Lz;
-            }
-            r = sqrtf(vx * vx + vy * vy + vz * vz);
-        }
-        int my_r = 0, my_a = 0;
-#pragma unroll
-        for (int s = 0; s < kMaxSpecies; ++s) {
-            const unsigned long long mr = ballot(in_r && z == s);
-            const unsigned long long ma = ballot(in_a && z == s);
-            if (z == s) {
-                my_r = off_r[s] + rank_below(mr);
-                my_a = off_a[s] + rank_below(ma);
-            }
-            off_r[s] += __popcll(mr);
-            off_a[s] += __popcll(ma);
-        }
-        const float inv_r = r > 0.f ? 1.0f / r : 0.f;
-        if (in_r && my_r < kMaxR) {
-            H.rr[my_r] = r;
-            H.rfc[my_r] = cutoff_fc(r, P.pi_rc_r);
-            H.rzs[my_r] = z | ((p - b) << 8);
-            if (kBwd) {
-                rux[my_r] = vx * inv_r;
-                ruy[my_r] = vy * inv_r;
-                ruz[my_r] = vz * inv_r;
-                rdfc[my_r] = -0.5f * P.pi_rc_r * __sinf(P.pi_rc_r * r);
-            }
-        }
-        if (in_a && my_a < kMaxA) {
-            H.ax[my_a] = vx * inv_r;
-            H.ay[my_a] = vy * inv_r;
-            H.az[my_a] = vz * inv_r;
-            H.ar[my_a] = r;
-            H.afc[my_a] = cutoff_fc(r, P.pi_rc_a);
-            H.azs[my_a] = z | (my_r << 8);
-            if (kBwd) adfc[my_a] = -0.5f * P.pi_rc_a * __sinf(P.pi_rc_a * r);
-        }
-    }
-    wave_sync();
-    return true;
-}
+__device__ __forceinline__ float cutoff_fc(float r, float pi_rc) { return 0.5f * __cosf(pi_rc * r) + 0.5f; }
 
 __device__ __forceinline__ int species_pair(int s, int t, int ns) {
     if (s > t) { int u = s; s = t; t = u; }
@@ -200,8 +45,7 @@ __device__ __forceinline__ int species_pair(int s, int t, int ns) {
 __device__ __forceinline__ void tri_decode(int v, int c, int& j, int& k) {
     const float tc = (float)(2 * c - 1);
     int jj = (int)((tc - sqrtf(fmaxf(tc * tc - 8.0f * (float)v, 0.f))) * 0.5f);
-    if (jj < 0) jj = 0;
-    if (jj > c - 2) jj = c - 2;
+    jj = max(0, min(jj, c - 2));
     while (jj > 0 && (jj * (2 * c - jj - 1)) / 2 > v) --jj;
     while (jj + 1 <= c - 2 && ((jj + 1) * (2 * c - jj - 2)) / 2 <= v) ++jj;
     j = jj;
@@ -219,194 +63,298 @@ __device__ __forceinline__ void store_out<float>(float* p, float v) { *p = v; }
 template <>
 __device__ __forceinline__ void store_out<uint16_t>(uint16_t* p, float v) { *p = f32_to_bf16(v); }
 
+// Row slots of one atom, held in registers (slot = lane + 64 q).
+struct Row {
+    float vx[kQ], vy[kQ], vz[kQ], r2[kQ];
+    int z[kQ];
+    bool in_r[kQ], in_a[kQ];
+    int b, len;
+};
+
+// Load the row and classify every slot.  Returns false (and flags) if the
+// row is longer than the kernels support.
+__device__ __forceinline__ bool load_row(Row& R, const AevConst& P, int i, const float* __restrict__ pos,
+                                         const int32_t* __restrict__ species, const BoxConst& bx,
+                                         const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                         const int8_t* __restrict__ shift, unsigned* flags) {
+    const int l = lane_id();
+    const int b = row_ptr[i], e = row_ptr[i + 1];
+    R.b = b;
+    R.len = e - b;
+    if (R.len > kMaxR) {
+        if (l == 0) set_flag(flags, NNP_FLAG_ROW);
+        return false;
+    }
+    const float xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    int j[kQ];
+    float sx[kQ], sy[kQ], sz[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int p = b + l + kWave * q;
+        j[q] = -1;
+        sx[q] = sy[q] = sz[q] = 0.f;
+        if (p < e) {
+            j[q] = col[p];
+            if (bx.periodic) {
+                sx[q] = (float)shift[3 * p];
+                sy[q] = (float)shift[3 * p + 1];
+                sz[q] = (float)shift[3 * p + 2];
+            }
+        }
+    }
+    const float rc_r2 = P.rc_r * P.rc_r, rc_a2 = P.rc_a * P.rc_a;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        R.in_r[q] = R.in_a[q] = false;
+        R.z[q] = 0;
+        R.vx[q] = R.vy[q] = R.vz[q] = R.r2[q] = 0.f;
+        if (j[q] >= 0) {
+            const int zz = species[j[q]];
+            float vx = pos[3 * j[q]] - xi, vy = pos[3 * j[q] + 1] - yi, vz = pos[3 * j[q] + 2] - zi;
+            vx += sx[q] * bx.L[0];
+            vy += sy[q] * bx.L[1];
+            vz += sz[q] * bx.L[2];
+            const float r2 = vx * vx + vy * vy + vz * vz;
+            R.vx[q] = vx;
+            R.vy[q] = vy;
+            R.vz[q] = vz;
+            R.r2[q] = r2;
+            if (zz < 0 || zz >= P.ns) {
+                set_flag(flags, NNP_FLAG_SPECIES);
+            } else {
+                R.z[q] = zz;
+                R.in_r[q] = r2 < rc_r2;
+                R.in_a[q] = R.in_r[q] && r2 < rc_a2;
+            }
+        }
+    }
+    return true;
+}
+
+// Stable positions of the slots in species-grouped lists (radial and angular).
+// seg_r / seg_a receive the species offsets (ns + 1 entries).  Returns false if
+// more than kMaxA neighbours fall inside the angular cutoff.
+__device__ __forceinline__ bool group_species(const Row& R, int ns, int* pos_r, int* pos_a, int* seg_r,
+                                              int* seg_a, unsigned* flags) {
+    const int l = lane_id();
+    const int nq = (R.len + kWave - 1) / kWave;
+    int off_r = 0, off_a = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) pos_r[q] = pos_a[q] = -1;
+    for (int s = 0; s < ns; ++s) {
+        if (l == 0) {
+            seg_r[s] = off_r;
+            seg_a[s] = off_a;
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            if (q < nq) {
+                const bool is = R.z[q] == s;
+                const unsigned long long mr = ballot(R.in_r[q] && is);
+                const unsigned long long ma = ballot(R.in_a[q] && is);
+                if (R.in_r[q] && is) pos_r[q] = off_r + rank_below(mr);
+                if (R.in_a[q] && is) pos_a[q] = off_a + rank_below(ma);
+                off_r += __popcll(mr);
+                off_a += __popcll(ma);
+            }
+        }
+    }
+    if (l == 0) {
+        seg_r[ns] = off_r;
+        seg_a[ns] = off_a;
+    }
+    if (off_a > kMaxA) {
+        if (l == 0) set_flag(flags, NNP_FLAG_ROW);
+        return false;
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------- forward
 
+struct FwdLds {
+    float rr[kMaxR];           // radial list: r, fc (species-grouped)
+    float rfc[kMaxR];
+    float4 au[kMaxA];          // angular list: unit vector, r
+    float afc[kMaxA];
+    float f1[kWave][kNz];      // pair tile: 8 angle factors
+    float f2[kWave][kNa];      // pair tile: 4 radial factors times 2 fc fc
+    int seg_r[kMaxSpecies + 1];
+    int seg_a[kMaxSpecies + 1];
+};
+
 template <typename OutT>
-__global__ __launch_bounds__(kWavesFwd* kWave) void k_aev_fwd(
-    const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species,
-    const BoxConst bx, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const int8_t* __restrict__ shift, const int32_t* __restrict__ out_row, OutT* __restrict__ out,
-    unsigned* flags) {
-    __shared__ Hood hood[kWavesFwd];
-    __shared__ float pairs[kWavesFwd][kWave * kPairStride];
-    __shared__ int pstart[kWavesFwd][40];    // pair-segment prefix over species pairs
+__global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
+    const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int8_t* __restrict__ shift,
+    const int32_t* __restrict__ out_row, OutT* __restrict__ out, unsigned* flags) {
+    __shared__ FwdLds lds[kWaves];
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
-    const int i = blockIdx.x * kWavesFwd + w;
+    const int i = blockIdx.x * kWaves + w;
     if (i >= n) return;
-    Hood& H = hood[w];
+    FwdLds& S = lds[w];
     const int row = out_row ? out_row[i] : i;
     if (row < 0) return;   // atom without a grouped row (invalid species, flagged elsewhere)
     OutT* orow = out + (size_t)row * P.stride;
-    if (!build_hood<false>(H, P, i, pos, species, bx, row_ptr, col, shift, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, flags)) {
+    const int ns = P.ns;
+    Row R;
+    int pr_[kQ], pa_[kQ];
+    if (!load_row(R, P, i, pos, species, bx, row_ptr, col, shift, flags) ||
+        !group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, flags)) {
         for (int c = l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
         return;
     }
-    const int ns = P.ns;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if (pr_[q] >= 0) {
+            const float r = sqrtf(R.r2[q]);
+            S.rr[pr_[q]] = r;
+            S.rfc[pr_[q]] = cutoff_fc(r, P.pi_rc_r);
+            if (pa_[q] >= 0) {
+                const float inv = r > 0.f ? 1.f / r : 0.f;
+                S.au[pa_[q]] = make_float4(R.vx[q] * inv, R.vy[q] * inv, R.vz[q] * inv, r);
+                S.afc[pa_[q]] = cutoff_fc(r, P.pi_rc_a);
+            }
+        }
+    }
+    wave_sync();
     // ---- radial: lane = (k, q); species segments in order
     {
         const int k = l & 15, q = l >> 4;
         const float rk = P.shf_r[k];
         for (int s = 0; s < ns; ++s) {
-            const int sb = H.seg_r[s], se = H.seg_r[s + 1];
+            const int sb = S.seg_r[s], se = S.seg_r[s + 1];
             float acc = 0.f;
             for (int m = sb + q; m < se; m += 4) {
-                const float d = H.rr[m] - rk;
-                acc += __expf(-P.eta_r * d * d) * H.rfc[m];
+                const float d = S.rr[m] - rk;
+                acc += __expf(-P.eta_r * d * d) * S.rfc[m];
             }
             acc += shfl_xor(acc, 16);
             acc += shfl_xor(acc, 32);
             if (q == 0) store_out(orow + 16 * s + k, P.pr * acc);
         }
     }
-    // ---- angular
-    const int n_sp = ns * (ns + 1) / 2;
-    if (l == 0) {
-        int acc = 0, p = 0;
-        for (int s = 0; s < ns; ++s) {
-            const int cs = H.seg_a[s + 1] - H.seg_a[s];
-            for (int t = s; t < ns; ++t, ++p) {
-                const int ct = H.seg_a[t + 1] - H.seg_a[t];
-                pstart[w][p] = acc;
-                acc += (s == t) ? cs * (cs - 1) / 2 : cs * ct;
-            }
-        }
-        pstart[w][n_sp] = acc;
-    }
-    wave_sync();
-    const int total = pstart[w][n_sp];
-    float* T = pairs[w];
-    const int col_az = l & 31, half = l >> 5;
-    float acc = 0.f;
-    int p_cur = 0;
-    for (int u0 = 0;; u0 += kWave) {
-        const int nvalid = min(kWave, total - u0);
-        // phase 1: one pair per lane
-        if (l < nvalid) {
-            const int u = u0 + l;
-            int lo = 0, hi = n_sp;   // last segment p with pstart[p] <= u
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (pstart[w][mid] <= u) lo = mid; else hi = mid;
-            }
-            const int p = lo;
-            // species pair (s, t) of segment p
-            int s = 0, rem = p;
-            while (rem >= ns - s) { rem -= ns - s; ++s; }
-            const int t = s + rem;
-            const int v = u - pstart[w][p];
-            int ja, ka;
-            if (s == t) {
-                const int c = H.seg_a[s + 1] - H.seg_a[s];
-                tri_decode(v, c, ja, ka);
-                ja += H.seg_a[s];
-                ka += H.seg_a[s];
-            } else {
-                const int ct = H.seg_a[t + 1] - H.seg_a[t];
-                ja = H.seg_a[s] + v / ct;
-                ka = H.seg_a[t] + v % ct;
-            }
-            float c = H.ax[ja] * H.ax[ka] + H.ay[ja] * H.ay[ka] + H.az[ja] * H.az[ka];
-            c = fminf(1.f, fmaxf(-1.f, c));
-            const float uu = P.cs * c;
-            const float sq = sqrtf(1.f - uu * uu);
-            const float rbar = 0.5f * (H.ar[ja] + H.ar[ka]);
-            const float w2 = 2.f * H.afc[ja] * H.afc[ka];
-            float f2[kNa];
+    // ---- angular: one species-pair bin at a time
+    const int az = l & 31, half = l >> 5;
+    const int ca = az >> 3, cz = az & 7;
+    int p = 0;
+    for (int s = 0; s < ns; ++s) {
+        const int bs = S.seg_a[s], cs_ = S.seg_a[s + 1] - bs;
+        for (int t = s; t < ns; ++t, ++p) {
+            const int bt = S.seg_a[t], ct = S.seg_a[t + 1] - bt;
+            const int np_ = (s == t) ? cs_ * (cs_ - 1) / 2 : cs_ * ct;
+            float acc = 0.f;
+            for (int u0 = 0; u0 < np_; u0 += kWave) {
+                const int u = u0 + l;
+                if (u < np_) {
+                    int ja, ka;
+                    if (s == t) {
+                        tri_decode(u, cs_, ja, ka);
+                        ja += bs;
+                        ka += bs;
+                    } else {
+                        ja = bs + u / ct;
+                        ka = bt + u % ct;
+                    }
+                    const float4 A = S.au[ja], B = S.au[ka];
+                    float c = A.x * B.x + A.y * B.y + A.z * B.z;
+                    c = fminf(1.f, fmaxf(-1.f, c));
+                    const float uu = P.cs * c;
+                    const float sq = sqrtf(1.f - uu * uu);
+                    const float rbar = 0.5f * (A.w + B.w);
+                    const float w2 = 2.f * S.afc[ja] * S.afc[ka];
 #pragma unroll
-            for (int a = 0; a < kNa; ++a) {
-                const float d = rbar - P.shf_a[a];
-                f2[a] = w2 * __expf(-P.eta_a * d * d);
-            }
+                    for (int a = 0; a < kNa; ++a) {
+                        const float d = rbar - P.shf_a[a];
+                        S.f2[l][a] = w2 * __expf(-P.eta_a * d * d);
+                    }
 #pragma unroll
-            for (int z = 0; z < kNz; ++z) {
-                const float base = 0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]);
-                const float f1 = pow_zeta(base, P.zeta);
-#pragma unroll
-                for (int a = 0; a < kNa; ++a) T[l * kPairStride + 8 * a + z] = f1 * f2[a];
+                    for (int z = 0; z < kNz; ++z)
+                        S.f1[l][z] = pow_zeta(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), P.zeta);
+                }
+                wave_sync();
+                const int nv = min(kWave, np_ - u0);
+                const int h0 = (nv + 1) >> 1;
+                const int lo = half ? h0 : 0, hi = half ? nv : h0;
+                for (int m = lo; m < hi; ++m) acc += S.f1[m][cz] * S.f2[m][ca];
+                wave_sync();
             }
+            const float tot = acc + shfl_xor(acc, 32);
+            if (half == 0) store_out(orow + P.radial_dim + 32 * p + az, tot);
         }
-        wave_sync();
-        // phase 2: lanes = (a z) columns x 2 halves; walk the segments of this chunk
-        const int u1 = u0 + nvalid;
-        const bool last = u0 + kWave >= total;
-        while (p_cur < n_sp) {
-            const int sb = pstart[w][p_cur], se = pstart[w][p_cur + 1];
-            const int a0 = max(sb, u0) - u0, a1 = min(se, u1) - u0;
-            if (a1 > a0) {
-                const int mid = (a0 + a1 + 1) >> 1;
-                const int lo = half ? mid : a0, hi = half ? a1 : mid;
-                for (int m = lo; m < hi; ++m) acc += T[m * kPairStride + col_az];
-            }
-            if (se <= u1 || last) {
-                const float tot = acc + shfl_xor(acc, 32);
-                if (half == 0) store_out(orow + P.radial_dim + 32 * p_cur + col_az, tot);
-                acc = 0.f;
-                ++p_cur;
-            } else {
-                break;   // segment continues in the next chunk
-            }
-        }
-        wave_sync();
-        if (last) break;
     }
     for (int c = P.dim + l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
 }
 
 // ---------------------------------------------------------------- adjoint
 
-struct HoodB {
-    Hood H;
-    float rux[kMaxR], ruy[kMaxR], ruz[kMaxR], rdfc[kMaxR];
-    float adfc[kMaxA];
-    short loc[kMaxR];        // row slot -> radial list index (-1: none)
+struct BwdLds {
+    float g[1280];              // dE/dAEV row of the atom
+    float4 au[kMaxA];           // angular list: unit vector, r
+    float afc[kMaxA], adfc[kMaxA];
+    int azs[kMaxA];             // species | slot << 8
+    float pb[kWave][7];         // pair tile: contributions to the two edges
+    float ga[kMaxA][3];         // angular gradient per angular neighbour
+    unsigned char amap[kMaxR];  // slot -> angular index (255: none)
+    int seg_r[kMaxSpecies + 1];
+    int seg_a[kMaxSpecies + 1];
 };
 
-__global__ __launch_bounds__(kWavesBwd* kWave) void k_aev_bwd(
-    const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species,
-    const BoxConst bx, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const int8_t* __restrict__ shift, const int32_t* __restrict__ g_row, const float* __restrict__ g,
-    float* __restrict__ Gx, float* __restrict__ Gy, float* __restrict__ Gz, unsigned* flags) {
-    __shared__ HoodB hb[kWavesBwd];
-    __shared__ float gl[kWavesBwd][1280];
-    __shared__ float pb[kWavesBwd][kWave * 7];
+__global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
+    const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int8_t* __restrict__ shift,
+    const int32_t* __restrict__ g_row, const float* __restrict__ g, float* __restrict__ Gx, float* __restrict__ Gy,
+    float* __restrict__ Gz, unsigned* flags) {
+    __shared__ BwdLds lds[kWaves];
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
-    const int i = blockIdx.x * kWavesBwd + w;
+    const int i = blockIdx.x * kWaves + w;
     if (i >= n) return;
-    HoodB& B = hb[w];
-    Hood& H = B.H;
-    const int b = row_ptr[i], e = row_ptr[i + 1];
-    const bool ok = build_hood<true>(H, P, i, pos, species, bx, row_ptr, col, shift, B.rux, B.ruy, B.ruz,
-                                     B.rdfc, B.adfc, flags);
-    if (!ok) {
-        for (int p = b + l; p < e; p += kWave) Gx[p] = Gy[p] = Gz[p] = 0.f;
-        return;
-    }
+    BwdLds& S = lds[w];
+    const int ns = P.ns;
+    Row R;
+    int pr_[kQ], pa_[kQ];
     const int row = g_row ? g_row[i] : i;
-    if (row < 0) {
+    const bool ok = load_row(R, P, i, pos, species, bx, row_ptr, col, shift, flags) &&
+                    group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, flags) && row >= 0;
+    if (!ok) {
+        const int b = row_ptr[i], e = row_ptr[i + 1];
         for (int p = b + l; p < e; p += kWave) Gx[p] = Gy[p] = Gz[p] = 0.f;
         return;
     }
     const float* grow = g + (size_t)row * P.stride;
-    for (int c = l; c < P.dim; c += kWave) gl[w][c] = grow[c];
-    for (int c = l; c < e - b; c += kWave) B.loc[c] = -1;
-    wave_sync();
-    for (int m = l; m < H.n_r; m += kWave) B.loc[H.rzs[m] >> 8] = (short)m;
-    wave_sync();
-    const int n_r = H.n_r, n_a = H.n_a;
-    // ---- radial part, one neighbour per lane (up to 4 per lane)
-    float gx[4], gy[4], gz[4];
+    for (int c = l; c < P.dim; c += kWave) S.g[c] = grow[c];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) gx[q] = gy[q] = gz[q] = 0.f;
+    for (int q = 0; q < kQ; ++q) {
+        const int slot = l + kWave * q;
+        if (slot < R.len) S.amap[slot] = 255;
+    }
+    // angular list entries
+    float r_[kQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int m = l + q * kWave;
-        if (m < n_r) {
-            const float r = H.rr[m], fc = H.rfc[m], dfc = B.rdfc[m];
-            const int s = H.rzs[m] & 0xff;
-            const float* gs = &gl[w][16 * s];
+    for (int q = 0; q < kQ; ++q) {
+        r_[q] = sqrtf(R.r2[q]);
+        if (pa_[q] >= 0) {
+            const float r = r_[q];
+            const float inv = r > 0.f ? 1.f / r : 0.f;
+            S.au[pa_[q]] = make_float4(R.vx[q] * inv, R.vy[q] * inv, R.vz[q] * inv, r);
+            S.afc[pa_[q]] = cutoff_fc(r, P.pi_rc_a);
+            S.adfc[pa_[q]] = -0.5f * P.pi_rc_a * __sinf(P.pi_rc_a * r);
+            S.azs[pa_[q]] = R.z[q] | ((l + kWave * q) << 8);
+        }
+    }
+    wave_sync();
+    // ---- radial gradient by the lane holding the slot
+    float gx[kQ], gy[kQ], gz[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        gx[q] = gy[q] = gz[q] = 0.f;
+        if (R.in_r[q]) {
+            const float r = r_[q];
+            const float fc = cutoff_fc(r, P.pi_rc_r);
+            const float dfc = -0.5f * P.pi_rc_r * __sinf(P.pi_rc_r * r);
+            const float* gs = &S.g[16 * R.z[q]];
             float dEdr = 0.f;
 #pragma unroll
             for (int k = 0; k < kNr; ++k) {
@@ -415,35 +363,33 @@ __global__ __launch_bounds__(kWavesBwd* kWave) void k_aev_bwd(
                 dEdr += gs[k] * ek * (-2.f * P.eta_r * d * fc + dfc);
             }
             dEdr *= P.pr;
-            gx[q] = dEdr * B.rux[m];
-            gy[q] = dEdr * B.ruy[m];
-            gz[q] = dEdr * B.ruz[m];
+            const float inv = r > 0.f ? 1.f / r : 0.f;
+            gx[q] = dEdr * R.vx[q] * inv;
+            gy[q] = dEdr * R.vy[q] * inv;
+            gz[q] = dEdr * R.vz[q] * inv;
         }
     }
-    // ---- angular part: unordered pairs in triangle order over the angular list
-    const int ns = P.ns;
+    // ---- angular: unordered pairs in triangle order over the species-grouped list
+    const int n_a = S.seg_a[ns];
     const int total = n_a * (n_a - 1) / 2;
-    // per angular neighbour owned by this lane (lane m and m + 64 -> up to 2)
     float ax_[2] = {0.f, 0.f}, ay_[2] = {0.f, 0.f}, az_[2] = {0.f, 0.f};
     int jptr[2] = {0, 0};
-    float* PB = pb[w];
     for (int u0 = 0; u0 < total; u0 += kWave) {
         const int u = u0 + l;
         if (u < total) {
             int ja, ka;
             tri_decode(u, n_a, ja, ka);
-            const float uxj = H.ax[ja], uyj = H.ay[ja], uzj = H.az[ja];
-            const float uxk = H.ax[ka], uyk = H.ay[ka], uzk = H.az[ka];
-            float c = uxj * uxk + uyj * uyk + uzj * uzk;
+            const float4 A = S.au[ja], B = S.au[ka];
+            float c = A.x * B.x + A.y * B.y + A.z * B.z;
             c = fminf(1.f, fmaxf(-1.f, c));
             const float uu = P.cs * c;
             const float sq = sqrtf(1.f - uu * uu);
-            const float rj = H.ar[ja], rk = H.ar[ka];
+            const float rj = A.w, rk = B.w;
             const float rbar = 0.5f * (rj + rk);
-            const float fj = H.afc[ja], fk = H.afc[ka];
-            const float dfj = B.adfc[ja], dfk = B.adfc[ka];
-            const int p = species_pair(H.azs[ja] & 0xff, H.azs[ka] & 0xff, ns);
-            const float* gp = &gl[w][P.radial_dim + 32 * p];
+            const float fj = S.afc[ja], fk = S.afc[ka];
+            const float dfj = S.adfc[ja], dfk = S.adfc[ka];
+            const int pp = species_pair(S.azs[ja] & 0xff, S.azs[ka] & 0xff, ns);
+            const float* gp = &S.g[P.radial_dim + 32 * pp];
             float F2[kNa], dF2[kNa];
 #pragma unroll
             for (int a = 0; a < kNa; ++a) {
@@ -451,8 +397,8 @@ __global__ __launch_bounds__(kWavesBwd* kWave) void k_aev_bwd(
                 F2[a] = __expf(-P.eta_a * d * d);
                 dF2[a] = -2.f * P.eta_a * d * F2[a];
             }
-            float Rz[kNa] = {0.f, 0.f, 0.f, 0.f};   // sum_z g_az F1_z
-            float sum_c = 0.f, S = 0.f;
+            float Rz[kNa] = {0.f, 0.f, 0.f, 0.f};
+            float sum_c = 0.f, Ssum = 0.f;
             const float inv_sq = 1.f / sq;
 #pragma unroll
             for (int z = 0; z < kNz; ++z) {
@@ -472,7 +418,7 @@ __global__ __launch_bounds__(kWavesBwd* kWave) void k_aev_bwd(
                     Rz[a] += gaz * F1;
                 }
                 sum_c += Q * dF1 * dwdu;
-                S += Q * F1;
+                Ssum += Q * F1;
             }
             float sum_r = 0.f;
 #pragma unroll
@@ -480,82 +426,72 @@ __global__ __launch_bounds__(kWavesBwd* kWave) void k_aev_bwd(
             const float ff = 2.f * fj * fk;
             const float dEdc = ff * sum_c * P.cs;
             const float dEdrbar = ff * sum_r;
-            const float sj = 0.5f * dEdrbar + 2.f * fk * S * dfj;
-            const float sk = 0.5f * dEdrbar + 2.f * fj * S * dfk;
+            const float sj = 0.5f * dEdrbar + 2.f * fk * Ssum * dfj;
+            const float sk = 0.5f * dEdrbar + 2.f * fj * Ssum * dfk;
             const float ij = rj > 0.f ? 1.f / rj : 0.f;
             const float ik = rk > 0.f ? 1.f / rk : 0.f;
-            PB[l * 7 + 0] = dEdc * (uxk - c * uxj) * ij + sj * uxj;
-            PB[l * 7 + 1] = dEdc * (uyk - c * uyj) * ij + sj * uyj;
-            PB[l * 7 + 2] = dEdc * (uzk - c * uzj) * ij + sj * uzj;
-            PB[l * 7 + 3] = dEdc * (uxj - c * uxk) * ik + sk * uxk;
-            PB[l * 7 + 4] = dEdc * (uyj - c * uyk) * ik + sk * uyk;
-            PB[l * 7 + 5] = dEdc * (uzj - c * uzk) * ik + sk * uzk;
+            S.pb[l][0] = dEdc * (B.x - c * A.x) * ij + sj * A.x;
+            S.pb[l][1] = dEdc * (B.y - c * A.y) * ij + sj * A.y;
+            S.pb[l][2] = dEdc * (B.z - c * A.z) * ij + sj * A.z;
+            S.pb[l][3] = dEdc * (A.x - c * B.x) * ik + sk * B.x;
+            S.pb[l][4] = dEdc * (A.y - c * B.y) * ik + sk * B.y;
+            S.pb[l][5] = dEdc * (A.z - c * B.z) * ik + sk * B.z;
         }
         wave_sync();
-        // gather per angular neighbour, fixed order: first-element pairs, then second-element pairs
+        // gather per angular neighbour, fixed order: pairs (m, k > m) then pairs (j < m, m)
         const int u1 = min(u0 + kWave, total);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int m = l + q * kWave;
             if (m < n_a) {
-                // pairs (m, k>m): contiguous [tri(m), tri(m+1))
                 const int t0 = m * (2 * n_a - m - 1) / 2, t1 = t0 + (n_a - m - 1);
                 for (int t = max(t0, u0); t < min(t1, u1); ++t) {
-                    ax_[q] += PB[(t - u0) * 7 + 0];
-                    ay_[q] += PB[(t - u0) * 7 + 1];
-                    az_[q] += PB[(t - u0) * 7 + 2];
+                    ax_[q] += S.pb[t - u0][0];
+                    ay_[q] += S.pb[t - u0][1];
+                    az_[q] += S.pb[t - u0][2];
                 }
-                // pairs (j<m, m): u_j = tri(j) + m - j - 1, increasing in j
                 while (jptr[q] < m) {
                     const int jj = jptr[q];
                     const int t = jj * (2 * n_a - jj - 1) / 2 + (m - jj - 1);
                     if (t >= u1) break;
-                    ax_[q] += PB[(t - u0) * 7 + 3];
-                    ay_[q] += PB[(t - u0) * 7 + 4];
-                    az_[q] += PB[(t - u0) * 7 + 5];
+                    ax_[q] += S.pb[t - u0][3];
+                    ay_[q] += S.pb[t - u0][4];
+                    az_[q] += S.pb[t - u0][5];
                     ++jptr[q];
                 }
             }
         }
         wave_sync();
     }
-    // ---- combine radial and angular parts and write one value per row slot
-    // angular neighbours add to their radial entries: stage through LDS (reuse pair buffer)
-    float* GA = pb[w];   // [kMaxA][3] fits in kWave*7 floats (448 >= 3*96 = 288)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int m = l + q * kWave;
         if (m < n_a) {
-            GA[3 * m] = ax_[q];
-            GA[3 * m + 1] = ay_[q];
-            GA[3 * m + 2] = az_[q];
+            S.ga[m][0] = ax_[q];
+            S.ga[m][1] = ay_[q];
+            S.ga[m][2] = az_[q];
+            S.amap[S.azs[m] >> 8] = (unsigned char)m;
         }
     }
     wave_sync();
-    // radial entry -> angular entry map is implicit: angular entries store their radial index
-    __shared__ short amap[kWavesBwd][kMaxR];
-    for (int m = l; m < n_r; m += kWave) amap[w][m] = -1;
-    wave_sync();
-    for (int m = l; m < n_a; m += kWave) amap[w][H.azs[m] >> 8] = (short)m;
-    wave_sync();
+    // ---- one value per row slot: radial part + angular part (zero outside Rc_R)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int m = l + q * kWave;
-        if (m < n_r) {
-            const int am = amap[w][m];
-            if (am >= 0) {
-                gx[q] += GA[3 * am];
-                gy[q] += GA[3 * am + 1];
-                gz[q] += GA[3 * am + 2];
+    for (int q = 0; q < kQ; ++q) {
+        const int slot = l + kWave * q;
+        if (slot < R.len) {
+            const int am = S.amap[slot];
+            float x = gx[q], y = gy[q], z = gz[q];
+            if (am != 255) {
+                x += S.ga[am][0];
+                y += S.ga[am][1];
+                z += S.ga[am][2];
             }
-            const int slot = b + (H.rzs[m] >> 8);
-            Gx[slot] = gx[q];
-            Gy[slot] = gy[q];
-            Gz[slot] = gz[q];
+            const int p = R.b + slot;
+            Gx[p] = x;
+            Gy[p] = y;
+            Gz[p] = z;
         }
     }
-    for (int p = b + l; p < e; p += kWave)
-        if (B.loc[p - b] < 0) Gx[p] = Gy[p] = Gz[p] = 0.f;
 }
 
 }  // namespace
@@ -564,13 +500,13 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
                           const nnp_nlist* nl, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
                           hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int grid = ceil_div(n, kWavesFwd);
+    const int grid = ceil_div(n, kWaves);
     if (bf16)
-        k_aev_fwd<uint16_t><<<grid, kWavesFwd * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col,
-                                                               nl->shift, out_row, (uint16_t*)out, flags);
+        k_aev_fwd<uint16_t><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift,
+                                                            out_row, (uint16_t*)out, flags);
     else
-        k_aev_fwd<float><<<grid, kWavesFwd * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col,
-                                                            nl->shift, out_row, (float*)out, flags);
+        k_aev_fwd<float><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift,
+                                                         out_row, (float*)out, flags);
     return hipGetLastError();
 }
 
@@ -578,9 +514,9 @@ hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int3
                           const nnp_nlist* nl, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
                           unsigned* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int grid = ceil_div(n, kWavesBwd);
-    k_aev_bwd<<<grid, kWavesBwd * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift, g_row,
-                                                g, Gx, Gy, Gz, flags);
+    const int grid = ceil_div(n, kWaves);
+    k_aev_bwd<<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift, g_row, g, Gx,
+                                             Gy, Gz, flags);
     return hipGetLastError();
 }
 

@@ -343,6 +343,47 @@ __global__ __launch_bounds__(kThreads) void k_energy(int n_mol, const int32_t* m
     if (threadIdx.x == 0) e_mol[m] = part[0];
 }
 
+// Large single structure: fixed 4096-atom chunks summed per block, then the
+// chunk sums in order by one block (deterministic, two fixed trees).
+constexpr int kChunk = 4096;
+
+__global__ __launch_bounds__(1024) void k_energy_chunks(int n, const int32_t* prow, const int32_t* species,
+                                                       const SelfE se, const float* E_at, double* part,
+                                                       float* e_atom) {
+    __shared__ double red[1024];
+    const int base = blockIdx.x * kChunk;
+    double acc = 0.0;
+    for (int q = 0; q < kChunk / 1024; ++q) {
+        const int a = base + q * 1024 + threadIdx.x;
+        if (a < n) {
+            const bool ok = prow[a] >= 0;
+            const double v = ok ? (double)E_at[a] + se.e[species[a]] : 0.0;
+            if (e_atom) e_atom[a] = (float)v;
+            acc += v;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 512; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_energy_final(int nparts, const double* part, double* e_mol) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += 256) acc += part[q];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e_mol[0] = red[0];
+}
+
 __global__ void k_mol_ranges2(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end, unsigned* flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -475,6 +516,15 @@ hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool 
 hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
                          int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_at, double* e_mol,
                          float* e_atom, unsigned* flags, hipStream_t s) {
+    if (n_mol == 1 && n > 2 * kChunk) {
+        // mol must still be validated: a single structure means every mol entry is 0
+        if (mol) k_mol_ranges2<<<ceil_div(n, 256), 256, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
+        const int nparts = ceil_div(n, kChunk);
+        double* part = (double*)W.bcount;   // >= nparts doubles: bcount holds 8 ints per 1024 atoms
+        k_energy_chunks<<<nparts, 1024, 0, s>>>(n, W.prow, species, se, E_at, part, e_atom);
+        k_energy_final<<<1, 256, 0, s>>>(nparts, part, e_mol);
+        return hipGetLastError();
+    }
     if (n_mol > 0) {
         k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mstart, n_mol, 0);
         k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mend, n_mol, 0);

@@ -27,6 +27,8 @@ struct Grid {
     int ns[3];          // stencil width per dimension (min(3, nc))
     double L[3];        // box sides (float32 widened)
     double inv_cs[3];   // nc / L
+    float Lf[3];        // box sides
+    float inv_Lf[3];    // 1 / L (float32, fast path only)
 };
 
 struct PairOut {
@@ -35,7 +37,7 @@ struct PairOut {
 };
 
 // Exact predicate.  No contraction: each +, -, *, / is rounded on its own.
-__device__ __forceinline__ PairOut pair_predicate(float3 xi, float3 xj, const Grid g, double r2) {
+__device__ __forceinline__ PairOut pair_predicate_exact(float3 xi, float3 xj, const Grid& g, double r2) {
 #pragma clang fp contract(off)
     double d[3], n[3];
     const double a[3] = {(double)xi.x, (double)xi.y, (double)xi.z};
@@ -64,6 +66,53 @@ __device__ __forceinline__ PairOut pair_predicate(float3 xi, float3 xj, const Gr
                    n[2] > 127.0))
         o.packed_shift = -1;   // caller flags it
     return o;
+}
+
+// Same decision, float32 first.  With M the largest coordinate or box
+// magnitude involved, every float32 component of d is within 4 ulp(M) of the
+// float64 one, so |d2_f32 - d2_exact| < 2 r e + e^2 with e = 1e-5 M, which
+// is 20x that bound.  Outside that band around r^2 the float32 decision (and,
+// for kept pairs, the image shift, since then |d0/L + n| < 1/2 - 1e-6) equals
+// the exact one; inside the band the exact float64 predicate decides.
+__device__ __forceinline__ PairOut pair_predicate(float3 xi, float3 xj, const Grid& g, double r2, float rf) {
+    float d[3], n[3];
+    const float a[3] = {xi.x, xi.y, xi.z};
+    const float b[3] = {xj.x, xj.y, xj.z};
+    float M = 1.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float d0 = b[k] - a[k];
+        M = fmaxf(M, fmaxf(fabsf(a[k]), fabsf(b[k])));
+        if (g.periodic) {
+            n[k] = -rintf(d0 * g.inv_Lf[k]);
+            d[k] = d0 + n[k] * g.Lf[k];
+            M = fmaxf(M, g.Lf[k]);
+        } else {
+            n[k] = 0.f;
+            d[k] = d0;
+        }
+    }
+    const float d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const float e = 1e-5f * M;
+    const float band = e * (2.0f * rf + e);
+    const float r2f = rf * rf;
+    PairOut o;
+    if (d2 > r2f + band) {
+        o.keep = false;
+        o.packed_shift = 0;
+        return o;
+    }
+    if (d2 < r2f - band) {
+        o.keep = true;
+        if (fabsf(n[0]) > 127.f || fabsf(n[1]) > 127.f || fabsf(n[2]) > 127.f) {
+            o.packed_shift = -1;
+        } else {
+            const int ix = (int)n[0], iy = (int)n[1], iz = (int)n[2];
+            o.packed_shift = (ix & 0xff) | ((iy & 0xff) << 8) | ((iz & 0xff) << 16);
+        }
+        return o;
+    }
+    return pair_predicate_exact(xi, xj, g, r2);
 }
 
 __device__ __forceinline__ float3 load_pos(const float* pos, int i) {
@@ -147,6 +196,7 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     if (i >= n) return;
     const float3 xi = load_pos(pos, i);
     const int mi = mol ? mol[i] : 0;
+    const float rf = (float)sqrt(r2);
     int n_src = 0;
     if (g.periodic) {
         const int ci = cell_of[i];
@@ -219,7 +269,7 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
             j = g.periodic ? cell_atoms[idx] : idx;
             if (j != i && (!mol || mol[j] == mi)) {
                 const float3 xj = load_pos(pos, j);
-                PairOut o = pair_predicate(xi, xj, g, r2);
+                PairOut o = pair_predicate(xi, xj, g, r2, rf);
                 keep = o.keep;
                 sh = o.packed_shift;
                 if (keep && sh == -1) {
@@ -312,6 +362,8 @@ nnp_status make_grid(const float* box_host, float r_list, Grid* g) {
         g->ns[k] = 1;
         g->L[k] = 1.0;
         g->inv_cs[k] = 0.0;
+        g->Lf[k] = 1.0f;
+        g->inv_Lf[k] = 1.0f;
     }
     if (!box_host) return NNP_OK;
     const double r = (double)r_list;
@@ -326,6 +378,8 @@ nnp_status make_grid(const float* box_host, float r_list, Grid* g) {
         g->ns[k] = nc >= 3 ? 3 : (int)nc;
         g->L[k] = L;
         g->inv_cs[k] = (double)nc / L;
+        g->Lf[k] = box_host[k];
+        g->inv_Lf[k] = (float)(1.0 / L);
     }
     return NNP_OK;
 }

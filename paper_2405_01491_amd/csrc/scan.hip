@@ -86,6 +86,41 @@ __global__ __launch_bounds__(kScanThreads) void k_block_scan(const int32_t* in, 
     }
 }
 
+// Small inputs: one block of 1024 threads, 8 items per thread.
+constexpr int kSmallThreads = 1024, kSmallItems = 8;
+
+__global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int32_t* in, int n, int32_t* out,
+                                                              int64_t* total) {
+    __shared__ long long wsum[kSmallThreads / kWave];
+    const int t = threadIdx.x, w = t / kWave;
+    const int base = t * kSmallItems;
+    int32_t v[kSmallItems];
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    long long inc = wave_inclusive(s);
+    if (lane_id() == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    long long off = 0, all = 0;
+    for (int q = 0; q < kSmallThreads / kWave; ++q) {
+        if (q < w) off += wsum[q];
+        all += wsum[q];
+    }
+    long long ex = off + inc - s;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+        if (base + k < n) out[base + k] = ex > 0x7fffffffLL ? 0x7fffffff : (int32_t)ex;
+        ex += v[k];
+    }
+    if (t == 0) {
+        *total = all;
+        out[n] = all > 0x7fffffffLL ? 0x7fffffff : (int32_t)all;
+    }
+}
+
 }  // namespace
 
 size_t scan_tmp_elems(int n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanBlock) + 1; }
@@ -93,6 +128,10 @@ size_t scan_tmp_elems(int n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanBlock
 // out has n + 1 entries; out[n] = total (saturated to int32); *total_out (device) = exact total.
 hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
                                      int64_t* block_tmp, hipStream_t s) {
+    if (n <= kSmallThreads * kSmallItems) {
+        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, n, out, total_out);
+        return hipGetLastError();
+    }
     const int nb = ceil_div(n > 0 ? n : 1, kScanBlock);
     k_block_sums<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp);
     k_scan_sums<<<1, kScanThreads, 0, s>>>(block_tmp, nb, total_out, out + n);
