@@ -137,6 +137,10 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (reference for FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with the measured HBM traffic of the dominant stage (bytes per launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the spatial decomposition "
@@ -144,6 +148,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        dev = torch.device("cuda", 0)
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4, "launches": 5}))
+        return
     import synthetic
     import paper_2405_01491_amd as nnp
     from paper_2405_01491_amd import md as nmd
@@ -227,6 +241,13 @@ def main():
                 "frac": achieved / MI355X_PEAK["hbm_GBs"], "traffic": None, "stage": dom,
                 "algorithmic_per_launch": "%.4g B" % byt}
     roof["avg_launch_ms"] = avg_ms
+    if args.traffic:
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        key = "%s_cfg%d_%s" % (dom, args.config, precision)
+        if key in tr:
+            roof["traffic"] = tr[key]["bytes_per_launch"]
+            roof["traffic_source"] = tr[key]["source"]
 
     result = {
         "metric": "energy+force atom-steps/s at 1 MI355X (FP32 vs BF16-MLP); p50/p99 request latency",

@@ -131,6 +131,13 @@ void nnp_model_destroy(nnp_model* model);
 /* Switch the precision form used by later nnp_energy_forces calls. */
 nnp_status nnp_model_set_precision(nnp_model* model, nnp_precision precision);
 const char* nnp_status_str(nnp_status status);
+/* 1 if the species networks run as one fused kernel per tile (forward, head
+ * and adjoint; available for the 1008-256-192-160-1 shape), 0 if they run
+ * as one GEMM kernel per layer. */
+int32_t nnp_model_fused_mlp(const nnp_model* model);
+/* Allow (1) or forbid (0) the fused kernel; forbidding selects the per-layer
+ * GEMM path (both compute the same function; used to compare them). */
+nnp_status nnp_model_set_fused_mlp(nnp_model* model, int32_t allow);
 /* Number of AEV features (1008 for ANI-2x) and padded row stride used by
  * nnp_aev (1024). */
 int32_t nnp_aev_dim(const nnp_model* model);

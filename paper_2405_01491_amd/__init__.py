@@ -99,6 +99,13 @@ class Model:
         check(lib().nnp_model_set_precision(self.handle, _PRECISIONS[precision]), "nnp_model_set_precision")
         self.precision = precision
 
+    @property
+    def fused_mlp(self):
+        return bool(lib().nnp_model_fused_mlp(self.handle))
+
+    def set_fused_mlp(self, allow):
+        check(lib().nnp_model_set_fused_mlp(self.handle, 1 if allow else 0), "nnp_model_set_fused_mlp")
+
     def workspace(self, nbytes):
         """A device byte buffer of at least nbytes, reused across calls on the
         same stream (kernels on one stream run in order)."""

@@ -25,6 +25,8 @@ SIGNATURES = {
     "nnp_model_destroy": (None, [c_void_p]),
     "nnp_model_set_precision": (ctypes.c_int, [c_void_p, ctypes.c_int]),
     "nnp_aev_dim": (ctypes.c_int32, [c_void_p]),
+    "nnp_model_fused_mlp": (ctypes.c_int32, [c_void_p]),
+    "nnp_model_set_fused_mlp": (ctypes.c_int, [c_void_p, ctypes.c_int32]),
     "nnp_check": (ctypes.c_int, [c_void_p, c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "nnp_neighbors_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, c_void_p, ctypes.c_float]),
     "nnp_neighbors": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.c_int32, c_void_p,

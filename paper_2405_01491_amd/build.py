@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnnp.so")
 
-SOURCES = ["scan.hip", "neighbors.hip", "aev.hip", "mlp.hip", "forces.hip", "serve.cpp", "api.cpp"]
+SOURCES = ["scan.hip", "neighbors.hip", "aev.hip", "mlp.hip", "mlp_fused.hip", "forces.hip", "serve.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -40,14 +40,20 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = list(SOURCES)
+    missing = [s for s in srcs if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise RuntimeError("missing sources: %s" % missing)
+    extra = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")) and f not in srcs)
+    if extra:
+        raise RuntimeError("sources not in the build list: %s" % extra)
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         results = list(ex.map(_compile, srcs))
     for _obj, msgs in results:
         if verbose and msgs.strip():
             print(msgs)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp] + [o for o, _ in results]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

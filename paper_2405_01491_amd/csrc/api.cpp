@@ -19,13 +19,7 @@ namespace {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-uint16_t host_bf16(float f) {
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+uint16_t host_bf16(float f) { return nnp::host_bf16_bits(f); }
 
 std::mutex g_stage_mutex;
 
@@ -106,8 +100,8 @@ struct EfWs {
     MlpWs mw;
     int32_t* mstart;
     int32_t* mend;
-    void* aev;          // [rows_max][stride] fp32-sized (aliased by g)
-    float* g;
+    void* aev;          // [rows_max][stride] float32-sized (bf16 rows use the first half)
+    float* g;           // [rows_max][stride] float32 dE/dAEV (its own buffer: tiles run concurrently)
     float* h[kMaxLayers];
     float* E_row;
     float* E_at;        // network energies in atom order
@@ -134,7 +128,7 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.mstart = (int32_t*)take(sizeof(int32_t) * (nn + 1));
     W.mend = (int32_t*)take(sizeof(int32_t) * (nn + 1));
     W.aev = take(sizeof(float) * (size_t)rows_max * m->aev.stride);
-    W.g = (float*)W.aev;
+    W.g = (float*)take(sizeof(float) * (size_t)rows_max * m->aev.stride);
     for (int l = 0; l + 1 < m->n_layers; ++l) W.h[l] = (float*)take(sizeof(float) * (size_t)rows_max * m->wpad[l + 1]);
     W.E_row = (float*)take(sizeof(float) * rows_max);
     W.E_at = (float*)take(sizeof(float) * nn);
@@ -164,6 +158,14 @@ nnp_status hip_status(hipError_t e) { return e == hipSuccess ? NNP_OK : NNP_E_HI
 }  // namespace
 
 namespace nnp {
+
+uint16_t host_bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev, int64_t* total_host) {
     std::lock_guard<std::mutex> lock(g_stage_mutex);
@@ -206,14 +208,20 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     if (n > 0) {
         prof_begin(m, NNP_STAGE_GROUP, s);
         e = launch_species_group(m, n, species, W.mw, flags, s);
-        if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, bf, s);
+        // the per-layer GEMMs read padding rows; the fused kernel keeps them to their own rows
+        if (e == hipSuccess && !(m->fused && !m->force_unfused))
+            e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, bf, s);
         prof_end(m, NNP_STAGE_GROUP, s);
         prof_begin(m, NNP_STAGE_AEV, s);
         if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.aev, bf, flags, s);
         prof_end(m, NNP_STAGE_AEV, s);
         prof_begin(m, NNP_STAGE_MLP, s);
-        if (e == hipSuccess)
-            e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, W.E_at, s);
+        if (e == hipSuccess) {
+            if (m->fused && !m->force_unfused)
+                e = launch_mlp_fused(m, W.mw, W.aev, forces ? W.g : nullptr, W.E_row, W.E_at, n, s);
+            else
+                e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, W.E_at, s);
+        }
         prof_end(m, NNP_STAGE_MLP, s);
     }
     prof_begin(m, NNP_STAGE_ENERGY, s);
@@ -369,6 +377,28 @@ nnp_status nnp_model_create(const nnp_aev_params* a, const nnp_mlp_params* p, nn
         }
         m->ptrs.head_w[s] = (const float*)(d + offH[s]);
     }
+    m->fused = fused_mlp_shape(m->widths, L, ns);
+    if (m->fused) {
+        const size_t per = pack_fused_species(nullptr, false, nullptr, nullptr, nullptr, dim, m->widths[3]);
+        const size_t perb = pack_fused_species(nullptr, true, nullptr, nullptr, nullptr, dim, m->widths[3]);
+        std::vector<char> hp(per * ns + perb * ns);
+        for (int s = 0; s < ns; ++s) {
+            const float* W1 = p->W[s * L + 0];
+            const float* W2 = p->W[s * L + 1];
+            const float* W3 = p->W[s * L + 2];
+            pack_fused_species(hp.data() + per * s, false, W1, W2, W3, dim, m->widths[3]);
+            pack_fused_species(hp.data() + per * ns + perb * s, true, W1, W2, W3, dim, m->widths[3]);
+        }
+        if (hipMalloc(&m->fused_dev, hp.size()) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
+        if (hipMemcpy(m->fused_dev, hp.data(), hp.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            nnp_model_destroy(m);
+            return NNP_E_HIP;
+        }
+        for (int s = 0; s < ns; ++s) {
+            m->fused_fp32[s] = (char*)m->fused_dev + per * s;
+            m->fused_bf16[s] = (char*)m->fused_dev + per * ns + perb * s;
+        }
+    }
     if (hipMalloc(&m->flags, 256) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
     if (hipMemset(m->flags, 0, 256) != hipSuccess) { nnp_model_destroy(m); return NNP_E_HIP; }
     if (hipHostMalloc(&m->host_stage, 256, 0) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
@@ -379,6 +409,7 @@ nnp_status nnp_model_create(const nnp_aev_params* a, const nnp_mlp_params* p, nn
 void nnp_model_destroy(nnp_model* m) {
     if (!m) return;
     if (m->dev_weights) (void)hipFree(m->dev_weights);
+    if (m->fused_dev) (void)hipFree(m->fused_dev);
     if (m->flags) (void)hipFree(m->flags);
     if (m->host_stage) (void)hipHostFree(m->host_stage);
     delete m->prof;
@@ -392,6 +423,14 @@ nnp_status nnp_model_set_precision(nnp_model* m, nnp_precision p) {
 }
 
 int32_t nnp_aev_dim(const nnp_model* m) { return m ? m->aev.dim : 0; }
+
+int32_t nnp_model_fused_mlp(const nnp_model* m) { return m && m->fused && !m->force_unfused ? 1 : 0; }
+
+nnp_status nnp_model_set_fused_mlp(nnp_model* m, int32_t allow) {
+    if (!m) return NNP_E_ARG;
+    m->force_unfused = allow == 0;
+    return NNP_OK;
+}
 
 nnp_status nnp_check(nnp_model* m, void* stream, uint32_t* flags) {
     if (!m) return NNP_E_ARG;
@@ -453,10 +492,19 @@ nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float*
     if (n == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
     const EfWs W = ef_layout(m, n, 0, (char*)ws);
+    const bool fused = m->fused && !m->force_unfused;
+    const bool bfa = fused && m->precision == NNP_BF16_MLP;   // the fused BF16 kernel reads bf16 rows
+    void* rows = W.aev;
     hipError_t e = launch_species_group(m, n, species, W.mw, m->flags, s);
-    if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, false, s);
-    if (e == hipSuccess) e = launch_permute_rows(true, W.mw.prow, n, m->aev.stride, aev_in, (float*)W.aev, s);
-    if (e == hipSuccess) e = launch_mlp(m, W.mw, W.aev, false, W.h, daev_out ? W.g : nullptr, W.E_row, nullptr, s);
+    if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, rows, bfa, s);
+    if (e == hipSuccess) {
+        if (bfa) e = launch_permute_rows_bf16(W.mw.prow, n, m->aev.stride, aev_in, (uint16_t*)rows, s);
+        else e = launch_permute_rows(true, W.mw.prow, n, m->aev.stride, aev_in, (float*)W.aev, s);
+    }
+    if (e == hipSuccess) {
+        if (fused) e = launch_mlp_fused(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, s);
+        else e = launch_mlp(m, W.mw, W.aev, false, W.h, daev_out ? W.g : nullptr, W.E_row, nullptr, s);
+    }
     if (e == hipSuccess) e = launch_gather_e(W.mw.prow, n, species, self_e(m), W.E_row, e_atom, s);
     if (e == hipSuccess && daev_out) e = launch_permute_rows(false, W.mw.prow, n, m->aev.stride, W.g, daev_out, s);
     return hip_status(e);

@@ -106,6 +106,69 @@ __global__ __launch_bounds__(256) void k_species_rank(const int32_t* species, in
     }
 }
 
+// Small systems: the whole stable grouping in one block of 1024 threads
+// (counts, padded offsets, ranks in ascending atom order).
+constexpr int kSmallGroup = 16384;
+
+__global__ __launch_bounds__(1024) void k_group_small(const int32_t* species, int n, int ns, int32_t* meta,
+                                                     int32_t* prow, int32_t* row_atom, int rows_max,
+                                                     unsigned* flags) {
+    __shared__ int cnt[kMaxSpecies];
+    __shared__ int off[kMaxSpecies];
+    __shared__ int wcnt[16][kMaxSpecies];
+    const int t = threadIdx.x, w = t / kWave;
+    if (t < kMaxSpecies) cnt[t] = 0;
+    for (int r = t; r < rows_max; r += 1024) row_atom[r] = -1;
+    __syncthreads();
+    for (int a = t; a < n; a += 1024) {
+        const int s = species[a];
+        if (s >= 0 && s < ns) atomicAdd(&cnt[s], 1);
+        else set_flag(flags, NNP_FLAG_SPECIES);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int o = 0;
+        for (int q = 0; q < kMaxSpecies; ++q) {
+            const int c = q < ns ? cnt[q] : 0;
+            meta[q] = c;
+            meta[8 + q] = o;
+            off[q] = o;
+            o += ((c + kTileM - 1) / kTileM) * kTileM;
+        }
+        meta[8 + kMaxSpecies] = o;
+    }
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int a = base + t;
+        const int s = a < n ? species[a] : -1;
+        int rank = 0;
+        for (int q = 0; q < ns; ++q) {
+            const unsigned long long m = ballot(s == q);
+            if (s == q) rank = rank_below(m);
+            if (lane_id() == 0) wcnt[w][q] = __popcll(m);
+        }
+        __syncthreads();
+        if (a < n) {
+            if (s >= 0 && s < ns) {
+                int before = 0;
+                for (int q = 0; q < w; ++q) before += wcnt[q][s];
+                const int row = off[s] + before + rank;
+                prow[a] = row;
+                row_atom[row] = a;
+            } else {
+                prow[a] = -1;
+            }
+        }
+        __syncthreads();
+        if (t < ns) {
+            int add = 0;
+            for (int q = 0; q < 16; ++q) add += wcnt[q][t];
+            off[t] += add;
+        }
+        __syncthreads();
+    }
+}
+
 // zero AEV rows that no atom owns (padding of each species segment)
 template <typename T>
 __global__ void k_zero_pad_rows(const int32_t* row_atom, int rows, int stride, T* aev) {
@@ -384,6 +447,26 @@ __global__ __launch_bounds__(256) void k_energy_final(int nparts, const double* 
     if (threadIdx.x == 0) e_mol[0] = red[0];
 }
 
+__global__ __launch_bounds__(1024) void k_energy_single(int n, const int32_t* prow, const int32_t* species,
+                                                       const SelfE se, const float* E_at, double* e_mol,
+                                                       float* e_atom) {
+    __shared__ double red[1024];
+    double acc = 0.0;
+    for (int a = threadIdx.x; a < n; a += 1024) {
+        const bool ok = prow[a] >= 0;
+        const double v = ok ? (double)E_at[a] + se.e[species[a]] : 0.0;
+        if (e_atom) e_atom[a] = (float)v;
+        acc += v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 512; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e_mol[0] = red[0];
+}
+
 __global__ void k_mol_ranges2(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end, unsigned* flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -418,6 +501,15 @@ __global__ void k_permute_rows(const int32_t* prow, int n, int stride, const flo
     for (int c = threadIdx.x; c < stride; c += blockDim.x) d[c] = s[c];
 }
 
+__global__ void k_permute_rows_bf16(const int32_t* prow, int n, int stride, const float* src, uint16_t* dst) {
+    const int a = blockIdx.x;
+    if (a >= n) return;
+    const int r = prow[a];
+    if (r < 0) return;
+    for (int c = threadIdx.x; c < stride; c += blockDim.x)
+        dst[(size_t)r * stride + c] = f32_to_bf16(src[(size_t)a * stride + c]);
+}
+
 __global__ void k_gather_e(const int32_t* prow, int n, const int32_t* species, const SelfE se, const float* E_row,
                            float* e_atom) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -433,6 +525,10 @@ __global__ void k_gather_e(const int32_t* prow, int n, const int32_t* species, c
 hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, unsigned* flags,
                                 hipStream_t s) {
     const int ns = m->aev.ns;
+    if (n <= kSmallGroup) {
+        k_group_small<<<1, 1024, 0, s>>>(species, n, ns, W.meta, W.prow, W.row_atom, W.rows_max, flags);
+        return hipGetLastError();
+    }
     const int nb = ceil_div(n > 0 ? n : 1, kGroupBlock);
     k_fill_i32<<<ceil_div(W.rows_max, 256), 256, 0, s>>>(W.row_atom, W.rows_max, -1);
     k_species_count<<<nb, 256, 0, s>>>(species, n, ns, W.bcount, flags);
@@ -516,6 +612,10 @@ hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool 
 hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
                          int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_at, double* e_mol,
                          float* e_atom, unsigned* flags, hipStream_t s) {
+    if (n_mol == 1 && !mol && n <= 2 * kChunk) {
+        k_energy_single<<<1, 1024, 0, s>>>(n, W.prow, species, se, E_at, e_mol, e_atom);
+        return hipGetLastError();
+    }
     if (n_mol == 1 && n > 2 * kChunk) {
         // mol must still be validated: a single structure means every mol entry is 0
         if (mol) k_mol_ranges2<<<ceil_div(n, 256), 256, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
@@ -544,6 +644,13 @@ hipError_t launch_permute_rows(bool to_grouped, const int32_t* prow, int n, int 
     if (n <= 0) return hipSuccess;
     if (to_grouped) k_permute_rows<true><<<n, 256, 0, s>>>(prow, n, stride, src, dst);
     else k_permute_rows<false><<<n, 256, 0, s>>>(prow, n, stride, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_rows_bf16(const int32_t* prow, int n, int stride, const float* src, uint16_t* dst,
+                                    hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_permute_rows_bf16<<<n, 256, 0, s>>>(prow, n, stride, src, dst);
     return hipGetLastError();
 }
 

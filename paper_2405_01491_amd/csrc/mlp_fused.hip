@@ -1,0 +1,511 @@
+// Fused species network: forward, head and adjoint of the
+// 1008-256-192-160-1 CELU network (Sec. 2.2, "Neural Networks"; Sec. 2.4)
+// for one tile of TM same-species atoms in a single kernel.
+//
+//   h1 = CELU(W1 a + b1), h2 = CELU(W2 h1 + b2), h3 = CELU(W3 h2 + b3)
+//   E  = w4 . h3 + b4
+//   d3 = w4 * CELU'(h3), d2 = (W3^T d3) * CELU'(h2), d1 = (W2^T d2) * CELU'(h1)
+//   dE/da = W1^T d1
+//
+// Four waves split every layer's output columns (64 / 48 / 48 per wave; the
+// 160-wide layer is padded to 192 with zero weights).  Each wave keeps its
+// h1 and h2 columns in registers (MFMA accumulator layout) for the CELU'
+// epilogues of the adjoint, which produces exactly the same columns.  The A
+// operand of every GEMM is the previous layer's output, staged in one LDS
+// tile (float32 for the FP32 form, bfloat16 for the BF16 form, where the
+// GEMM inputs are bf16 by definition); the first layer streams the AEV tile
+// through a double-buffered part of the same LDS.  B operands (weights) are
+// pre-packed per species in MFMA fragment order, so a lane fetches its
+// fragment with one 16-byte load; each wave reads only its own columns.
+//   FP32 form: v_mfma_f32_16x16x4_f32   (a 16-byte B load covers 4 k-steps)
+//   BF16 form: v_mfma_f32_16x16x32_bf16 (float32 accumulation)
+// Only the AEV tile is read from and dE/dAEV written to HBM; activations
+// never leave the CU.
+#include <type_traits>
+
+#include "nnp_internal.hpp"
+
+namespace nnp {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int K0 = 1024, N1 = 256, N2 = 192, N3 = 192;
+constexpr int kThreads = 256;
+
+template <bool BF>
+struct Cfg;
+template <>
+struct Cfg<false> {                 // FP32
+    typedef float act_t;
+    static constexpr int kStep = 4;     // k per MFMA
+    static constexpr int kLd = N1 + 4;  // act row stride (elements)
+    static constexpr int kChunk = 32;   // layer-1 K chunk
+    static constexpr int kChunkLd = kChunk + 4;
+};
+template <>
+struct Cfg<true> {                  // BF16
+    typedef uint16_t act_t;
+    static constexpr int kStep = 32;
+    static constexpr int kLd = N1 + 8;
+    static constexpr int kChunk = 64;
+    static constexpr int kChunkLd = kChunk + 8;
+};
+
+__device__ __forceinline__ float celu(float v, float alpha) { return v > 0.f ? v : alpha * (__expf(v / alpha) - 1.f); }
+__device__ __forceinline__ float celu_grad_from_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
+
+// one MFMA k-step: A fragment from LDS activations (row stride ld), B fragment given
+template <bool BF>
+__device__ __forceinline__ f32x4 mfma_step(const typename Cfg<BF>::act_t* act, int ld, int row, int k, const void* bfrag,
+                                           f32x4 c);
+template <>
+__device__ __forceinline__ f32x4 mfma_step<false>(const float* act, int ld, int row, int k, const void* bfrag,
+                                                  f32x4 c) {
+    const float a = act[row * ld + k];
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, *(const float*)bfrag, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ f32x4 mfma_step<true>(const uint16_t* act, int ld, int row, int k, const void* bfrag,
+                                                 f32x4 c) {
+    const bf16x8 a = *(const bf16x8*)(act + row * ld + k);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, *(const bf16x8*)bfrag, c, 0, 0, 0);
+}
+
+// C[TM x (NCB*16 columns of this wave)] = A[TM x K] (LDS, stride ld) * B (packed, global)
+// FP32 pack: [nb][K/16][64 lanes][4]   BF16 pack: [nb][K/32][64 lanes][8]
+template <bool BF, int MB, int NCB, int K>
+__device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int ld, const void* Bpack, int nb0,
+                                         f32x4 (&acc)[MB][NCB]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if (!BF) {
+        const float4* B = (const float4*)Bpack;
+        for (int kq = 0; kq < K / 16; ++kq) {
+            float4 b[NCB];
+#pragma unroll
+            for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * (K / 16) + kq) * 64 + l];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * kq + 4 * j + (l >> 4);
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    const float a = ((const float*)act)[(16 * mb + (l & 15)) * ld + k];
+#pragma unroll
+                    for (int nb = 0; nb < NCB; ++nb) {
+                        const float bv = j == 0 ? b[nb].x : j == 1 ? b[nb].y : j == 2 ? b[nb].z : b[nb].w;
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[mb][nb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    } else {
+        const u16x8* B = (const u16x8*)Bpack;
+        for (int ks = 0; ks < K / 32; ++ks) {
+            bf16x8 b[NCB];
+#pragma unroll
+            for (int nb = 0; nb < NCB; ++nb) {
+                const u16x8 v = B[((size_t)(nb0 + nb) * (K / 32) + ks) * 64 + l];
+                b[nb] = __builtin_bit_cast(bf16x8, v);
+            }
+            const int k = 32 * ks + 8 * (l >> 4);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const bf16x8 a = *(const bf16x8*)((const uint16_t*)act + (16 * mb + (l & 15)) * ld + k);
+#pragma unroll
+                for (int nb = 0; nb < NCB; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <bool BF>
+__device__ __forceinline__ void put_act(typename Cfg<BF>::act_t* act, int idx, float v);
+template <>
+__device__ __forceinline__ void put_act<false>(float* act, int idx, float v) { act[idx] = v; }
+template <>
+__device__ __forceinline__ void put_act<true>(uint16_t* act, int idx, float v) { act[idx] = f32_to_bf16(v); }
+
+struct FusedArgs {
+    const void* Bf1[kMaxSpecies];   // forward packs
+    const void* Bf2[kMaxSpecies];
+    const void* Bf3[kMaxSpecies];
+    const void* Ba3[kMaxSpecies];   // adjoint packs
+    const void* Ba2[kMaxSpecies];
+    const void* Ba1[kMaxSpecies];
+    const float* b1[kMaxSpecies];
+    const float* b2[kMaxSpecies];
+    const float* b3[kMaxSpecies];
+    const float* w4[kMaxSpecies];   // head weights, padded to N3
+    float b4[kMaxSpecies];
+    const int32_t* meta;
+    const int32_t* row_atom;
+    const void* aev;                 // [rows][K0] float32 or bf16
+    float* g_out;                    // [rows][K0] float32 or null
+    float* E_row;                    // [rows]
+    float* E_atomo;                  // [n] atom order or null
+    float alpha;
+    int ns;
+};
+
+template <bool BF, int TM>
+__global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
+    typedef typename Cfg<BF>::act_t act_t;
+    constexpr int MB = TM / 16;
+    constexpr int LD = Cfg<BF>::kLd;
+    constexpr int CH = Cfg<BF>::kChunk, CLD = Cfg<BF>::kChunkLd;
+    constexpr int kActBytes = TM * LD * (int)sizeof(act_t);
+    constexpr int kStageBytes = 2 * TM * CLD * (int)sizeof(act_t);
+    constexpr int kLdsBytes = kActBytes > kStageBytes ? kActBytes : kStageBytes;
+    __shared__ __attribute__((aligned(16))) char smem[kLdsBytes];
+    __shared__ float epart[TM][4];
+    act_t* act = (act_t*)smem;
+    const int row0 = blockIdx.x * TM;
+    const int32_t* meta = A.meta;
+    if (row0 >= meta[8 + A.ns]) return;
+    int s = 0;
+    for (int q = 1; q < A.ns; ++q)
+        if (meta[8 + q] <= row0) s = q;
+    // skip tiles that hold only segment padding
+    if (row0 >= meta[8 + s] + meta[s]) return;
+    const int t = threadIdx.x, w = t / kWave, l = lane_id();
+    const float alpha = A.alpha;
+
+    // ---------------- layer 1: K0 -> N1, A streamed from HBM through LDS
+    f32x4 h1[MB][4];
+    {
+        act_t* stage = act;
+        const act_t* src = (const act_t*)A.aev + (size_t)row0 * K0;
+        constexpr int kElems = TM * CH;                       // per chunk
+        constexpr int kVec = 16 / sizeof(act_t);              // elements per 16-byte load
+        constexpr int kPer = kElems / kVec / kThreads > 0 ? kElems / kVec / kThreads : 1;
+        typedef typename std::conditional<BF, u16x8, float4>::type vec_t;
+        vec_t pre[kPer];
+        auto gload = [&](int c) {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int idx = (t + kThreads * q) * kVec;
+                if (idx < kElems) {
+                    const int r = idx / CH, cc = idx % CH;
+                    pre[q] = *(const vec_t*)(src + (size_t)r * K0 + c * CH + cc);
+                }
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int idx = (t + kThreads * q) * kVec;
+                if (idx < kElems) {
+                    const int r = idx / CH, cc = idx % CH;
+                    *(vec_t*)(stage + buf * TM * CLD + r * CLD + cc) = pre[q];
+                }
+            }
+        };
+        const float4* Bf = (const float4*)A.Bf1[s];
+        const u16x8* Bb = (const u16x8*)A.Bf1[s];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) h1[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        constexpr int NCH = K0 / CH;
+        for (int c = 0; c < NCH; ++c) {
+            if (c + 1 < NCH) gload(c + 1);
+            const act_t* cur = stage + (c & 1) * TM * CLD;
+            if (!BF) {
+#pragma unroll
+                for (int kq = 0; kq < CH / 16; ++kq) {
+                    float4 b[4];
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+                        b[nb] = Bf[((size_t)(4 * w + nb) * (K0 / 16) + (c * CH / 16 + kq)) * 64 + l];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = 16 * kq + 4 * j + (l >> 4);
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb) {
+                            const float a = ((const float*)cur)[(16 * mb + (l & 15)) * CLD + k];
+#pragma unroll
+                            for (int nb = 0; nb < 4; ++nb) {
+                                const float bv = j == 0 ? b[nb].x : j == 1 ? b[nb].y : j == 2 ? b[nb].z : b[nb].w;
+                                h1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, h1[mb][nb], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < CH / 32; ++ks) {
+                    bf16x8 b[4];
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+                        b[nb] = __builtin_bit_cast(
+                            bf16x8, Bb[((size_t)(4 * w + nb) * (K0 / 32) + (c * CH / 32 + ks)) * 64 + l]);
+                    const int k = 32 * ks + 8 * (l >> 4);
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) {
+                        const bf16x8 a = *(const bf16x8*)((const uint16_t*)cur + (16 * mb + (l & 15)) * CLD + k);
+#pragma unroll
+                        for (int nb = 0; nb < 4; ++nb)
+                            h1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], h1[mb][nb], 0, 0, 0);
+                    }
+                }
+            }
+            if (c + 1 < NCH) sstore((c + 1) & 1);
+            __syncthreads();
+        }
+    }
+    // epilogue 1: h1 = CELU(z1 + b1) (kept), act = h1
+    {
+        const float* b1 = A.b1[s];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int col = 64 * w + 16 * nb + (l & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float h = celu(h1[mb][nb][r] + b1[col], alpha);
+                    h1[mb][nb][r] = h;
+                    put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col, h);
+                }
+            }
+    }
+    __syncthreads();
+    // ---------------- layer 2: N1 -> N2
+    f32x4 h2[MB][3];
+    gemm_act<BF, MB, 3, N1>(act, LD, A.Bf2[s], 3 * w, h2);
+    __syncthreads();
+    {
+        const float* b2 = A.b2[s];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 3; ++nb) {
+                const int col = 48 * w + 16 * nb + (l & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float h = celu(h2[mb][nb][r] + b2[col], alpha);
+                    h2[mb][nb][r] = h;
+                    put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col, h);
+                }
+            }
+    }
+    __syncthreads();
+    // ---------------- layer 3: N2 -> N3 (160 padded to 192), head, d3
+    {
+        f32x4 z3[MB][3];
+        gemm_act<BF, MB, 3, N2>(act, LD, A.Bf3[s], 3 * w, z3);
+        __syncthreads();
+        const float* b3 = A.b3[s];
+        const float* w4 = A.w4[s];
+        float part[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[mb][r] = 0.f;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 3; ++nb) {
+                const int col = 48 * w + 16 * nb + (l & 15);
+                const float wc = w4[col];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float h = celu(z3[mb][nb][r] + b3[col], alpha);
+                    part[mb][r] += h * wc;
+                    put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col, wc * celu_grad_from_h(h, alpha));
+                }
+            }
+        // reduce the 16 lanes sharing a row (columns), fixed butterfly
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = part[mb][r];
+#pragma unroll
+                for (int m = 8; m >= 1; m >>= 1) v += shfl_xor(v, m);
+                if ((l & 15) == 0) epart[16 * mb + 4 * (l >> 4) + r][w] = v;
+            }
+    }
+    __syncthreads();
+    if (t < TM) {
+        const float e = ((epart[t][0] + epart[t][1]) + (epart[t][2] + epart[t][3])) + A.b4[s];
+        const int row = row0 + t;
+        A.E_row[row] = e;
+        const int a = A.row_atom[row];
+        if (a >= 0 && A.E_atomo) A.E_atomo[a] = e;
+    }
+    if (!A.g_out) return;
+    // ---------------- adjoint 3: d2 = (W3^T d3) * CELU'(h2)
+    {
+        f32x4 d[MB][3];
+        gemm_act<BF, MB, 3, N3>(act, LD, A.Ba3[s], 3 * w, d);
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 3; ++nb) {
+                const int col = 48 * w + 16 * nb + (l & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col,
+                                d[mb][nb][r] * celu_grad_from_h(h2[mb][nb][r], alpha));
+            }
+    }
+    __syncthreads();
+    // ---------------- adjoint 2: d1 = (W2^T d2) * CELU'(h1)
+    {
+        f32x4 d[MB][4];
+        gemm_act<BF, MB, 4, N2>(act, LD, A.Ba2[s], 4 * w, d);
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int col = 64 * w + 16 * nb + (l & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col,
+                                d[mb][nb][r] * celu_grad_from_h(h1[mb][nb][r], alpha));
+            }
+    }
+    __syncthreads();
+    // ---------------- adjoint 1: g = W1^T d1, 1024 columns, 4 passes of 64 per wave
+    for (int pass = 0; pass < 4; ++pass) {
+        f32x4 gacc[MB][4];
+        const int nb0 = 16 * w + 4 * pass;
+        gemm_act<BF, MB, 4, N1>(act, LD, A.Ba1[s], nb0, gacc);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int col = 16 * (nb0 + nb) + (l & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    A.g_out[(size_t)(row0 + 16 * mb + 4 * (l >> 4) + r) * K0 + col] = gacc[mb][nb][r];
+            }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+bool fused_mlp_shape(const int* widths, int n_layers, int ns) {
+    const int dim = ns * kNr + ns * (ns + 1) / 2 * kNa * kNz;
+    return n_layers == 4 && dim <= K0 && dim > K0 - 64 && widths[1] == N1 && widths[2] == N2 &&
+           widths[3] <= N3 && widths[3] > N3 - 64 && widths[4] == 1;
+}
+
+// Packs B[k][n] (k < K, n < N, accessor) into MFMA fragment order.
+// FP32: out[((nb * K/16 + kq) * 64 + lane) * 4 + j] = B[16 kq + 4 j + lane/16][16 nb + lane%16]
+// BF16: out[((nb * K/32 + ks) * 64 + lane) * 8 + e] = B[32 ks + 8 (lane/16) + e][16 nb + lane%16]
+template <typename F>
+static void pack_fp32(float* out, int K, int N, F B) {
+    for (int nb = 0; nb < N / 16; ++nb)
+        for (int kq = 0; kq < K / 16; ++kq)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 4; ++j)
+                    out[(((size_t)nb * (K / 16) + kq) * 64 + lane) * 4 + j] =
+                        B(16 * kq + 4 * j + lane / 16, 16 * nb + lane % 16);
+}
+
+uint16_t host_bf16_bits(float f);
+
+template <typename F>
+static void pack_bf16(uint16_t* out, int K, int N, F B) {
+    for (int nb = 0; nb < N / 16; ++nb)
+        for (int ks = 0; ks < K / 32; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e)
+                    out[(((size_t)nb * (K / 32) + ks) * 64 + lane) * 8 + e] =
+                        host_bf16_bits(B(32 * ks + 8 * (lane / 16) + e, 16 * nb + lane % 16));
+}
+
+// Builds the six packs of one species from row-major W_l [out][in] (host).
+// Returns bytes used at dst (dst may be null to size).
+size_t pack_fused_species(char* dst, bool bf16, const float* W1, const float* W2, const float* W3, int n_in,
+                          int n3) {
+    // logical padded matrices: W1p [N1][K0], W2p [N2][N1], W3p [N3][N2] (rows >= n3 zero)
+    auto w1 = [&](int o, int i) { return i < n_in ? W1[(size_t)o * n_in + i] : 0.f; };
+    auto w2 = [&](int o, int i) { return W2[(size_t)o * N1 + i]; };
+    auto w3 = [&](int o, int i) { return o < n3 ? W3[(size_t)o * N2 + i] : 0.f; };
+    struct L { int K, N; int kind; };
+    const L layers[6] = {{K0, N1, 0}, {N1, N2, 1}, {N2, N3, 2}, {N3, N2, 3}, {N2, N1, 4}, {N1, K0, 5}};
+    size_t off = 0;
+    for (const L& q : layers) {
+        const size_t bytes = (size_t)q.K * q.N * (bf16 ? 2 : 4);
+        if (dst) {
+            auto B = [&](int k, int n) -> float {
+                switch (q.kind) {
+                    case 0: return w1(n, k);     // forward: B[k][n] = W[n][k]
+                    case 1: return w2(n, k);
+                    case 2: return w3(n, k);
+                    case 3: return w3(k, n);     // adjoint: B[k][n] = W[k][n]
+                    case 4: return w2(k, n);
+                    default: return w1(k, n);
+                }
+            };
+            if (bf16) pack_bf16((uint16_t*)(dst + off), q.K, q.N, B);
+            else pack_fp32((float*)(dst + off), q.K, q.N, B);
+        }
+        off += (bytes + 255) & ~(size_t)255;
+    }
+    return off;
+}
+
+hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,
+                            float* E_atomo, int n_atoms, hipStream_t s) {
+    const bool bf = m->precision == NNP_BF16_MLP;
+    FusedArgs A;
+    const int ns = m->aev.ns;
+    for (int q = 0; q < ns; ++q) {
+        const char* base = (const char*)(bf ? m->fused_bf16[q] : m->fused_fp32[q]);
+        const size_t unit = bf ? 2 : 4;
+        size_t off = 0;
+        const int KN[6][2] = {{K0, N1}, {N1, N2}, {N2, N3}, {N3, N2}, {N2, N1}, {N1, K0}};
+        const void** dst[6] = {A.Bf1, A.Bf2, A.Bf3, A.Ba3, A.Ba2, A.Ba1};
+        for (int k = 0; k < 6; ++k) {
+            dst[k][q] = base + off;
+            off += ((size_t)KN[k][0] * KN[k][1] * unit + 255) & ~(size_t)255;
+        }
+        A.b1[q] = m->ptrs.b[q][0];
+        A.b2[q] = m->ptrs.b[q][1];
+        A.b3[q] = m->ptrs.b[q][2];
+        A.w4[q] = m->ptrs.head_w[q];
+        A.b4[q] = m->ptrs.head_b[q];
+    }
+    A.meta = W.meta;
+    A.row_atom = W.row_atom;
+    A.aev = aev;
+    A.g_out = g_out;
+    A.E_row = E_row;
+    A.E_atomo = E_atomo;
+    A.alpha = m->celu_alpha;
+    A.ns = ns;
+    // tile height: enough tiles to fill the chip twice over (the FP32 form stops at
+    // 32 rows: its 64-row tile does not fit the register file)
+    int tm = n_atoms >= 48 * 1024 ? 64 : (n_atoms >= 12 * 1024 ? 32 : 16);
+    if (!bf && tm > 32) tm = 32;
+    const int grid = ceil_div(W.rows_max, tm);
+    if (bf) {
+        if (tm == 64) k_mlp_fused<true, 64><<<grid, kThreads, 0, s>>>(A);
+        else if (tm == 32) k_mlp_fused<true, 32><<<grid, kThreads, 0, s>>>(A);
+        else k_mlp_fused<true, 16><<<grid, kThreads, 0, s>>>(A);
+    } else {
+        if (tm == 32) k_mlp_fused<false, 32><<<grid, kThreads, 0, s>>>(A);
+        else k_mlp_fused<false, 16><<<grid, kThreads, 0, s>>>(A);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nnp

@@ -66,6 +66,11 @@ struct nnp_model {
     nnp::MlpPtrs ptrs;
     unsigned* flags;                  // device sticky error flags
     void* host_stage;                 // pinned host staging for synchronous reads
+    bool fused;                       // widths match the fused 1008-256-192-160-1 kernel
+    bool force_unfused;               // use the per-layer GEMM path (testing / comparison)
+    void* fused_dev;
+    const void* fused_fp32[nnp::kMaxSpecies];   // fragment-ordered weight packs (float32)
+    const void* fused_bf16[nnp::kMaxSpecies];   // (bfloat16)
     struct nnp_prof* prof;            // per-stage event timing (host side)
 };
 
@@ -163,6 +168,13 @@ hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* specie
 hipError_t launch_zero_pad_rows(const MlpWs& W, int stride, void* aev, bool bf16, hipStream_t s);
 hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool aev_bf16, float* const* h,
                       float* g_out, float* E_row, float* E_atomo, hipStream_t s);
+bool fused_mlp_shape(const int* widths, int n_layers, int ns);
+size_t pack_fused_species(char* dst, bool bf16, const float* W1, const float* W2, const float* W3, int n_in, int n3);
+uint16_t host_bf16_bits(float f);
+hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,
+                            float* E_atomo, int n_atoms, hipStream_t s);
+hipError_t launch_permute_rows_bf16(const int32_t* prow, int n, int stride, const float* src, uint16_t* dst,
+                                    hipStream_t s);
 hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
                          int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_at, double* e_mol,
                          float* e_atom, unsigned* flags, hipStream_t s);

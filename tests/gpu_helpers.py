@@ -33,6 +33,23 @@ def energy_error(E, E_ref):
     return float(np.max(np.abs(E - E_ref) / np.maximum(np.abs(E_ref), rms))) if len(E_ref) else 0.0
 
 
+def bf16_flip_error(x, ref, scale):
+    """Per-row error of the BF16 form against the oracle's bf16 emulation, as
+    (median, max) of max_row|x - ref| / scale.
+
+    Both sides round the same values to bfloat16, but the GPU accumulates in
+    float32 and the oracle exactly; where the two pre-rounding values straddle
+    a bfloat16 rounding boundary the rounded inputs differ by one bf16 ulp
+    (2^-8 relative).  Such flips touch a minority of atoms (about one atom in
+    ten for these widths), so the median row must sit at float32 accumulation
+    error while the maximum is bounded by the effect of a few flips."""
+    d = np.abs(np.asarray(x, np.float64) - ref)
+    if d.ndim > 1:
+        d = d.reshape(len(d), -1).max(1)
+    d = d / scale
+    return (float(np.median(d)), float(d.max())) if len(d) else (0.0, 0.0)
+
+
 def organic(n, seed=31, density=0.1):
     return synthetic.organic_box(n=n, density=density, seed=seed)
 
