@@ -35,7 +35,52 @@ def mlp_flops_per_atom(widths):
     return fwd, adj
 
 
-def cpu_baseline(w, spec, budget_s=20.0):
+# one kernel per timed stage where the roofline is reported
+STAGE_KERNEL = {("mlp", True): "k_mlp_fused", ("mlp", False): "k_gemm_* chain", ("aev", True): "k_aev_fwd",
+                ("aev", False): "k_aev_fwd", ("aev_adjoint", True): "k_aev_bwd",
+                ("aev_adjoint", False): "k_aev_bwd", ("forces", True): "k_force_gather",
+                ("forces", False): "k_force_gather"}
+STAGE_SOURCE = {"mlp": "mlp_fused.hip", "aev": "aev.hip", "aev_adjoint": "aev.hip", "forces": "forces.hip",
+                "neighbors": "neighbors.hip"}
+
+
+def stage_bytes(stage, N, P, precision, D):
+    """Algorithmic HBM bytes of one launch: every input read once, every
+    output written once (N atoms, P list pairs, D features)."""
+    feat = 2 if precision == "bf16" else 4       # feature rows handed to the networks
+    nl = 4 * (N + 1) + 7 * P                     # row_ptr, col (int32), shift (3 x int8)
+    atoms = 20 * N                               # position, species, species-grouped row
+    return {"aev": atoms + nl + feat * D * N,
+            "aev_adjoint": atoms + nl + 4 * D * N + 12 * P,
+            "forces": 4 * (N + 1) + 16 * P + 12 * N,
+            "neighbors": 12 * N + nl + 4 * P}.get(stage, 0)
+
+
+def source_digest(stage):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2405_01491_amd", "csrc", STAGE_SOURCE.get(stage, ""))
+    if not os.path.isfile(path):
+        return None
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def load_traffic(path, stage, config, precision):
+    """Measured HBM bytes per launch of the stage's kernel (FETCH_SIZE +
+    WRITE_SIZE counters scaled by a plain-copy calibration), or None when no
+    measurement exists or the kernel source changed since it was taken."""
+    path = path or os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.isfile(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    e = tab.get("%s/config%d/%s" % (stage, config, precision))
+    if not e or e.get("source_sha256") != source_digest(stage):
+        return None
+    return e
+
+
+def cpu_baseline(w, spec, budget_s=12.0):
     """The FP64 oracle on the same workload, on the host's cores."""
     import oracle
     try:
@@ -49,7 +94,7 @@ def cpu_baseline(w, spec, budget_s=20.0):
         t0 = time.perf_counter()
         oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec)
         times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s / 2 or len(times) >= 3:
+        if time.perf_counter() - t_start > budget_s and len(times) >= 2:
             break
     t = float(np.median(times))
     return {"value": w.n_atoms / t, "unit": "atom-steps/s", "cores": int(cores), "kind": "oracle",
@@ -140,7 +185,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (reference for FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--traffic", default=None,
-                    help="JSON file with the measured HBM traffic of the dominant stage (bytes per launch)")
+                    help="JSON table of measured HBM bytes per launch (default: profiles/hbm_traffic.json)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the spatial decomposition "
@@ -217,6 +262,7 @@ def main():
     stages = nmd.profile_read(model)
     nmd.profile_enable(model, False)
     nnp.nnp_check(model)
+    n_pairs = int((nl if args.config == 3 else sim.nl).c.n_pairs)
     dt_s = t1 - t0
     N = w.n_atoms
     value = N * args.steps / dt_s
@@ -233,21 +279,17 @@ def main():
                 "traffic": None, "stage": "mlp (per-species GEMM chain, forward + adjoint)",
                 "algorithmic_per_launch": "%.4g FLOP" % flop}
     else:
-        bytes_per = {"aev": 4032 + 12 + 70 * 7, "aev_adjoint": 4032 + 70 * (7 + 12), "forces": 70 * (4 + 24) + 12,
-                     "neighbors": 12 + 70 * 11}.get(dom, 0)
-        byt = bytes_per * N
+        byt = stage_bytes(dom, N, n_pairs, precision, spec.aev_dim)
         achieved = byt / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": MI355X_PEAK["hbm_GBs"], "unit": "GB/s",
                 "frac": achieved / MI355X_PEAK["hbm_GBs"], "traffic": None, "stage": dom,
                 "algorithmic_per_launch": "%.4g B" % byt}
     roof["avg_launch_ms"] = avg_ms
-    if args.traffic:
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        key = "%s_cfg%d_%s" % (dom, args.config, precision)
-        if key in tr:
-            roof["traffic"] = tr[key]["bytes_per_launch"]
-            roof["traffic_source"] = tr[key]["source"]
+    roof["kernel"] = STAGE_KERNEL.get((dom, model.fused_mlp), dom)
+    tr = load_traffic(args.traffic, dom, args.config, precision)
+    if tr is not None:
+        roof["traffic"] = tr["bytes_per_launch"]
+        roof["traffic_source"] = tr["profile"]
 
     result = {
         "metric": "energy+force atom-steps/s at 1 MI355X (FP32 vs BF16-MLP); p50/p99 request latency",
@@ -255,7 +297,7 @@ def main():
         "ms_per_step": 1e3 * dt_s / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if precision == "fp32" else "f32+bf16(mlp)", "data": "synthetic",
         "config": {"workload": workload, "n_atoms": N, "precision": precision, "skin_A": skin,
-                   "rebuild_every": every},
+                   "rebuild_every": every, "list_pairs": n_pairs},
         "stages_ms_per_step": {k: round(v[0] * v[1] / args.steps, 5) for k, v in per_step.items()},
         "roofline": roof,
     }

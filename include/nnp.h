@@ -200,6 +200,25 @@ nnp_status nnp_energy_forces(nnp_model* model, int32_t n_atoms, const float* pos
                              float* e_atom, float* forces, void* ws, size_t ws_bytes,
                              void* stream);
 
+/* nnp_energy_forces plus the virial (the stress-tensor output of the
+ * energy/forces/virial call of Sec. 5.1).  With G_ij = dE_i/dv_ij the edge
+ * gradient of the force adjoint,
+ *   W = - sum over edges i -> j of v_ij (outer) G_ij      (eV),
+ * which equals sum_a x_a (outer) F_a for an open structure and minus the
+ * (transposed) derivative of E under a homogeneous strain of every edge
+ * vector for a periodic one; pressure = (N k_B T + tr W / 3) / V.
+ *   virial       device float64 [n_mol][3][3] row-major (written; required)
+ *   atom_virial  device float32 [n_atoms][3][3] or NULL: the same sum over
+ *                the edges leaving each atom (written)
+ *   forces       required (the virial comes from the force adjoint)
+ * Structure sums are float64 in ascending atom order (deterministic).
+ * Other arguments, errors and asynchrony as nnp_energy_forces. */
+nnp_status nnp_energy_forces_virial(nnp_model* model, int32_t n_atoms, const float* pos,
+                                    const int32_t* species, const int32_t* mol, int32_t n_mol,
+                                    const float* box_host, const nnp_nlist* nl, double* e_mol,
+                                    float* e_atom, float* forces, double* virial,
+                                    float* atom_virial, void* ws, size_t ws_bytes, void* stream);
+
 /* The AEV alone (the radial and angular features of Sec. 2.2 / App. A):
  * writes aev_out, device float32 [n_atoms][aev_stride] (aev_stride =
  * nnp_aev_dim rounded up to 1024; padding columns are zero), rows in atom

@@ -22,6 +22,11 @@ Chain rule, written out:
   is taken as zero (1/r is replaced by 0 there).
   Forces, since v_ij = x_j + n L - x_i:
     F_a = -dE/dx_a = sum_{a->j} G_aj - sum_{i->a} G_ia.
+  Virial (the stress-tensor output of Sec. 5.1), per structure and per atom:
+    W = - sum over edges i->j of v_ij (outer) G_ij,
+  which is sum_a x_a (outer) F_a for an open structure; a homogeneous strain
+  v -> (1 + eps) v of every edge vector changes E by -tr(W^T eps) to first
+  order.
 """
 import numpy as np
 
@@ -122,8 +127,25 @@ def forces_from_edges(N, nl, G):
     return F
 
 
+def virial_from_edges(nl, v, G, mol=None, n_mol=1, n_atoms=None):
+    """(W_mol [n_mol,3,3], W_atom [N,3,3]): W = -sum_edges v_ij (outer) G_ij,
+    per structure (edges summed in ascending centre order) and per centre."""
+    i = nl[0]
+    N = (int(i.max()) + 1 if len(i) else 0) if n_atoms is None else n_atoms
+    outer = -v[:, :, None] * G[:, None, :]                      # [P,3,3]
+    W_atom = np.zeros((N, 3, 3))
+    for a in range(3):
+        for b in range(3):
+            W_atom[:, a, b] = np.bincount(i, weights=outer[:, a, b], minlength=N)
+    mol = np.zeros(N, dtype=np.int64) if mol is None else np.asarray(mol)
+    W_mol = np.zeros((n_mol, 3, 3))
+    for a in range(N):
+        W_mol[mol[a]] += W_atom[a]
+    return W_mol, W_atom
+
+
 def energy_forces(pos, species, mol, n_mol, box, spec, r_list=None, precision="fp64",
-                  nl=None, need_forces=True):
+                  nl=None, need_forces=True, need_virial=False):
     """Full evaluation.  Returns dict with E_mol [n_mol], E_atom [N],
     F [N,3] (if requested), aev [N,D], g [N,D], nl."""
     if r_list is None:
@@ -138,10 +160,13 @@ def energy_forces(pos, species, mol, n_mol, box, spec, r_list=None, precision="f
     for a in range(N):                                  # ascending atom index
         E_mol[mol[a]] += E_atom[a]
     out = dict(E_mol=E_mol, E_atom=E_atom, aev=A, g=g, nl=nl)
-    if need_forces:
+    if need_forces or need_virial:
         G = edge_gradients(pos, species, box, nl, spec, g)
         out["G"] = G
         out["F"] = forces_from_edges(N, nl, G)
+    if need_virial:
+        v, _ = pair_geometry(pos, box, nl)
+        out["W_mol"], out["W_atom"] = virial_from_edges(nl, v, out["G"], mol, n_mol, N)
     return out
 
 

@@ -204,9 +204,12 @@ def nnp_neighbors(model, pos, mol=None, n_mol=1, box=None, r_list=None, nl=None,
 
 
 def nnp_energy_forces(model, pos, species, mol=None, n_mol=1, box=None, nl=None, forces=True, e_atom=False,
-                      out=None):
+                      out=None, virial=False, atom_virial=False):
     """Energies (float64 [n_mol]), optional atomic energies (float32 [N]) and
-    forces (float32 [N,3]); asynchronous on the current stream."""
+    forces (float32 [N,3]); asynchronous on the current stream.  With
+    ``virial`` (or ``atom_virial``) the virial W = -sum_edges v_ij (outer)
+    dE_i/dv_ij per structure (float64 [n_mol,3,3]) and, if asked, per atom
+    (float32 [N,3,3]) are stored in ``out["virial"]`` / ``out["atom_virial"]``."""
     L = lib()
     n = pos.shape[0]
     if nl is None:
@@ -230,6 +233,24 @@ def nnp_energy_forces(model, pos, species, mol=None, n_mol=1, box=None, nl=None,
     _b, bptr = _box_arg(box)
     need = L.nnp_workspace_bytes(model.handle, n, nl.capacity)
     ws = model.workspace(need)
+    if virial or atom_virial:
+        if F is None:
+            raise ValueError("the virial comes from the force adjoint: forces=True is required")
+        W = out.get("virial")
+        if W is None or W.shape[0] != n_mol:
+            W = torch.empty((n_mol, 3, 3), dtype=torch.float64, device=dev)
+        Wa = None
+        if atom_virial:
+            Wa = out.get("atom_virial")
+            if Wa is None or Wa.shape[0] != n:
+                Wa = torch.empty((n, 3, 3), dtype=torch.float32, device=dev)
+        with torch.cuda.device(dev):
+            check(L.nnp_energy_forces_virial(model.handle, n, _ptr(pos), _ptr(species), _ptr(mol), int(n_mol), bptr,
+                                             ctypes.byref(nl.struct()), _ptr(e_mol_t), _ptr(e_at), _ptr(F), _ptr(W),
+                                             _ptr(Wa), _ptr(ws), ws.numel(), _stream(dev)),
+                  "nnp_energy_forces_virial")
+        out.update(e_mol=e_mol_t, e_atom=e_at, forces=F, virial=W, atom_virial=Wa)
+        return e_mol_t, e_at, F
     with torch.cuda.device(dev):
         check(L.nnp_energy_forces(model.handle, n, _ptr(pos), _ptr(species), _ptr(mol), int(n_mol), bptr,
                                   ctypes.byref(nl.struct()), _ptr(e_mol_t), _ptr(e_at), _ptr(F), _ptr(ws),

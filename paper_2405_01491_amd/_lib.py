@@ -36,6 +36,9 @@ SIGNATURES = {
     "nnp_energy_forces": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_int32,
                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                          ctypes.c_size_t, c_void_p]),
+    "nnp_energy_forces_virial": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
+                                                ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                                c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
     "nnp_aev": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, ctypes.c_size_t, c_void_p]),
     "nnp_mlp": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -301,11 +301,14 @@ struct BwdLds {
     int seg_a[kMaxSpecies + 1];
 };
 
+// kVir: also the per-centre virial W_i = -sum_j v_ij (outer) G_ij, row-major
+// [n][9] (the strain derivative of E_i is -W_i transposed).
+template <bool kVir>
 __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int8_t* __restrict__ shift,
     const int32_t* __restrict__ g_row, const float* __restrict__ g, float* __restrict__ Gx, float* __restrict__ Gy,
-    float* __restrict__ Gz, unsigned* flags) {
+    float* __restrict__ Gz, float* __restrict__ Wat, unsigned* flags) {
     __shared__ BwdLds lds[kWaves];
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
@@ -321,6 +324,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     if (!ok) {
         const int b = row_ptr[i], e = row_ptr[i + 1];
         for (int p = b + l; p < e; p += kWave) Gx[p] = Gy[p] = Gz[p] = 0.f;
+        if (kVir && l < 9) Wat[9 * (size_t)i + l] = 0.f;
         return;
     }
     const float* grow = g + (size_t)row * P.stride;
@@ -475,6 +479,9 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     }
     wave_sync();
     // ---- one value per row slot: radial part + angular part (zero outside Rc_R)
+    float wv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wv[k] = 0.f;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         const int slot = l + kWave * q;
@@ -490,6 +497,25 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
             Gx[p] = x;
             Gy[p] = y;
             Gz[p] = z;
+            if (kVir) {
+                const float v[3] = {R.vx[q], R.vy[q], R.vz[q]}, G[3] = {x, y, z};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) wv[3 * a + c] -= v[a] * G[c];
+            }
+        }
+    }
+    if (kVir) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) wv[k] += shfl_xor(wv[k], m);
+        if (l < 9) {
+            float o = 0.f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) o = l == k ? wv[k] : o;
+            Wat[9 * (size_t)i + l] = o;
         }
     }
 }
@@ -512,11 +538,15 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
 
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
                           const nnp_nlist* nl, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
-                          unsigned* flags, hipStream_t s) {
+                          float* atom_virial, unsigned* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
-    k_aev_bwd<<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift, g_row, g, Gx,
-                                             Gy, Gz, flags);
+    if (atom_virial)
+        k_aev_bwd<true><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift, g_row,
+                                                        g, Gx, Gy, Gz, atom_virial, flags);
+    else
+        k_aev_bwd<false><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift,
+                                                         g_row, g, Gx, Gy, Gz, nullptr, flags);
     return hipGetLastError();
 }
 

@@ -108,6 +108,8 @@ struct EfWs {
     float* Gx;
     float* Gy;
     float* Gz;
+    float* Wat;         // per-centre virials [n][9] when the caller passes none
+    double* vpart;      // chunk partials of the structure virial
     size_t end;
 };
 
@@ -136,6 +138,8 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.Gx = (float*)take(sizeof(float) * c);
     W.Gy = (float*)take(sizeof(float) * c);
     W.Gz = (float*)take(sizeof(float) * c);
+    W.Wat = (float*)take(sizeof(float) * 9 * (size_t)nn);
+    W.vpart = (double*)take(sizeof(double) * virial_partial_doubles(nn));
     W.end = o;
     return W;
 }
@@ -190,7 +194,7 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species,
                                    const int32_t* mol, int32_t n_mol, const float* box_host, const nnp_nlist* nl,
                                    double* e_mol, float* e_atom, float* forces, void* ws, size_t ws_bytes,
-                                   hipStream_t s, unsigned* flags) {
+                                   hipStream_t s, unsigned* flags, double* virial, float* atom_virial) {
     if (!m || !nl || n < 0) return NNP_E_ARG;
     if (n > 0 && (!pos || !species)) return NNP_E_ARG;
     if (n_mol < 0 || (n > 0 && n_mol < 1) || n_mol > (n > 0 ? n : 1)) return NNP_E_ARG;
@@ -231,12 +235,15 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     prof_end(m, NNP_STAGE_ENERGY, s);
     if (e == hipSuccess && forces && n > 0) {
         prof_begin(m, NNP_STAGE_AEV_ADJ, s);
-        e = launch_aev_bwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, flags, s);
+        float* wat = virial || atom_virial ? (atom_virial ? atom_virial : W.Wat) : nullptr;
+        e = launch_aev_bwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, wat, flags, s);
         prof_end(m, NNP_STAGE_AEV_ADJ, s);
         prof_begin(m, NNP_STAGE_FORCES, s);
         if (e == hipSuccess) e = launch_force_gather(n, nl, W.Gx, W.Gy, W.Gz, forces, s);
         prof_end(m, NNP_STAGE_FORCES, s);
     }
+    if (e == hipSuccess && virial)
+        e = launch_virial(n, n_mol, W.mstart, W.mend, atom_virial ? atom_virial : W.Wat, W.vpart, virial, s);
     return hip_status(e);
 }
 
@@ -472,6 +479,16 @@ nnp_status nnp_energy_forces(nnp_model* m, int32_t n, const float* pos, const in
     if (nl->n_atoms != n || nl->n_pairs > nl->capacity) return NNP_E_ARG;
     return energy_forces_impl(m, n, pos, species, mol, n_mol, box_host, nl, e_mol, e_atom, forces, ws, ws_bytes,
                               (hipStream_t)stream, m->flags);
+}
+
+nnp_status nnp_energy_forces_virial(nnp_model* m, int32_t n, const float* pos, const int32_t* species,
+                                    const int32_t* mol, int32_t n_mol, const float* box_host, const nnp_nlist* nl,
+                                    double* e_mol, float* e_atom, float* forces, double* virial, float* atom_virial,
+                                    void* ws, size_t ws_bytes, void* stream) {
+    if (!m || !nl || n < 0 || !forces || !virial) return NNP_E_ARG;
+    if (nl->n_atoms != n || nl->n_pairs > nl->capacity) return NNP_E_ARG;
+    return energy_forces_impl(m, n, pos, species, mol, n_mol, box_host, nl, e_mol, e_atom, forces, ws, ws_bytes,
+                              (hipStream_t)stream, m->flags, virial, atom_virial);
 }
 
 nnp_status nnp_aev(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const float* box_host,

@@ -89,7 +89,69 @@ __global__ void k_wrap(int n, float* pos, float Lx, float Ly, float Lz) {
     }
 }
 
+// Structure virials in float64 from per-centre virials: per-thread sums in
+// ascending atom order, then a fixed tree (deterministic).  One block per
+// structure; a single large structure is split into fixed chunks whose
+// partial sums are added in order by one block.
+constexpr int kVirThreads = 256;
+constexpr int kVirChunk = 4096;
+
+__device__ void block_sum9(double (&acc)[9], double (*red)[9]) {
+    for (int k = 0; k < 9; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int st = kVirThreads / 2; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < 9; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kVirThreads) void k_virial_mol(int n_mol, const int32_t* mstart, const int32_t* mend,
+                                                           const float* Wat, double* out) {
+    __shared__ double red[kVirThreads][9];
+    const int m = blockIdx.x;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = mstart[m] + threadIdx.x; a < mend[m]; a += kVirThreads)
+        for (int k = 0; k < 9; ++k) acc[k] += (double)Wat[9 * (size_t)a + k];
+    block_sum9(acc, red);
+    if (threadIdx.x < 9) out[9 * (size_t)m + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ __launch_bounds__(kVirThreads) void k_virial_chunks(int n, const float* Wat, double* part) {
+    __shared__ double red[kVirThreads][9];
+    const int base = blockIdx.x * kVirChunk;
+    const int end = min(n, base + kVirChunk);
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = base + threadIdx.x; a < end; a += kVirThreads)
+        for (int k = 0; k < 9; ++k) acc[k] += (double)Wat[9 * (size_t)a + k];
+    block_sum9(acc, red);
+    if (threadIdx.x < 9) part[9 * (size_t)blockIdx.x + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ void k_virial_final(int nparts, const double* part, double* out) {
+    if (threadIdx.x >= 9) return;
+    double acc = 0.0;
+    for (int q = 0; q < nparts; ++q) acc += part[9 * (size_t)q + threadIdx.x];
+    out[threadIdx.x] = acc;
+}
+
 }  // namespace
+
+size_t virial_partial_doubles(int n) { return 9 * (size_t)ceil_div(n > 0 ? n : 1, kVirChunk); }
+
+// n_mol == 1: the whole range [0, n); otherwise mstart/mend hold each structure's atom range.
+hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t* mend, const float* Wat, double* part,
+                         double* virial, hipStream_t s) {
+    if (n_mol <= 0) return hipSuccess;
+    if (n_mol == 1) {
+        const int nparts = ceil_div(n > 0 ? n : 1, kVirChunk);
+        k_virial_chunks<<<nparts, kVirThreads, 0, s>>>(n, Wat, part);
+        k_virial_final<<<1, 64, 0, s>>>(nparts, part, virial);
+    } else {
+        k_virial_mol<<<n_mol, kVirThreads, 0, s>>>(n_mol, mstart, mend, Wat, virial);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_force_gather(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
                                hipStream_t s) {

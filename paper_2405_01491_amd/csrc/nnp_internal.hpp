@@ -152,7 +152,8 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
 // nnp_energy_forces with an explicit device flags word (n_pairs of nl is not checked)
 nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
                               int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,
-                              float* forces, void* ws, size_t ws_bytes, hipStream_t s, unsigned* flags);
+                              float* forces, void* ws, size_t ws_bytes, hipStream_t s, unsigned* flags,
+                              double* virial = nullptr, float* atom_virial = nullptr);
 nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev,
                                 int64_t* total_host);
 
@@ -161,7 +162,7 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
                           hipStream_t s);
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
                           const nnp_nlist* nl, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
-                          unsigned* flags, hipStream_t s);
+                          float* atom_virial, unsigned* flags, hipStream_t s);
 
 hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, unsigned* flags,
                                 hipStream_t s);
@@ -183,6 +184,9 @@ hipError_t launch_permute_rows(bool to_grouped, const int32_t* prow, int n, int 
 hipError_t launch_gather_e(const int32_t* prow, int n, const int32_t* species, const SelfE& se, const float* E_row,
                            float* e_atom, hipStream_t s);
 
+size_t virial_partial_doubles(int n);
+hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t* mend, const float* Wat, double* part,
+                         double* virial, hipStream_t s);
 hipError_t launch_force_gather(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
                                hipStream_t s);
 hipError_t launch_kick_drift(int n, float* pos, float* vel, const float* F, const float* inv_mass, float dt,

@@ -241,3 +241,28 @@ def test_species_out_of_range_flagged(model):
         nnp.nnp_check(model)
     nnp.nnp_energy_forces(model, pos, sp, None, 1, None, nl)
     nnp.nnp_check(model)
+
+
+@pytest.mark.parametrize("case", ["organic_box", "batch"])
+def test_virial_parity(spec_bias, case):
+    if case == "organic_box":
+        w = organic(2000)
+    else:
+        w = synthetic.workload(4, n_mol=12)
+    m = nnp.Model(spec_bias, "fp32")
+    pos, sp, mol = to_dev(w)
+    nl = nnp.nnp_neighbors(m, pos, mol, w.n_mol, w.box, 5.1)
+    out = {}
+    nnp.nnp_energy_forces(m, pos, sp, mol, w.n_mol, w.box, nl, out=out, virial=True, atom_virial=True)
+    ref = oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec_bias,
+                               need_virial=True)
+    Wm = out["virial"].cpu().numpy()
+    Wa = out["atom_virial"].cpu().numpy()
+    sa = np.abs(ref["W_atom"]).max()
+    ea = np.abs(Wa - ref["W_atom"]).max() / sa
+    em = np.abs(Wm - ref["W_mol"]).max() / max(np.abs(ref["W_mol"]).max(), sa)
+    print("virial %s: per-atom max err %.3g, per-structure %.3g (of scale %.3g eV)" % (case, ea, em, sa))
+    assert ea < 2e-5 and em < 2e-5
+    # the forces of the virial call are those of the plain call
+    _, _, F = nnp.nnp_energy_forces(m, pos, sp, mol, w.n_mol, w.box, nl)
+    assert torch.equal(F, out["forces"])

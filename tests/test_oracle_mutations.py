@@ -103,3 +103,24 @@ def test_mutant_wrong_image_rounding(monkeypatch):
     monkeypatch.setattr(onb, "_min_image", lambda d0, L: (d0 - np.floor(d0 / L) * L, -np.floor(d0 / L)))
     case = [c for c in __import__("synthetic").adversarial_cases() if c.name == "faces_periodic"][0]
     assert _fails(pins.test_neighbors_match_brute_force_adversarial, case)
+
+
+def test_mutant_virial_attributed_to_neighbour(monkeypatch, spec_bias):
+    # each edge's term booked on atom j instead of its centre i (the structure sum is unchanged);
+    # a transposed outer product would be no mistake: each W_i is symmetric, since E_i is
+    # invariant under a rotation of its edge vectors
+    orig = oforces.virial_from_edges
+
+    def bad(nl, v, G, mol=None, n_mol=1, n_atoms=None):
+        return orig((nl[1], nl[0], nl[2]), v, G, mol, n_mol, n_atoms)
+    monkeypatch.setattr(oforces, "virial_from_edges", bad)
+    assert _fails(pins.test_virial_is_the_strain_derivative, spec_bias, True)
+
+
+def test_mutant_virial_sign(monkeypatch, spec_bias):
+    orig = oforces.virial_from_edges
+
+    def bad(nl, v, G, mol=None, n_mol=1, n_atoms=None):
+        return orig(nl, -v, G, mol, n_mol, n_atoms)
+    monkeypatch.setattr(oforces, "virial_from_edges", bad)
+    assert _fails(pins.test_virial_of_open_structure_is_sum_x_outer_F, spec_bias)

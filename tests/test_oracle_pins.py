@@ -315,6 +315,56 @@ def test_forces_match_finite_differences_periodic(spec_bias):
     assert np.max(np.abs(out["F"][atoms] - F_fd)) <= 1e-7 * max(1.0, np.max(np.abs(F_fd)))
 
 
+def _strained_atom_energies(w, sp, spec, nl, eps):
+    """Atomic energies with every edge vector mapped v -> (I + eps) v (a
+    homogeneous strain; with a periodic box the images strain alongside)."""
+    from oracle.forces import _geometry64
+    v, _ = _geometry64(w.pos.astype(np.float64), w.box, nl)
+    v = v + v @ eps.T
+    A = oracle.aev(None, sp, w.box, nl, spec, geometry=(v, np.sqrt(np.sum(v * v, axis=1))), n_atoms=w.n_atoms)
+    return oracle.mlp_energy(A, sp, spec)
+
+
+@pytest.mark.parametrize("periodic", [False, True], ids=["cluster", "box"])
+def test_virial_is_the_strain_derivative(spec_bias, periodic):
+    """dE_i/d eps_ab = -W_i[b, a] per atom (and so for the structure sum),
+    from central differences of the atomic energies under a strain of
+    every edge vector; non-symmetric per-atom components are pinned too."""
+    if periodic:
+        w = small_water_box(40)
+        sp = synthetic.workload(3).species[:w.n_atoms]
+    else:
+        w = synthetic.workload(1)
+        sp = w.species
+    out = oracle.energy_forces(w.pos, sp, None, 1, w.box, spec_bias, need_virial=True)
+    nl = out["nl"]
+    W_atom, W_mol = out["W_atom"], out["W_mol"][0]
+    h = 1e-6
+    scale = np.max(np.abs(W_atom))
+    for a in range(3):
+        for b in range(3):
+            eps = np.zeros((3, 3))
+            eps[a, b] = h
+            d = (_strained_atom_energies(w, sp, spec_bias, nl, eps)
+                 - _strained_atom_energies(w, sp, spec_bias, nl, -eps)) / (2 * h)
+            assert np.max(np.abs(d + W_atom[:, b, a])) <= 1e-6 * scale, (a, b)
+            assert abs(d.sum() + W_mol[b, a]) <= 1e-6 * w.n_atoms * scale, (a, b)
+    assert np.allclose(W_atom.sum(0), W_mol, rtol=0, atol=1e-12 * w.n_atoms * scale)
+
+
+def test_virial_of_open_structure_is_sum_x_outer_F(spec_bias):
+    """For an open structure W = sum_a x_a (outer) F_a, which is symmetric
+    (zero net torque)."""
+    w = synthetic.workload(1)
+    out = oracle.energy_forces(w.pos, w.species, None, 1, None, spec_bias, need_virial=True)
+    x = w.pos.astype(np.float64)
+    ref = np.einsum("ia,ib->ab", x, out["F"])
+    W = out["W_mol"][0]
+    scale = np.max(np.abs(W))
+    assert np.max(np.abs(W - ref)) <= 1e-11 * w.n_atoms * scale
+    assert np.max(np.abs(W - W.T)) <= 1e-11 * w.n_atoms * scale
+
+
 def test_net_force_and_torque_vanish(spec_bias):
     w = synthetic.workload(1)
     out = oracle.energy_forces(w.pos, w.species, None, 1, None, spec_bias)
