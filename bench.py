@@ -1,8 +1,10 @@
 """Throughput benchmark: energy + force atom-steps/s on one MI355X.
 
-A step is one pass of the whole hot path on GPU-resident state: neighbour
-list build (cell list), AEV, species networks, float64 structure energy,
-AEV adjoint, force gather and the two velocity-Verlet half steps.
+A step is one pass of the whole hot path on GPU-resident state, run by the
+native MD engine (nnp_md_run: the steps are enqueued in one go and the host
+waits once, at the end): integrator half steps, the on-device rebuild
+decision, neighbour list build (cell list), AEV, species networks, float64
+structure energy, AEV adjoint and force gather.
 
 Default workload: periodic box of 1500 rigid-geometry waters (4,500 atoms,
 1.0 g/cm^3, L = 35.54 A), FP32, velocity Verlet at dt = 0.5 fs from 300 K
@@ -182,6 +184,11 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--integrator", default="nve", choices=["nve", "langevin"],
+                    help="nve: velocity Verlet (the configured workloads); langevin: BAOAB as in the paper's "
+                         "benchmarks")
+    ap.add_argument("--temperature", type=float, default=300.0)
+    ap.add_argument("--friction", type=float, default=1.0, help="Langevin friction, 1/ps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (reference for FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--traffic", default=None,
@@ -238,31 +245,46 @@ def main():
                     "L = 61.27 A, periodic; energy + forces per step (list built once), %s MLP" % precision)
     else:
         vel = torch.from_numpy(nmd.maxwell_boltzmann(masses, 300.0, seed=2024)).to(dev)
+        integ = args.integrator
+        dyn = ("velocity Verlet" if integ == "nve" else
+               "BAOAB Langevin %g K, friction %g/ps" % (args.temperature, args.friction))
         if args.config == 2:
             skin, every = 0.0, 1
-            workload = ("water_box_4500: 1500 rigid waters, 1.0 g/cm^3, L = 35.54 A, periodic; velocity Verlet "
-                        "dt = 0.5 fs from 300 K, neighbour list rebuilt every step; %s" % precision)
+            workload = ("water_box_4500: 1500 rigid waters, 1.0 g/cm^3, L = 35.54 A, periodic; %s "
+                        "dt = 0.5 fs from 300 K, neighbour list rebuilt every step; %s" % (dyn, precision))
         else:
             skin, every = 0.5, 20
-            workload = ("water_box_99999: 33,333 rigid waters, 1.0 g/cm^3, L = 99.905 A, periodic; velocity "
-                        "Verlet dt = 0.5 fs from 300 K, 0.5 A skin, rebuild every 20 steps; %s MLP" % precision)
-        sim = nmd.VelocityVerlet(model, pos, vel, sp, masses, w.box, dt=0.5, skin=skin, rebuild_every=every)
-        step = sim.step
+            workload = ("water_box_99999: 33,333 rigid waters, 1.0 g/cm^3, L = 99.905 A, periodic; %s "
+                        "dt = 0.5 fs from 300 K, 0.5 A skin, rebuild every 20 steps; %s MLP" % (dyn, precision))
+        sim = nmd.MDEngine(model, pos, vel, sp, masses, w.box, dt=0.5, integrator=integ,
+                           temperature=args.temperature, friction=args.friction, seed=2024, skin=skin,
+                           rebuild_every=every)
 
-    for _ in range(args.warmup):
-        step()
+    if args.config == 3:
+        for _ in range(args.warmup):
+            step()
+    else:
+        sim.run(args.warmup)
     torch.cuda.synchronize()
     nmd.profile_enable(model, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    if args.config == 3:
+        for _ in range(args.steps):
+            step()
+    else:
+        sim.run(args.steps)          # enqueued in one go, one synchronisation at the end
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = nmd.profile_read(model)
     nmd.profile_enable(model, False)
     nnp.nnp_check(model)
-    n_pairs = int((nl if args.config == 3 else sim.nl).c.n_pairs)
+    if args.config == 3:
+        n_pairs = int(nl.c.n_pairs)
+    else:
+        info = sim.info()
+        x_now = sim.state()[0]
+        n_pairs = int(nnp.nnp_neighbors(model, x_now, None, 1, w.box, info["r_list"]).c.n_pairs)
     dt_s = t1 - t0
     N = w.n_atoms
     value = N * args.steps / dt_s
@@ -302,8 +324,10 @@ def main():
         "roofline": roof,
     }
     if args.config != 3:
-        result["config"]["rebuilds"] = sim.rebuilds
-        result["config"]["early_rebuilds"] = sim.early_rebuilds
+        result["config"]["integrator"] = args.integrator
+        result["config"]["rebuilds"] = info["rebuilds"]
+        result["config"]["early_rebuilds"] = info["early_rebuilds"]
+        result["config"]["list_replays"] = info["replays"]
     if args.config == 2 and args.serving_seconds > 0:
         result["serving"] = serving_bench(model, duration_s=args.serving_seconds)
     if not args.no_cpu_baseline:

@@ -62,6 +62,7 @@ typedef enum {
 #define NNP_FLAG_NONFINITE 0x4u   /* non-finite coordinate                        */
 #define NNP_FLAG_MOL       0x8u   /* mol not non-decreasing or out of [0, n_mol) */
 #define NNP_FLAG_SHIFT     0x10u  /* periodic image shift outside int8 range      */
+#define NNP_FLAG_CAPACITY  0x20u  /* asynchronous list build exceeded its capacity */
 
 /* Largest neighbour-row length (pairs within the list cutoff of one atom) the
  * AEV kernels accept.  Longer rows set NNP_FLAG_ROW and contribute nothing. */
@@ -250,6 +251,81 @@ nnp_status nnp_md_kick(int32_t n_atoms, float* vel, const float* forces, const f
 /* Wrap positions into [0, L) per dimension (periodic boxes, before a rebuild). */
 nnp_status nnp_md_wrap(int32_t n_atoms, float* pos, const float* box_host, void* stream);
 
+/* ---------------------------------------------------------------- native MD engine */
+
+/* The paper's native engine (Sec. 5.4) keeps the whole time step on the GPU;
+ * its benchmarks (Sec. 5.5) run Langevin dynamics at 300 K with a 0.5 fs
+ * step and a neighbour-list buffer rebuilt every few steps.  An nnp_md owns
+ * one structure's state (periodic orthorhombic box or open) in device memory
+ * and advances it with:
+ *   NNP_MD_NVE       velocity Verlet: B(dt/2) A(dt) | F | B(dt/2)
+ *   NNP_MD_LANGEVIN  BAOAB: B(dt/2) A(dt/2) O A(dt/2) | F | B(dt/2), with
+ *                    O: v = c1 v + sqrt((1 - c1^2) kT / m) xi, c1 = exp(-gamma dt)
+ * B: v += h F/m (9.648533212e-3 converts eV/A/amu to A/fs^2), A: x += h v.
+ * xi for atom a at step s (steps counted from 0 at creation) are three
+ * Gaussian numbers from one Philox4x64-10 block (Salmon et al., SC'11) with
+ * counter (a + 1, s, 0, 0) and key (seed, 0): with the block's words w_k,
+ * u_k = ((w_k >> 40) + 1/2) 2^-24, xi = (rho0 cos 2pi u1, rho0 sin 2pi u1,
+ * rho2 cos 2pi u3), rho_k = sqrt(-2 ln u_k).
+ * The list (cutoff = radial cutoff + skin) is rebuilt, positions wrapped into
+ * the box, every rebuild_every steps, and earlier as soon as an atom has
+ * moved more than trigger * skin / 2 since the last build (skin > 0,
+ * trigger > 0); the decision is taken on the device. */
+typedef enum { NNP_MD_NVE = 0, NNP_MD_LANGEVIN = 1 } nnp_md_integrator;
+
+typedef struct {
+    nnp_md_integrator integrator;
+    float dt;                 /* fs                                               */
+    float temperature;        /* K (Langevin)                                     */
+    float friction;           /* gamma in 1/ps (Langevin)                         */
+    uint64_t seed;            /* key of the noise generator (Langevin)            */
+    float skin;               /* A, added to the radial cutoff for the list       */
+    int32_t rebuild_every;    /* >= 1                                             */
+    float trigger;            /* early rebuild threshold in units of skin / 2     */
+    int32_t log_every;        /* > 0: record (E_pot, E_kin) every log_every steps */
+    int32_t log_capacity;     /* rows kept (later rows are dropped)               */
+    float capacity_slack;     /* list capacity = pairs needed * (1 + slack)      */
+} nnp_md_params;
+
+typedef struct {
+    int64_t steps;            /* steps taken since creation                       */
+    int64_t rebuilds;         /* list builds, the one at creation included        */
+    int64_t early_rebuilds;   /* builds triggered by displacement                 */
+    int64_t replays;          /* runs replayed after a list regrow                */
+    int64_t capacity;         /* current list capacity (pairs)                    */
+    float r_list;
+} nnp_md_stats;
+
+typedef struct nnp_md nnp_md;
+
+/* Create an engine for n_atoms atoms: pos, vel (A/fs) device float32
+ * [n][3], species device int32 [n], masses device float32 [n] (amu, > 0),
+ * box_host host float32 [3] or NULL.  Inputs are copied; the engine owns
+ * its device memory (allocated here and when the list regrows).  Builds the
+ * list (synchronously) and the starting forces.  The model must outlive it.
+ * NNP_E_BOX if a box side is below 2 (cutoff + skin); NNP_E_NONFINITE for
+ * non-finite positions or non-positive masses. */
+nnp_status nnp_md_create(nnp_model* model, int32_t n_atoms, const float* pos, const float* vel,
+                         const int32_t* species, const float* masses, const float* box_host,
+                         const nnp_md_params* params, void* stream, nnp_md** out);
+/* Advance n_steps steps.  The steps are enqueued without waiting; the call
+ * synchronises `stream` once at the end to read the error flags.  If a list
+ * rebuild needed more room than the list has, the run is rolled back to its
+ * start, the list regrown and the run replayed (same result).  Errors:
+ * NNP_E_NONFINITE, NNP_E_ROW, NNP_E_CAPACITY (regrowth failed). */
+nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream);
+/* Copy the current state into caller device buffers (any may be NULL):
+ * pos, vel, forces float32 [n][3], e_pot float64 [1].  Asynchronous. */
+nnp_status nnp_md_get(nnp_md* md, float* pos, float* vel, float* forces, double* e_pot,
+                      void* stream);
+/* Copy up to max_rows logged rows {E_pot, E_kin} (eV, float64) to host
+ * memory; *n_rows receives the count.  Synchronises. */
+nnp_status nnp_md_log(nnp_md* md, double* host_rows, int32_t max_rows, int32_t* n_rows,
+                      void* stream);
+/* Counters (synchronises). */
+nnp_status nnp_md_info(nnp_md* md, nnp_md_stats* out, void* stream);
+void nnp_md_destroy(nnp_md* md);
+
 /* ---------------------------------------------------------------- serving */
 
 /* Continuous-batching server over one model (the model must outlive it).
@@ -296,7 +372,8 @@ enum {
     NNP_STAGE_ENERGY = 4,      /* float64 structure energies                            */
     NNP_STAGE_AEV_ADJ = 5,     /* AEV adjoint -> edge gradients (one kernel)             */
     NNP_STAGE_FORCES = 6,      /* force gather (one kernel)                              */
-    NNP_N_STAGES = 7
+    NNP_STAGE_INTEGRATE = 7,   /* MD engine: integrator kernels and rebuild decision      */
+    NNP_N_STAGES = 8
 };
 
 /* Enable (1) or disable (0) per-stage timing: while enabled, the library

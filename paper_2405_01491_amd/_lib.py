@@ -16,7 +16,7 @@ STATUS_NAMES = ["NNP_OK", "NNP_E_ARG", "NNP_E_CAPACITY", "NNP_E_BOX", "NNP_E_NON
                 "NNP_E_NOMEM", "NNP_E_BUSY", "NNP_E_PENDING", "NNP_E_HIP", "NNP_E_ROW"]
 NNP_MAX_ROW = 256
 NNP_MAX_ANGULAR = 96
-STAGES = ["neighbors", "group", "aev", "mlp", "energy", "aev_adjoint", "forces"]
+STAGES = ["neighbors", "group", "aev", "mlp", "energy", "aev_adjoint", "forces", "integrate"]
 
 # symbol -> (restype, argtypes)
 SIGNATURES = {
@@ -47,6 +47,13 @@ SIGNATURES = {
                                          c_void_p, c_void_p, c_void_p]),
     "nnp_md_kick": (ctypes.c_int, [ctypes.c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p]),
     "nnp_md_wrap": (ctypes.c_int, [ctypes.c_int32, c_void_p, c_void_p, c_void_p]),
+    "nnp_md_create": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "nnp_md_run": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p]),
+    "nnp_md_get": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nnp_md_log": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), c_void_p]),
+    "nnp_md_info": (ctypes.c_int, [c_void_p, c_void_p, c_void_p]),
+    "nnp_md_destroy": (None, [c_void_p]),
     "nnp_server_create": (ctypes.c_int, [c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.POINTER(c_void_p)]),
     "nnp_submit": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
@@ -83,6 +90,22 @@ class NList(ctypes.Structure):
         ("row_ptr", c_void_p), ("col", c_void_p), ("shift", c_void_p), ("rev", c_void_p),
         ("capacity", ctypes.c_int64), ("r_list", ctypes.c_float), ("n_atoms", ctypes.c_int32),
         ("n_pairs", ctypes.c_int64),
+    ]
+
+
+class MdParams(ctypes.Structure):
+    _fields_ = [
+        ("integrator", ctypes.c_int32), ("dt", ctypes.c_float), ("temperature", ctypes.c_float),
+        ("friction", ctypes.c_float), ("seed", ctypes.c_uint64), ("skin", ctypes.c_float),
+        ("rebuild_every", ctypes.c_int32), ("trigger", ctypes.c_float), ("log_every", ctypes.c_int32),
+        ("log_capacity", ctypes.c_int32), ("capacity_slack", ctypes.c_float),
+    ]
+
+
+class MdStats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64), ("rebuilds", ctypes.c_int64), ("early_rebuilds", ctypes.c_int64),
+        ("replays", ctypes.c_int64), ("capacity", ctypes.c_int64), ("r_list", ctypes.c_float),
     ]
 
 

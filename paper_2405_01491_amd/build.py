@@ -15,7 +15,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnnp.so")
 
-SOURCES = ["scan.hip", "neighbors.hip", "aev.hip", "mlp.hip", "mlp_fused.hip", "forces.hip", "serve.cpp", "api.cpp"]
+SOURCES = ["scan.hip", "neighbors.hip", "aev.hip", "mlp.hip", "mlp_fused.hip", "forces.hip", "md.hip",
+           "md_engine.cpp", "serve.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -448,6 +448,7 @@ nnp_status nnp_check(nnp_model* m, void* stream, uint32_t* flags) {
     if (!fl) return NNP_OK;
     if (fl & NNP_FLAG_NONFINITE) return NNP_E_NONFINITE;
     if (fl & NNP_FLAG_ROW) return NNP_E_ROW;
+    if (fl & NNP_FLAG_CAPACITY) return NNP_E_CAPACITY;
     return NNP_E_ARG;
 }
 

@@ -132,9 +132,9 @@ __device__ __forceinline__ int cell_coord(float x, double L, double inv_cs, int 
 
 // structure ranges for contiguous molecules; validates mol
 __global__ void k_mol_ranges(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end,
-                             unsigned* flags) {
+                             unsigned* flags, const int32_t* gate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (gate && *gate == 0)) return;
     const int m = mol[i];
     if (m < 0 || m >= n_mol) {
         set_flag(flags, NNP_FLAG_MOL);
@@ -148,9 +148,9 @@ __global__ void k_mol_ranges(const int32_t* mol, int n, int n_mol, int32_t* star
 }
 
 __global__ void k_bin(const float* pos, int n, const Grid g, int32_t* cell_of, int32_t* cell_slot,
-                      int32_t* cell_count, unsigned* flags) {
+                      int32_t* cell_count, unsigned* flags, const int32_t* gate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (gate && *gate == 0)) return;
     const float3 p = load_pos(pos, i);
     if (!finite3(p)) {
         set_flag(flags, NNP_FLAG_NONFINITE);
@@ -166,26 +166,28 @@ __global__ void k_bin(const float* pos, int n, const Grid g, int32_t* cell_of, i
 }
 
 __global__ void k_scatter(int n, const int32_t* cell_of, const int32_t* cell_slot, const int32_t* cell_start,
-                          int32_t* cell_atoms) {
+                          int32_t* cell_atoms, const int32_t* gate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (gate && *gate == 0)) return;
     const int c = cell_of[i];
     if (c >= 0) cell_atoms[cell_start[c] + cell_slot[i]] = i;
 }
 
-__global__ void k_finite(const float* pos, int n, unsigned* flags) {
+__global__ void k_finite(const float* pos, int n, unsigned* flags, const int32_t* gate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (gate && *gate == 0)) return;
     if (!finite3(load_pos(pos, i))) set_flag(flags, NNP_FLAG_NONFINITE);
 }
 
 // One wave per row.  Mode 0: count into row_count.  Mode 1: write the
-// sorted row at row_ptr[i].
+// sorted row at row_ptr[i]; only the first row_ptr[i+1] - row_ptr[i]
+// entries are written (a row cut short by a capacity clamp stays in bounds).
 template <int kMode>
 __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     const float* pos, int n, const int32_t* mol, int n_mol, const Grid g, double r2, const int32_t* cell_of,
     const int32_t* cell_start, const int32_t* cell_atoms, const int32_t* mol_start, const int32_t* mol_end,
-    int32_t* row_count, const int32_t* row_ptr, int32_t* col, int8_t* shift, unsigned* flags) {
+    int32_t* row_count, const int32_t* row_ptr, int32_t* col, int8_t* shift, unsigned* flags, const int32_t* gate) {
+    if (gate && *gate == 0) return;
     __shared__ int s_off[kRowsPerBlock][28];
     __shared__ int s_beg[kRowsPerBlock][28];
     __shared__ int s_col[kMode ? kRowsPerBlock : 1][kMode ? kRowLds : 1];
@@ -298,10 +300,12 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     if (overflow || count > kRowLds) return;   // reported in count mode
     // rank sort by neighbour index (indices in a row are distinct)
     const int base_out = row_ptr[i];
+    const int lim = row_ptr[i + 1] - base_out;
     for (int e = l; e < count; e += kWave) {
         const int je = s_col[w][e];
         int rank = 0;
         for (int f = 0; f < count; ++f) rank += s_col[w][f] < je;
+        if (rank >= lim) continue;
         col[base_out + rank] = je;
         const int sh = s_sh[w][e];
         shift[3 * (base_out + rank) + 0] = (int8_t)(sh & 0xff);
@@ -310,12 +314,13 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     }
 }
 
-// reverse index: rev[p] = slot of (j -> i) in row j
-__global__ void k_rev(int n, const int32_t* row_ptr, const int32_t* col, int32_t* rev) {
+// reverse index: rev[p] = slot of (j -> i) in row j (p itself if absent,
+// which only a capacity-clamped list can produce)
+__global__ void k_rev(int n, const int32_t* row_ptr, const int32_t* col, int32_t* rev, const int32_t* gate) {
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
     const int i = blockIdx.x * (blockDim.x / kWave) + w;
-    if (i >= n) return;
+    if (i >= n || (gate && *gate == 0)) return;
     const int b = row_ptr[i], e = row_ptr[i + 1];
     for (int p = b + l; p < e; p += kWave) {
         const int j = col[p];
@@ -326,6 +331,28 @@ __global__ void k_rev(int n, const int32_t* row_ptr, const int32_t* col, int32_t
         }
         rev[p] = (lo < row_ptr[j + 1] && col[lo] == i) ? lo : p;
     }
+}
+
+__global__ void k_fill_gated(int32_t* p, long n, int32_t v, const int32_t* gate) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || (gate && *gate == 0)) return;
+    p[i] = v;
+}
+
+// Asynchronous builds: if the pair total exceeds the capacity, cut the row
+// pointers at the capacity (every later read stays in bounds), raise
+// NNP_FLAG_CAPACITY and record the required size.
+__global__ void k_clamp_rows(int n, int32_t* row_ptr, const int64_t* total, int64_t capacity, int64_t* need,
+                             unsigned* flags, const int32_t* gate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n || (gate && *gate == 0)) return;
+    const long long t = *total;
+    if (t <= capacity) return;
+    if (i == 0) {
+        set_flag(flags, NNP_FLAG_CAPACITY);
+        if (need) atomicMax((unsigned long long*)need, (unsigned long long)t);
+    }
+    if (row_ptr[i] > capacity) row_ptr[i] = (int32_t)capacity;
 }
 
 struct WsLayout {
@@ -398,7 +425,8 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host,
-                           void* ws, size_t ws_bytes, hipStream_t s, bool sync, unsigned* flags_override) {
+                           void* ws, size_t ws_bytes, hipStream_t s, bool sync, unsigned* flags_override,
+                           const int32_t* gate, int64_t* need_pairs) {
     Grid g;
     nnp_status st = make_grid(box_host, r_list, &g);
     if (st != NNP_OK) return st;
@@ -424,26 +452,29 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
 
     hipError_t he = hipSuccess;
     auto chk = [&](hipError_t x) { if (he == hipSuccess) he = x; };
+    auto fill = [&](int32_t* p, long cnt) {
+        if (cnt > 0) k_fill_gated<<<(int)((cnt + 255) / 256), 256, 0, s>>>(p, cnt, 0, gate);
+    };
     prof_begin(model, NNP_STAGE_NEIGHBORS, s);
     if (n > 0) {
         if (mol) {
-            chk(hipMemsetAsync(mol_start, 0, sizeof(int32_t) * n_mol, s));
-            chk(hipMemsetAsync(mol_end, 0, sizeof(int32_t) * n_mol, s));
-            k_mol_ranges<<<nb, tb, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags);
+            fill(mol_start, n_mol);
+            fill(mol_end, n_mol);
+            k_mol_ranges<<<nb, tb, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags, gate);
         }
         if (g.periodic) {
-            chk(hipMemsetAsync(cell_count, 0, sizeof(int32_t) * (n_cells + 1), s));
-            k_bin<<<nb, tb, 0, s>>>(pos, n, g, cell_of, cell_slot, cell_count, flags);
-            chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s));
-            k_scatter<<<nb, tb, 0, s>>>(n, cell_of, cell_slot, cell_start, cell_atoms);
+            fill(cell_count, n_cells + 1);
+            k_bin<<<nb, tb, 0, s>>>(pos, n, g, cell_of, cell_slot, cell_count, flags, gate);
+            chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s, gate));
+            k_scatter<<<nb, tb, 0, s>>>(n, cell_of, cell_slot, cell_start, cell_atoms, gate);
         } else {
-            k_finite<<<nb, tb, 0, s>>>(pos, n, flags);
+            k_finite<<<nb, tb, 0, s>>>(pos, n, flags, gate);
         }
         k_rows<0><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
             pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count, nullptr, nullptr,
-            nullptr, flags);
+            nullptr, flags, gate);
     }
-    chk(launch_exclusive_scan_i32(row_count, nl->row_ptr, totals, n, scan_tmp, s));
+    chk(launch_exclusive_scan_i32(row_count, nl->row_ptr, totals, n, scan_tmp, s, gate));
     chk(hipGetLastError());
     if (he != hipSuccess) {
         prof_end(model, NNP_STAGE_NEIGHBORS, s);
@@ -452,15 +483,18 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     int64_t total = 0;
     uint32_t fl = 0;
     if (!sync) {
-        // caller guarantees the capacity (e.g. all pairs of every structure) and checks flags itself
+        // the pair count is not read back: a list longer than the capacity is cut
+        // short in bounds and flagged (NNP_FLAG_CAPACITY) for the caller to check
         nl->n_atoms = n;
         nl->r_list = r_list;
         nl->n_pairs = -1;
+        k_clamp_rows<<<ceil_div(n + 1, 256), 256, 0, s>>>(n, nl->row_ptr, totals, nl->capacity, need_pairs, flags,
+                                                          gate);
         if (n > 0) {
             k_rows<1><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
                 pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, nullptr, nl->row_ptr,
-                nl->col, nl->shift, flags);
-            k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev);
+                nl->col, nl->shift, flags, gate);
+            k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev, gate);
         }
         prof_end(model, NNP_STAGE_NEIGHBORS, s);
         return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
@@ -484,8 +518,8 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     if (n > 0 && total > 0) {
         k_rows<1><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
             pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, nullptr, nl->row_ptr,
-            nl->col, nl->shift, flags);
-        k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev);
+            nl->col, nl->shift, flags, nullptr);
+        k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev, nullptr);
     }
     prof_end(model, NNP_STAGE_NEIGHBORS, s);
     return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;

@@ -140,7 +140,7 @@ void prof_begin(nnp_model* m, int stage, hipStream_t s);
 void prof_end(nnp_model* m, int stage, hipStream_t s);
 
 hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
-                                     int64_t* block_tmp, hipStream_t s);
+                                     int64_t* block_tmp, hipStream_t s, const int32_t* gate = nullptr);
 size_t scan_tmp_elems(int n);
 
 size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list);
@@ -148,7 +148,8 @@ size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host,
 // device flags go to flags_override (or the model's flags if null).
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host, void* ws,
-                           size_t ws_bytes, hipStream_t s, bool sync = true, unsigned* flags_override = nullptr);
+                           size_t ws_bytes, hipStream_t s, bool sync = true, unsigned* flags_override = nullptr,
+                           const int32_t* gate = nullptr, int64_t* need_pairs = nullptr);
 // nnp_energy_forces with an explicit device flags word (n_pairs of nl is not checked)
 nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
                               int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,

@@ -39,7 +39,9 @@ __device__ long long block_exclusive(long long v, long long* tot) {
     return off + inc - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_block_sums(const int32_t* in, int n, int64_t* bsum) {
+__global__ __launch_bounds__(kScanThreads) void k_block_sums(const int32_t* in, int n, int64_t* bsum,
+                                                             const int32_t* gate) {
+    if (gate && *gate == 0) return;
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
     long long s = 0;
 #pragma unroll
@@ -51,7 +53,8 @@ __global__ __launch_bounds__(kScanThreads) void k_block_sums(const int32_t* in, 
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t* bsum, int nb, int64_t* total,
-                                                            int32_t* out_last) {
+                                                            int32_t* out_last, const int32_t* gate) {
+    if (gate && *gate == 0) return;
     long long carry = 0;
     for (int c0 = 0; c0 < nb; c0 += kScanThreads) {
         const int i = c0 + threadIdx.x;
@@ -68,7 +71,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t* bsum, int n
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_block_scan(const int32_t* in, int n, const int64_t* boff,
-                                                             int32_t* out) {
+                                                             int32_t* out, const int32_t* gate) {
+    if (gate && *gate == 0) return;
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
     int32_t v[kScanItems];
     long long s = 0;
@@ -90,7 +94,8 @@ __global__ __launch_bounds__(kScanThreads) void k_block_scan(const int32_t* in, 
 constexpr int kSmallThreads = 1024, kSmallItems = 8;
 
 __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int32_t* in, int n, int32_t* out,
-                                                              int64_t* total) {
+                                                              int64_t* total, const int32_t* gate) {
+    if (gate && *gate == 0) return;
     __shared__ long long wsum[kSmallThreads / kWave];
     const int t = threadIdx.x, w = t / kWave;
     const int base = t * kSmallItems;
@@ -126,16 +131,17 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int32_t* in,
 size_t scan_tmp_elems(int n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanBlock) + 1; }
 
 // out has n + 1 entries; out[n] = total (saturated to int32); *total_out (device) = exact total.
+// With a gate, every kernel does nothing while *gate == 0.
 hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
-                                     int64_t* block_tmp, hipStream_t s) {
+                                     int64_t* block_tmp, hipStream_t s, const int32_t* gate) {
     if (n <= kSmallThreads * kSmallItems) {
-        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, n, out, total_out);
+        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, n, out, total_out, gate);
         return hipGetLastError();
     }
     const int nb = ceil_div(n > 0 ? n : 1, kScanBlock);
-    k_block_sums<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp);
-    k_scan_sums<<<1, kScanThreads, 0, s>>>(block_tmp, nb, total_out, out + n);
-    k_block_scan<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp, out);
+    k_block_sums<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp, gate);
+    k_scan_sums<<<1, kScanThreads, 0, s>>>(block_tmp, nb, total_out, out + n, gate);
+    k_block_scan<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp, out, gate);
     return hipGetLastError();
 }
 

@@ -125,3 +125,77 @@ def profile_read(model):
     cnt = (ctypes.c_int64 * len(_lib.STAGES))()
     check(lib().nnp_profile_read(model.handle, ms, cnt), "nnp_profile_read")
     return {name: (ms[k], cnt[k]) for k, name in enumerate(_lib.STAGES)}
+
+
+class MDEngine:
+    """The native engine (nnp_md_*): NVE velocity Verlet or BAOAB Langevin
+    dynamics with the whole step on the GPU; ``run(k)`` enqueues k steps and
+    synchronises once.  State lives in the engine; ``state()`` copies it out."""
+
+    def __init__(self, model, pos, vel, species, masses, box=None, dt=0.5, integrator="nve", temperature=300.0,
+                 friction=1.0, seed=0, skin=0.0, rebuild_every=1, trigger=0.8, log_every=0, log_capacity=0,
+                 capacity_slack=0.25):
+        L = lib()
+        self.model = model
+        self.dev = pos.device
+        self.n = pos.shape[0]
+        m = torch.as_tensor(np.asarray(masses, dtype=np.float32)).to(self.dev)
+        p = _lib.MdParams()
+        p.integrator = {"nve": 0, "langevin": 1}[integrator]
+        p.dt, p.temperature, p.friction, p.seed = float(dt), float(temperature), float(friction), int(seed)
+        p.skin, p.rebuild_every, p.trigger = float(skin), int(rebuild_every), float(trigger)
+        p.log_every, p.log_capacity, p.capacity_slack = int(log_every), int(log_capacity), float(capacity_slack)
+        self.params = p
+        self.box = None if box is None else np.asarray(box, dtype=np.float32)
+        bptr = None if box is None else (ctypes.c_float * 3)(*self.box.tolist())
+        h = ctypes.c_void_p()
+        pos = pos.contiguous()
+        vel = vel.contiguous()
+        species = species.contiguous()
+        with torch.cuda.device(self.dev):
+            check(L.nnp_md_create(model.handle, self.n, ctypes.c_void_p(pos.data_ptr()),
+                                  ctypes.c_void_p(vel.data_ptr()), ctypes.c_void_p(species.data_ptr()),
+                                  ctypes.c_void_p(m.data_ptr()), bptr, ctypes.byref(p), _s(self.dev),
+                                  ctypes.byref(h)), "nnp_md_create")
+        self.handle = h
+
+    def run(self, n_steps):
+        with torch.cuda.device(self.dev):
+            check(lib().nnp_md_run(self.handle, int(n_steps), _s(self.dev)), "nnp_md_run")
+
+    def state(self):
+        """(pos, vel, forces, e_pot) as new device tensors."""
+        pos = torch.empty((self.n, 3), dtype=torch.float32, device=self.dev)
+        vel = torch.empty_like(pos)
+        F = torch.empty_like(pos)
+        e = torch.empty(1, dtype=torch.float64, device=self.dev)
+        with torch.cuda.device(self.dev):
+            check(lib().nnp_md_get(self.handle, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vel.data_ptr()),
+                                   ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(e.data_ptr()), _s(self.dev)),
+                  "nnp_md_get")
+        return pos, vel, F, e
+
+    def log(self):
+        """Logged rows [k, 2]: (E_pot, E_kin) in eV."""
+        cap = max(int(self.params.log_capacity), 1)
+        buf = np.zeros((cap, 2), dtype=np.float64)
+        rows = ctypes.c_int32(0)
+        check(lib().nnp_md_log(self.handle, ctypes.c_void_p(buf.ctypes.data), cap, ctypes.byref(rows),
+                               _s(self.dev)), "nnp_md_log")
+        return buf[:rows.value].copy()
+
+    def info(self):
+        st = _lib.MdStats()
+        check(lib().nnp_md_info(self.handle, ctypes.byref(st), _s(self.dev)), "nnp_md_info")
+        return {k: getattr(st, k) for k, _ in _lib.MdStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nnp_md_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

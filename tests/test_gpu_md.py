@@ -87,3 +87,114 @@ def test_stage_profiling_counts(spec):
     st = nmd.profile_read(model)
     assert st["neighbors"][1] == 1 and st["aev"][1] == 3 and st["mlp"][1] == 3 and st["forces"][1] == 3
     assert all(v[0] >= 0 for v in st.values())
+
+
+# ---------------------------------------------------------------- native engine (nnp_md_*)
+
+def _engine(model, w, v0, **kw):
+    pos, sp, _ = to_dev(w)
+    return nmd.MDEngine(model, pos, torch.from_numpy(np.ascontiguousarray(v0)).to(dev()), sp,
+                        synthetic.MASSES[w.species], w.box, **kw)
+
+
+def _min_image(d, box):
+    return d if box is None else d - box * np.round(d / box)
+
+
+def test_engine_nve_tracks_oracle(spec_bias):
+    w = synthetic.workload(1)
+    model = nnp.Model(spec_bias, "fp32")
+    masses = synthetic.MASSES[w.species]
+    v0 = nmd.maxwell_boltzmann(masses, 300.0, seed=5)
+    eng = _engine(model, w, v0, dt=0.5)
+    eng.run(10)
+    x, v, F, e = [t.cpu().numpy() for t in eng.state()]
+    nl = oracle.neighbor_list(w.pos, None, None, 9.0)
+    xr, vr, en = oracle.velocity_verlet(w.pos, v0, masses,
+                                        lambda y: oracle.energy_forces_f64(y, w.species, None, spec_bias, nl),
+                                        0.5, 10)
+    print("engine NVE 10 steps: max |dx| %.3g A, max |dv| %.3g A/fs" % (np.abs(x - xr).max(), np.abs(v - vr).max()))
+    assert np.abs(x - xr).max() < 1e-4 and np.abs(v - vr).max() < 1e-5
+    assert abs(float(e[0]) - en[-1][0]) < 1e-4 * max(1.0, abs(en[-1][0]))
+    assert eng.info()["steps"] == 10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_engine_langevin_tracks_oracle(spec_bias, precision):
+    w = synthetic.geometry.small_water_box(40)
+    model = nnp.Model(spec_bias, precision)
+    masses = synthetic.MASSES[w.species]
+    v0 = nmd.maxwell_boltzmann(masses, 300.0, seed=8)
+    eng = _engine(model, w, v0, dt=0.5, integrator="langevin", temperature=300.0, friction=20.0, seed=77,
+                  skin=0.5, rebuild_every=5)
+    eng.run(6)
+    eng.run(4)                      # the noise stream continues across runs
+    x, v, F, e = [t.cpu().numpy() for t in eng.state()]
+    nl = oracle.neighbor_list(w.pos, None, w.box, 5.6)
+    xr, vr, en = oracle.langevin_baoab(
+        w.pos, v0, masses,
+        lambda y: oracle.energy_forces_f64(y, w.species, w.box, spec_bias, nl,
+                                           precision="bf16" if precision == "bf16" else "fp64"),
+        0.5, 10, 300.0, 20.0, seed=77)
+    dx = np.abs(_min_image(x - xr, w.box)).max()
+    dv = np.abs(v - vr).max()
+    print("engine Langevin %s 10 steps: max |dx| %.3g A, max |dv| %.3g A/fs, info %s"
+          % (precision, dx, dv, eng.info()))
+    tol = 1 if precision == "fp32" else 20
+    assert dx < 1e-4 * tol and dv < 1e-5 * tol
+
+
+def test_engine_replay_after_regrow_is_exact(spec):
+    """A list that must regrow mid-run rolls the run back and replays it: the
+    result is bit-identical to a run that never regrew."""
+    w = synthetic.geometry.small_water_box(64)
+    masses = synthetic.MASSES[w.species]
+    v0 = nmd.maxwell_boltzmann(masses, 600.0, seed=9)
+    out = []
+    for slack in (0.0, 0.5):
+        model = nnp.Model(spec, "fp32")
+        eng = _engine(model, w, v0, dt=0.5, integrator="langevin", temperature=600.0, friction=5.0, seed=3,
+                      rebuild_every=1, capacity_slack=slack)
+        for _ in range(3):
+            eng.run(10)
+        out.append(([t.cpu() for t in eng.state()], eng.info()))
+    print("replays with no slack: %d, with slack: %d" % (out[0][1]["replays"], out[1][1]["replays"]))
+    assert out[1][1]["replays"] == 0
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
+
+
+def test_engine_nve_energy_log(spec):
+    w = synthetic.geometry.small_water_box(64)
+    model = nnp.Model(spec, "fp32")
+    masses = synthetic.MASSES[w.species]
+    v0 = nmd.maxwell_boltzmann(masses, 300.0, seed=6)
+    eng = _engine(model, w, v0, dt=0.25, log_every=20, log_capacity=10)
+    eng.run(200)
+    rows = eng.log()
+    assert rows.shape == (10, 2)
+    tot = rows.sum(1)
+    ke = rows[:, 1].mean()
+    drift = np.abs(tot - tot[0]).max()
+    print("engine NVE 200 steps: drift %.3g eV (KE %.3g eV)" % (drift, ke))
+    assert drift < 0.02 * max(ke, 1.0)
+    # the log's last row is the state's energies
+    _, v, _, e = eng.state()
+    assert abs(rows[-1, 0] - float(e[0])) < 1e-12 * max(1.0, abs(rows[-1, 0]))
+    ke_now = float(0.5 * (torch.from_numpy(masses).double()[:, None] * v.cpu().double() ** 2).sum()
+                   / nmd.ACC_UNIT)
+    assert abs(rows[-1, 1] - ke_now) < 1e-6 * ke_now
+
+
+def test_engine_langevin_thermalises(spec):
+    """A cold start heats to the bath temperature (equipartition, 3N/2 kT)."""
+    w = synthetic.geometry.small_water_box(64)
+    model = nnp.Model(spec, "fp32")
+    v0 = np.zeros((w.n_atoms, 3), np.float32)
+    eng = _engine(model, w, v0, dt=0.5, integrator="langevin", temperature=300.0, friction=100.0, seed=12,
+                  skin=0.5, rebuild_every=20, log_every=10, log_capacity=100)
+    eng.run(600)
+    ke = eng.log()[-30:, 1].mean()
+    want = 1.5 * w.n_atoms * nmd.KB_EV * 300.0
+    print("Langevin cold start: <KE> %.4f eV, 3N kT/2 %.4f eV, info %s" % (ke, want, eng.info()))
+    assert abs(ke / want - 1.0) < 0.15

@@ -483,3 +483,65 @@ def test_velocity_verlet_second_order_and_reversible(spec_bias):
     xT, vT, _ = oracle.velocity_verlet(m[0], v0, masses, ff64, 0.1, 20)
     xb, vb, _ = oracle.velocity_verlet(xT, -vT, masses, ff64, 0.1, 20)
     assert np.max(np.abs(xb - m[0].astype(np.float64))) < 1e-9
+
+
+def _philox4x64_10(ctr, key):
+    """Philox4x64-10 from its published definition (Salmon, Moraes, Dror and
+    Shaw, SC'11): 10 rounds of two 64x64->128 multiplies with a Weyl key
+    schedule.  Independent of numpy's implementation used by the oracle."""
+    M = (1 << 64) - 1
+    c0, c1, c2, c3 = ctr
+    k0, k1 = key
+    for r in range(10):
+        if r:
+            k0, k1 = (k0 + 0x9E3779B97F4A7C15) & M, (k1 + 0xBB67AE8584CAA73B) & M
+        p0, p1 = 0xD2E7470EE14C6C93 * c0, 0xCA5A826395121157 * c2
+        c0, c1, c2, c3 = (p1 >> 64) ^ c1 ^ k0, p1 & M, (p0 >> 64) ^ c3 ^ k1, p0 & M
+    return [c0, c1, c2, c3]
+
+
+def test_philox_stream_definition():
+    from oracle.md import philox_block
+    # known-answer vector published with the Random123 library: counter 0, key 0
+    assert _philox4x64_10([0, 0, 0, 0], [0, 0]) == [0x16554D9ECA36314C, 0xDB20FE9D672D0FDC,
+                                                   0xD7E772CEE186176B, 0x7E68B68AEC7BA23B]
+    for seed, step, atom in [(0, 0, 0), (2024, 7, 3), (2 ** 63 + 5, 123456, 99999)]:
+        assert [int(x) for x in philox_block(seed, step, atom)] == _philox4x64_10([atom + 1, step, 0, 0], [seed, 0])
+
+
+def test_baoab_without_friction_is_velocity_verlet(spec_bias):
+    rng = np.random.default_rng(4)
+    m = synthetic.serving_molecule(rng, n=10)
+    masses = synthetic.MASSES[m[1]]
+    nl = oracle.neighbor_list(m[0], None, None, 9.0)
+
+    def ff64(x):
+        return oracle.energy_forces_f64(x, m[1], None, spec_bias, nl)
+    v0 = rng.normal(scale=0.01, size=(10, 3))
+    xa, va, ea = oracle.velocity_verlet(m[0], v0, masses, ff64, 0.5, 6)
+    xb, vb, eb = oracle.langevin_baoab(m[0], v0, masses, ff64, 0.5, 6, 300.0, 0.0, seed=1)
+    assert np.max(np.abs(xa - xb)) < 1e-12 and np.max(np.abs(va - vb)) < 1e-13
+    assert np.max(np.abs(np.array(ea) - np.array(eb))) < 1e-10
+
+
+def test_baoab_free_particles(spec):
+    """No forces: at T = 0 the O step is the exact decay v -> exp(-gamma t) v
+    (gamma in 1/ps, t in fs); at T > 0 the velocities relax to the
+    Maxwell-Boltzmann variance kT/m (equipartition) with standard normal noise."""
+    n = 1500
+    rng = np.random.default_rng(5)
+    masses = rng.choice(synthetic.MASSES, size=n)
+    x0 = rng.uniform(0, 10, size=(n, 3))
+    v0 = rng.normal(scale=0.02, size=(n, 3))
+
+    def free(x):
+        return 0.0, np.zeros_like(x)
+    _, v, _ = oracle.langevin_baoab(x0, v0, masses, free, 0.5, 4, 0.0, 50.0, seed=3)
+    assert np.max(np.abs(v - v0 * np.exp(-50.0 * 1e-3 * 0.5 * 4))) < 1e-15
+    xi = oracle.langevin_noise(11, 2, n)
+    assert abs(xi.mean()) < 4 / np.sqrt(3 * n) and abs(xi.var() - 1.0) < 6 * np.sqrt(2 / (3 * n))
+    T = 300.0
+    _, v, _ = oracle.langevin_baoab(x0, np.zeros((n, 3)), masses, free, 1.0, 40, T, 200.0, seed=9)
+    z = v * np.sqrt(masses[:, None] / (oracle.md.KB_EV * T * oracle.md.ACC_UNIT))
+    want = 1.0 - np.exp(-2 * 200.0 * 1e-3 * 1.0 * 40)
+    assert abs(z.var() - want) < 6 * np.sqrt(2 / (3 * n))
