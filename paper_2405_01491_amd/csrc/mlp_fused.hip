@@ -76,6 +76,8 @@ __device__ __forceinline__ f32x4 mfma_step<true>(const uint16_t* act, int ld, in
 
 // C[TM x (NCB*16 columns of this wave)] = A[TM x K] (LDS, stride ld) * B (packed, global)
 // FP32 pack: [nb][K/16][64 lanes][4]   BF16 pack: [nb][K/32][64 lanes][8]
+// The next k-step's B fragments are loaded before the current step's MFMAs
+// (register double buffering), so their latency hides behind the MFMAs.
 template <bool BF, int MB, int NCB, int K>
 __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int ld, const void* Bpack, int nb0,
                                          f32x4 (&acc)[MB][NCB]) {
@@ -85,11 +87,17 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
 #pragma unroll
         for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
     if (!BF) {
+        constexpr int NK = K / 16;
         const float4* B = (const float4*)Bpack;
-        for (int kq = 0; kq < K / 16; ++kq) {
-            float4 b[NCB];
+        float4 b[NCB], bn[NCB];
 #pragma unroll
-            for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * (K / 16) + kq) * 64 + l];
+        for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * NK + 0) * 64 + l];
+        for (int kq = 0; kq < NK; ++kq) {
+            if (kq + 1 < NK) {
+#pragma unroll
+                for (int nb = 0; nb < NCB; ++nb) bn[nb] = B[((size_t)(nb0 + nb) * NK + kq + 1) * 64 + l];
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = 16 * kq + 4 * j + (l >> 4);
@@ -103,24 +111,32 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
                     }
                 }
             }
+#pragma unroll
+            for (int nb = 0; nb < NCB; ++nb) b[nb] = bn[nb];
         }
     } else {
+        constexpr int NK = K / 32;
         const u16x8* B = (const u16x8*)Bpack;
-        for (int ks = 0; ks < K / 32; ++ks) {
-            bf16x8 b[NCB];
+        u16x8 b[NCB], bn[NCB];
 #pragma unroll
-            for (int nb = 0; nb < NCB; ++nb) {
-                const u16x8 v = B[((size_t)(nb0 + nb) * (K / 32) + ks) * 64 + l];
-                b[nb] = __builtin_bit_cast(bf16x8, v);
+        for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * NK + 0) * 64 + l];
+        for (int ks = 0; ks < NK; ++ks) {
+            if (ks + 1 < NK) {
+#pragma unroll
+                for (int nb = 0; nb < NCB; ++nb) bn[nb] = B[((size_t)(nb0 + nb) * NK + ks + 1) * 64 + l];
             }
+            __builtin_amdgcn_sched_barrier(0);
             const int k = 32 * ks + 8 * (l >> 4);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const bf16x8 a = *(const bf16x8*)((const uint16_t*)act + (16 * mb + (l & 15)) * ld + k);
 #pragma unroll
                 for (int nb = 0; nb < NCB; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b[nb]),
+                                                                          acc[mb][nb], 0, 0, 0);
             }
+#pragma unroll
+            for (int nb = 0; nb < NCB; ++nb) b[nb] = bn[nb];
         }
     }
 }
@@ -213,6 +229,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) h1[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        // B fragments of global k-step t (FP32: 16 k per step; BF16: 32), prefetched one step ahead
+        constexpr int KS = BF ? 32 : 16;
+        constexpr int NT = K0 / KS, TPC = CH / KS;
+        float4 bf[4], bfn[4];
+        u16x8 bb[4], bbn[4];
+        auto loadB = [&](int t, float4 (&df)[4], u16x8 (&db)[4]) {
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                if (!BF) df[nb] = Bf[((size_t)(4 * w + nb) * NT + t) * 64 + l];
+                else db[nb] = Bb[((size_t)(4 * w + nb) * NT + t) * 64 + l];
+            }
+        };
+        loadB(0, bf, bb);
         gload(0);
         sstore(0);
         __syncthreads();
@@ -220,13 +249,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         for (int c = 0; c < NCH; ++c) {
             if (c + 1 < NCH) gload(c + 1);
             const act_t* cur = stage + (c & 1) * TM * CLD;
-            if (!BF) {
 #pragma unroll
-                for (int kq = 0; kq < CH / 16; ++kq) {
-                    float4 b[4];
-#pragma unroll
-                    for (int nb = 0; nb < 4; ++nb)
-                        b[nb] = Bf[((size_t)(4 * w + nb) * (K0 / 16) + (c * CH / 16 + kq)) * 64 + l];
+            for (int kq = 0; kq < TPC; ++kq) {
+                const int t = c * TPC + kq;
+                if (t + 1 < NT) loadB(t + 1, bfn, bbn);
+                __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
+                if (!BF) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int k = 16 * kq + 4 * j + (l >> 4);
@@ -235,28 +263,26 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                             const float a = ((const float*)cur)[(16 * mb + (l & 15)) * CLD + k];
 #pragma unroll
                             for (int nb = 0; nb < 4; ++nb) {
-                                const float bv = j == 0 ? b[nb].x : j == 1 ? b[nb].y : j == 2 ? b[nb].z : b[nb].w;
+                                const float bv = j == 0 ? bf[nb].x : j == 1 ? bf[nb].y : j == 2 ? bf[nb].z : bf[nb].w;
                                 h1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, h1[mb][nb], 0, 0, 0);
                             }
                         }
                     }
-                }
-            } else {
-#pragma unroll
-                for (int ks = 0; ks < CH / 32; ++ks) {
-                    bf16x8 b[4];
-#pragma unroll
-                    for (int nb = 0; nb < 4; ++nb)
-                        b[nb] = __builtin_bit_cast(
-                            bf16x8, Bb[((size_t)(4 * w + nb) * (K0 / 32) + (c * CH / 32 + ks)) * 64 + l]);
-                    const int k = 32 * ks + 8 * (l >> 4);
+                } else {
+                    const int k = 32 * kq + 8 * (l >> 4);
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) {
                         const bf16x8 a = *(const bf16x8*)((const uint16_t*)cur + (16 * mb + (l & 15)) * CLD + k);
 #pragma unroll
                         for (int nb = 0; nb < 4; ++nb)
-                            h1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], h1[mb][nb], 0, 0, 0);
+                            h1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a, __builtin_bit_cast(bf16x8, bb[nb]), h1[mb][nb], 0, 0, 0);
                     }
+                }
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) {
+                    bf[nb] = bfn[nb];
+                    bb[nb] = bbn[nb];
                 }
             }
             if (c + 1 < NCH) sstore((c + 1) & 1);

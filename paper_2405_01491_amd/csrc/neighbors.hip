@@ -18,7 +18,7 @@ namespace nnp {
 namespace {
 
 constexpr int kRowsPerBlock = 4;              // one wave per row
-constexpr int kRowLds = 1024;                 // longest row the builder handles
+constexpr int kRowLds = NNP_MAX_ROW;          // longest row the builder handles (staging stride)
 constexpr int kMaxCellsPerDim = 128;
 
 struct Grid {
@@ -179,19 +179,20 @@ __global__ void k_finite(const float* pos, int n, unsigned* flags, const int32_t
     if (!finite3(load_pos(pos, i))) set_flag(flags, NNP_FLAG_NONFINITE);
 }
 
-// One wave per row.  Mode 0: count into row_count.  Mode 1: write the
-// sorted row at row_ptr[i]; only the first row_ptr[i+1] - row_ptr[i]
-// entries are written (a row cut short by a capacity clamp stays in bounds).
-template <int kMode>
+// One wave per row: the row's pairs are found once, rank-sorted by
+// neighbour index in LDS and written to a fixed-stride staging row
+// (stage_col / stage_sh at i * kRowLds) with their count; k_compact then
+// copies the rows to their CSR offsets.  A row longer than kRowLds raises
+// NNP_FLAG_ROW and is left empty.
 __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     const float* pos, int n, const int32_t* mol, int n_mol, const Grid g, double r2, const int32_t* cell_of,
     const int32_t* cell_start, const int32_t* cell_atoms, const int32_t* mol_start, const int32_t* mol_end,
-    int32_t* row_count, const int32_t* row_ptr, int32_t* col, int8_t* shift, unsigned* flags, const int32_t* gate) {
+    int32_t* row_count, int32_t* stage_col, int32_t* stage_sh, unsigned* flags, const int32_t* gate) {
     if (gate && *gate == 0) return;
     __shared__ int s_off[kRowsPerBlock][28];
     __shared__ int s_beg[kRowsPerBlock][28];
-    __shared__ int s_col[kMode ? kRowsPerBlock : 1][kMode ? kRowLds : 1];
-    __shared__ int s_sh[kMode ? kRowsPerBlock : 1][kMode ? kRowLds : 1];
+    __shared__ int s_col[kRowsPerBlock][kRowLds];
+    __shared__ int s_sh[kRowsPerBlock][kRowLds];
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
     const int i = blockIdx.x * kRowsPerBlock + w;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     if (g.periodic) {
         const int ci = cell_of[i];
         if (ci < 0) {
-            if (kMode == 0 && l == 0) row_count[i] = 0;
+            if (l == 0) row_count[i] = 0;
             return;
         }
         const int cz = ci % g.nc[2];
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
             }
         }
         const unsigned long long m = ballot(keep);
-        if (kMode == 1 && keep) {
+        if (keep) {
             const int pos_in_row = count + rank_below(m);
             if (pos_in_row < kRowLds) {
                 s_col[w][pos_in_row] = j;
@@ -292,44 +293,62 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
         }
         count += __popcll(m);
     }
-    if (kMode == 0) {
-        if (l == 0) row_count[i] = count;
-        if (count > kRowLds && l == 0) set_flag(flags, NNP_FLAG_ROW);
+    if (overflow || count > kRowLds) {
+        if (l == 0) {
+            set_flag(flags, NNP_FLAG_ROW);
+            row_count[i] = 0;
+        }
         return;
     }
-    if (overflow || count > kRowLds) return;   // reported in count mode
+    wave_sync();
     // rank sort by neighbour index (indices in a row are distinct)
-    const int base_out = row_ptr[i];
-    const int lim = row_ptr[i + 1] - base_out;
+    int32_t* oc = stage_col + (size_t)i * kRowLds;
+    int32_t* os = stage_sh + (size_t)i * kRowLds;
     for (int e = l; e < count; e += kWave) {
         const int je = s_col[w][e];
         int rank = 0;
         for (int f = 0; f < count; ++f) rank += s_col[w][f] < je;
-        if (rank >= lim) continue;
-        col[base_out + rank] = je;
-        const int sh = s_sh[w][e];
-        shift[3 * (base_out + rank) + 0] = (int8_t)(sh & 0xff);
-        shift[3 * (base_out + rank) + 1] = (int8_t)((sh >> 8) & 0xff);
-        shift[3 * (base_out + rank) + 2] = (int8_t)((sh >> 16) & 0xff);
+        oc[rank] = je;
+        os[rank] = s_sh[w][e];
     }
+    if (l == 0) row_count[i] = count;
 }
 
-// reverse index: rev[p] = slot of (j -> i) in row j (p itself if absent,
-// which only a capacity-clamped list can produce)
-__global__ void k_rev(int n, const int32_t* row_ptr, const int32_t* col, int32_t* rev, const int32_t* gate) {
+// Staging rows -> CSR at row_ptr (only the first row_ptr[i+1] - row_ptr[i]
+// entries: a row cut short by a capacity clamp stays in bounds), and the
+// reverse index: rev[p] of i -> j is the position of i in j's sorted staging
+// row (p itself if absent, which only a clamped list can produce).
+__global__ __launch_bounds__(kRowsPerBlock* kWave) void k_compact(
+    int n, const int32_t* __restrict__ row_count, const int32_t* __restrict__ stage_col,
+    const int32_t* __restrict__ stage_sh, const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+    int8_t* __restrict__ shift, int32_t* __restrict__ rev, const int32_t* gate) {
+    if (gate && *gate == 0) return;
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
-    const int i = blockIdx.x * (blockDim.x / kWave) + w;
-    if (i >= n || (gate && *gate == 0)) return;
-    const int b = row_ptr[i], e = row_ptr[i + 1];
-    for (int p = b + l; p < e; p += kWave) {
-        const int j = col[p];
-        int lo = row_ptr[j], hi = row_ptr[j + 1];
+    const int i = blockIdx.x * kRowsPerBlock + w;
+    if (i >= n) return;
+    const int b = row_ptr[i];
+    const int lim = row_ptr[i + 1] - b;
+    const int cnt = min(row_count[i], lim);
+    const int32_t* sc = stage_col + (size_t)i * kRowLds;
+    const int32_t* ss = stage_sh + (size_t)i * kRowLds;
+    for (int e = l; e < cnt; e += kWave) {
+        const int j = sc[e];
+        const int sh = ss[e];
+        const int p = b + e;
+        col[p] = j;
+        shift[3 * p + 0] = (int8_t)(sh & 0xff);
+        shift[3 * p + 1] = (int8_t)((sh >> 8) & 0xff);
+        shift[3 * p + 2] = (int8_t)((sh >> 16) & 0xff);
+        const int32_t* rj = stage_col + (size_t)j * kRowLds;
+        const int bj = row_ptr[j];
+        const int cj = min(row_count[j], row_ptr[j + 1] - bj);
+        int lo = 0, hi = cj;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (col[mid] < i) lo = mid + 1; else hi = mid;
+            if (rj[mid] < i) lo = mid + 1; else hi = mid;
         }
-        rev[p] = (lo < row_ptr[j + 1] && col[lo] == i) ? lo : p;
+        rev[p] = (lo < cj && rj[lo] == i) ? bj + lo : p;
     }
 }
 
@@ -356,8 +375,8 @@ __global__ void k_clamp_rows(int n, int32_t* row_ptr, const int64_t* total, int6
 }
 
 struct WsLayout {
-    size_t cell_count, cell_start, cell_of, cell_slot, cell_atoms, row_count, mol_start, mol_end,
-        scan_tmp, totals, end;
+    size_t cell_count, cell_start, cell_of, cell_slot, cell_atoms, row_count, stage_col, stage_sh, mol_start,
+        mol_end, scan_tmp, totals, end;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -373,6 +392,8 @@ WsLayout ws_layout(int n, int n_mol, long n_cells) {
     L.cell_slot = take(sizeof(int32_t) * nn);
     L.cell_atoms = take(sizeof(int32_t) * nn);
     L.row_count = take(sizeof(int32_t) * nn);
+    L.stage_col = take(sizeof(int32_t) * (size_t)nn * kRowLds);
+    L.stage_sh = take(sizeof(int32_t) * (size_t)nn * kRowLds);
     L.mol_start = take(sizeof(int32_t) * (n_mol > 0 ? n_mol : 1));
     L.mol_end = take(sizeof(int32_t) * (n_mol > 0 ? n_mol : 1));
     const long sn = n_cells > nn ? n_cells : nn;
@@ -440,6 +461,8 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     int32_t* cell_slot = (int32_t*)(base + L.cell_slot);
     int32_t* cell_atoms = (int32_t*)(base + L.cell_atoms);
     int32_t* row_count = (int32_t*)(base + L.row_count);
+    int32_t* stage_col = (int32_t*)(base + L.stage_col);
+    int32_t* stage_sh = (int32_t*)(base + L.stage_sh);
     int32_t* mol_start = (int32_t*)(base + L.mol_start);
     int32_t* mol_end = (int32_t*)(base + L.mol_end);
     int64_t* scan_tmp = (int64_t*)(base + L.scan_tmp);
@@ -470,9 +493,9 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         } else {
             k_finite<<<nb, tb, 0, s>>>(pos, n, flags, gate);
         }
-        k_rows<0><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
-            pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count, nullptr, nullptr,
-            nullptr, flags, gate);
+        k_rows<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
+            pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count, stage_col,
+            stage_sh, flags, gate);
     }
     chk(launch_exclusive_scan_i32(row_count, nl->row_ptr, totals, n, scan_tmp, s, gate));
     chk(hipGetLastError());
@@ -490,12 +513,9 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         nl->n_pairs = -1;
         k_clamp_rows<<<ceil_div(n + 1, 256), 256, 0, s>>>(n, nl->row_ptr, totals, nl->capacity, need_pairs, flags,
                                                           gate);
-        if (n > 0) {
-            k_rows<1><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
-                pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, nullptr, nl->row_ptr,
-                nl->col, nl->shift, flags, gate);
-            k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev, gate);
-        }
+        if (n > 0)
+            k_compact<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
+                n, row_count, stage_col, stage_sh, nl->row_ptr, nl->col, nl->shift, nl->rev, gate);
         prof_end(model, NNP_STAGE_NEIGHBORS, s);
         return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
     }
@@ -515,12 +535,9 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         return NNP_E_ARG;
     }
     if (total > nl->capacity || total > 0x7fffffffLL) return NNP_E_CAPACITY;
-    if (n > 0 && total > 0) {
-        k_rows<1><<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
-            pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, nullptr, nl->row_ptr,
-            nl->col, nl->shift, flags, nullptr);
-        k_rev<<<ceil_div(n, 4), 4 * kWave, 0, s>>>(n, nl->row_ptr, nl->col, nl->rev, nullptr);
-    }
+    if (n > 0 && total > 0)
+        k_compact<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
+            n, row_count, stage_col, stage_sh, nl->row_ptr, nl->col, nl->shift, nl->rev, nullptr);
     prof_end(model, NNP_STAGE_NEIGHBORS, s);
     return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
 }
