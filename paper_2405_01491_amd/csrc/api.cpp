@@ -10,6 +10,7 @@
 #include <mutex>
 #include <vector>
 
+#include "md_internal.hpp"
 #include "nnp_internal.hpp"
 
 using namespace nnp;
@@ -194,7 +195,8 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species,
                                    const int32_t* mol, int32_t n_mol, const float* box_host, const nnp_nlist* nl,
                                    double* e_mol, float* e_atom, float* forces, void* ws, size_t ws_bytes,
-                                   hipStream_t s, unsigned* flags, double* virial, float* atom_virial) {
+                                   hipStream_t s, unsigned* flags, double* virial, float* atom_virial,
+                                   const EfOpts* opts) {
     if (!m || !nl || n < 0) return NNP_E_ARG;
     if (n > 0 && (!pos || !species)) return NNP_E_ARG;
     if (n_mol < 0 || (n > 0 && n_mol < 1) || n_mol > (n > 0 ? n : 1)) return NNP_E_ARG;
@@ -209,13 +211,17 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     const BoxConst bx = box_const(box_host);
     const bool bf = m->precision == NNP_BF16_MLP;
     hipError_t e = hipSuccess;
-    if (n > 0) {
+    const MdBack* md = opts ? opts->md : nullptr;
+    if (md && (!forces || virial || atom_virial)) return NNP_E_ARG;
+    if (n > 0 && !(opts && opts->skip_group)) {
         prof_begin(m, NNP_STAGE_GROUP, s);
         e = launch_species_group(m, n, species, W.mw, flags, s);
         // the per-layer GEMMs read padding rows; the fused kernel keeps them to their own rows
         if (e == hipSuccess && !(m->fused && !m->force_unfused))
             e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, bf, s);
         prof_end(m, NNP_STAGE_GROUP, s);
+    }
+    if (n > 0) {
         prof_begin(m, NNP_STAGE_AEV, s);
         if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.aev, bf, flags, s);
         prof_end(m, NNP_STAGE_AEV, s);
@@ -228,18 +234,33 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
         }
         prof_end(m, NNP_STAGE_MLP, s);
     }
-    prof_begin(m, NNP_STAGE_ENERGY, s);
-    if (e == hipSuccess)
-        e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at, e_mol, e_atom, flags,
-                          s);
-    prof_end(m, NNP_STAGE_ENERGY, s);
+    if (!(md && md->fuse_energy)) {
+        prof_begin(m, NNP_STAGE_ENERGY, s);
+        if (e == hipSuccess)
+            e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at, e_mol, e_atom, flags,
+                              s);
+        prof_end(m, NNP_STAGE_ENERGY, s);
+    }
     if (e == hipSuccess && forces && n > 0) {
         prof_begin(m, NNP_STAGE_AEV_ADJ, s);
         float* wat = virial || atom_virial ? (atom_virial ? atom_virial : W.Wat) : nullptr;
         e = launch_aev_bwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, wat, flags, s);
         prof_end(m, NNP_STAGE_AEV_ADJ, s);
         prof_begin(m, NNP_STAGE_FORCES, s);
-        if (e == hipSuccess) e = launch_force_gather(n, nl, W.Gx, W.Gy, W.Gz, forces, s);
+        if (e == hipSuccess) {
+            if (md) {
+                // engine: gather + last half kick (+ structure energy) in one kernel
+                MdEnergyIn ein{};
+                ein.prow = W.mw.prow;
+                ein.species = species;
+                ein.E_at = W.E_at;
+                for (int k = 0; k < kMaxSpecies; ++k) ein.se[k] = m->self_energy[k];
+                ein.e_pot = e_mol;
+                e = md_launch_back(n, nl, W.Gx, W.Gy, W.Gz, forces, *md, &ein, s);
+            } else {
+                e = launch_force_gather(n, nl, W.Gx, W.Gy, W.Gz, forces, s);
+            }
+        }
         prof_end(m, NNP_STAGE_FORCES, s);
     }
     if (e == hipSuccess && virial)

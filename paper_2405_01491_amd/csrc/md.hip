@@ -27,40 +27,6 @@
 namespace nnp {
 namespace {
 
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ __forceinline__ float uniform24(uint64_t w) {
-    return ((float)(uint32_t)(w >> 40) + 0.5f) * 5.9604644775390625e-8f;   // 2^-24
-}
-
-__device__ __forceinline__ void gauss3(uint64_t seed, uint64_t step, int a, float xi[3]) {
-    uint64_t c[4] = {(uint64_t)a + 1, step, 0, 0};
-    philox4x64_10(c, seed, 0);
-    const float u0 = uniform24(c[0]), u1 = uniform24(c[1]), u2 = uniform24(c[2]), u3 = uniform24(c[3]);
-    const float r0 = sqrtf(-2.f * logf(u0)), r2 = sqrtf(-2.f * logf(u2));
-    const float t1 = 6.283185307179586f * u1, t3 = 6.283185307179586f * u3;
-    xi[0] = r0 * cosf(t1);
-    xi[1] = r0 * sinf(t1);
-    xi[2] = r2 * cosf(t3);
-}
-
 template <bool kLangevin>
 __global__ __launch_bounds__(256) void k_md_first(int n, float* __restrict__ pos, float* __restrict__ vel,
                                                  const float* __restrict__ F, const float* __restrict__ inv_mass,
@@ -68,59 +34,17 @@ __global__ __launch_bounds__(256) void k_md_first(int n, float* __restrict__ pos
                                                  MdState* st) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     float d2 = 0.f;
-    if (a < n) {
-        const float im = inv_mass[a];
-        const float kick = 0.5f * c.dt * kAccUnit * im;
-        float x[3], v[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            v[k] = vel[3 * a + k] + kick * F[3 * a + k];
-            x[k] = pos[3 * a + k];
-        }
-        if (kLangevin) {
-            float xi[3];
-            gauss3(c.seed, step, a, xi);
-            const float sig = c.c2 * sqrtf(c.kT * kAccUnit * im);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                x[k] += 0.5f * c.dt * v[k];
-                v[k] = c.c1 * v[k] + sig * xi[k];
-                x[k] += 0.5f * c.dt * v[k];
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) x[k] += c.dt * v[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            vel[3 * a + k] = v[k];
-            pos[3 * a + k] = x[k];
-            const float d = x[k] - ref[3 * a + k];
-            d2 += d * d;
-        }
-    }
+    if (a < n) d2 = md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref);
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
     if (lane_id() == 0 && d2 > 0.f) atomicMax((unsigned*)&st->max_d2, __float_as_uint(d2));
 }
 
-// Rebuild decision for this step: every `rebuild_every` steps, or earlier
-// once an atom has moved more than trigger * skin / 2 since the last build.
+// Rebuild decision for this step (large systems; small ones decide in the
+// fused front kernel of the neighbour builder).
 __global__ void k_md_decide(MdState* st, int rebuild_every, float trigger2) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int since = st->since + 1;
-    const bool due = since >= rebuild_every;
-    const bool moved = trigger2 >= 0.f && st->max_d2 > trigger2;
-    if (due || moved) {
-        st->gate = 1;
-        st->since = 0;
-        st->rebuilds += 1;
-        if (!due) st->early_rebuilds += 1;
-    } else {
-        st->gate = 0;
-        st->since = since;
-    }
-    st->max_d2 = 0.f;
+    md_decide(st, st->max_d2, rebuild_every, trigger2);
 }
 
 // On rebuild steps: wrap into the box (periodic) and take the new reference.
@@ -141,19 +65,62 @@ __global__ void k_md_wrap_ref(int n, float* pos, float* ref, BoxConst bx, const 
     }
 }
 
-// Last half kick; optionally per-block float64 kinetic energies (eV).
-__global__ __launch_bounds__(256) void k_md_last(int n, float* __restrict__ vel, const float* __restrict__ F,
-                                                const float* __restrict__ inv_mass, float dt, double* ke_part) {
-    __shared__ double red[256];
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    double ke = 0.0;
+// Force gather (16 lanes per atom over its row, F_a = sum_j G_aj - G_ja, as
+// in k_force_gather), the last half kick and per-block float64 kinetic
+// energies (eV), in one kernel.  With kEnergy, block 0 first sums the
+// structure energy in float64 (per-thread sums in ascending atom order, then
+// a fixed tree).
+constexpr int kBackThreads = 256, kBackLanes = 16, kBackAtoms = kBackThreads / kBackLanes;
+
+template <bool kEnergy>
+__global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const int32_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ rev, const float* __restrict__ Gx,
+                                                         const float* __restrict__ Gy, const float* __restrict__ Gz,
+                                                         float* __restrict__ F, float* __restrict__ vel,
+                                                         const float* __restrict__ inv_mass, float dt, double* ke_part,
+                                                         const MdEnergyIn E) {
+    __shared__ double red[kBackThreads];
+    if (kEnergy && blockIdx.x == 0) {
+        double acc = 0.0;
+        for (int a = threadIdx.x; a < n; a += kBackThreads)
+            if (E.prow[a] >= 0) acc += (double)E.E_at[a] + E.se[E.species[a]];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int st = kBackThreads / 2; st >= 1; st >>= 1) {
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *E.e_pot = red[0];
+        __syncthreads();
+    }
+    const int a = blockIdx.x * kBackAtoms + threadIdx.x / kBackLanes;
+    const int sub = threadIdx.x % kBackLanes;
+    float fx = 0.f, fy = 0.f, fz = 0.f;
     if (a < n) {
+        const int b = row_ptr[a], e = row_ptr[a + 1];
+        for (int p = b + sub; p < e; p += kBackLanes) {
+            const int q = rev[p];
+            fx += Gx[p] - Gx[q];
+            fy += Gy[p] - Gy[q];
+            fz += Gz[p] - Gz[q];
+        }
+    }
+#pragma unroll
+    for (int m = kBackLanes / 2; m >= 1; m >>= 1) {
+        fx += shfl_xor(fx, m);
+        fy += shfl_xor(fy, m);
+        fz += shfl_xor(fz, m);
+    }
+    double ke = 0.0;
+    if (a < n && sub == 0) {
+        const float f[3] = {fx, fy, fz};
         const float im = inv_mass[a];
         const float kick = 0.5f * dt * kAccUnit * im;
         double v2 = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float v = vel[3 * a + k] + kick * F[3 * a + k];
+            F[3 * a + k] = f[k];
+            const float v = vel[3 * a + k] + kick * f[k];
             vel[3 * a + k] = v;
             v2 += (double)v * v;
         }
@@ -162,8 +129,8 @@ __global__ __launch_bounds__(256) void k_md_last(int n, float* __restrict__ vel,
     if (!ke_part) return;
     red[threadIdx.x] = ke;
     __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = kBackThreads / 2; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
     if (threadIdx.x == 0) ke_part[blockIdx.x] = red[0];
@@ -211,11 +178,18 @@ hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx,
     return hipGetLastError();
 }
 
-int md_ke_parts(int n) { return ceil_div(n > 0 ? n : 1, 256); }
+int md_ke_parts(int n) { return ceil_div(n > 0 ? n : 1, kBackAtoms); }
 
-hipError_t md_launch_last(int n, float* vel, const float* F, const float* inv_mass, float dt, double* ke_part,
-                          hipStream_t s) {
-    k_md_last<<<md_ke_parts(n), 256, 0, s>>>(n, vel, F, inv_mass, dt, ke_part);
+hipError_t md_launch_back(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
+                          const MdBack& b, const MdEnergyIn* e, hipStream_t s) {
+    MdEnergyIn E{};
+    if (e) E = *e;
+    if (b.fuse_energy && e)
+        k_md_back<true><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, nl->row_ptr, nl->rev, Gx, Gy, Gz, F, b.vel,
+                                                                b.inv_mass, b.dt, b.ke_part, E);
+    else
+        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, nl->row_ptr, nl->rev, Gx, Gy, Gz, F, b.vel,
+                                                                 b.inv_mass, b.dt, b.ke_part, E);
     return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@ struct nnp_md {
     float trigger2 = -1.f;
     uint64_t step = 0;
     uint64_t replays = 0;
+    bool small = false;       // fused front / back kernels (md_front_fits)
+    bool grouped = false;     // species grouping in ws_ef is current
     // device state
     float *pos = nullptr, *vel = nullptr, *F = nullptr, *inv_mass = nullptr, *ref = nullptr;
     int32_t* species = nullptr;
@@ -85,6 +87,7 @@ nnp_status alloc_list(nnp_md* md, int64_t capacity) {
         dmalloc(&md->nl.rev, (size_t)capacity) != hipSuccess)
         return NNP_E_NOMEM;
     md->ws_ef_bytes = nnp_workspace_bytes(md->model, md->n, capacity);
+    md->grouped = false;
     if (hipMalloc(&md->ws_ef, md->ws_ef_bytes) != hipSuccess) return NNP_E_NOMEM;
     return NNP_OK;
 }
@@ -117,32 +120,54 @@ nnp_status build_sync(nnp_md* md, const float* x, hipStream_t s) {
     return NNP_E_CAPACITY;
 }
 
+// One step.  Small systems (md_front_fits): a fused front kernel (first half
+// step, displacement, rebuild decision, wrap and cell binning), the gated
+// row / scan / compaction kernels, AEV, networks, AEV adjoint, and a fused
+// back kernel (structure energy, force gather, last half kick): eight
+// launches.  Larger systems use the general multi-kernel path for the front
+// and the energy sum.
 nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     nnp_model* m = md->model;
     const bool langevin = md->p.integrator == NNP_MD_LANGEVIN;
     const float* bptr = md->bx.periodic ? md->box : nullptr;
     prof_begin(m, NNP_STAGE_INTEGRATE, s);
-    hipError_t e = md_launch_first(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->st,
-                                   langevin, s);
-    if (e == hipSuccess) e = md_launch_decide(md->st, md->p.rebuild_every, md->trigger2, s);
-    if (e == hipSuccess) e = md_launch_wrap_ref(md->n, md->pos, md->ref, md->bx, md->st, s);
+    hipError_t e = hipSuccess;
+    if (md->small) {
+        nnp_status st = launch_md_front(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->st,
+                                        md->p.rebuild_every, md->trigger2, langevin, bptr, md->r_list, md->ws_nb,
+                                        md->ws_nb_bytes, md->flags, s);
+        if (st != NNP_OK) return st;
+    } else {
+        e = md_launch_first(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->st, langevin, s);
+        if (e == hipSuccess) e = md_launch_decide(md->st, md->p.rebuild_every, md->trigger2, s);
+        if (e == hipSuccess) e = md_launch_wrap_ref(md->n, md->pos, md->ref, md->bx, md->st, s);
+    }
     prof_end(m, NNP_STAGE_INTEGRATE, s);
     if (e != hipSuccess) return NNP_E_HIP;
     nnp_status st = build_neighbors(m, md->n, md->pos, nullptr, 1, bptr, md->r_list, &md->nl, nullptr, md->ws_nb,
-                                    md->ws_nb_bytes, s, false, md->flags, &md->st->gate, md->need);
-    if (st != NNP_OK) return st;
-    st = energy_forces_impl(m, md->n, md->pos, md->species, nullptr, 1, bptr, &md->nl, md->e_pot, nullptr, md->F,
-                            md->ws_ef, md->ws_ef_bytes, s, md->flags);
+                                    md->ws_nb_bytes, s, false, md->flags, &md->st->gate, md->need, md->small);
     if (st != NNP_OK) return st;
     const bool log = md->p.log_every > 0 && ((step + 1) % (uint64_t)md->p.log_every) == 0 &&
                      md->log_rows < md->log_cap;
-    prof_begin(m, NNP_STAGE_INTEGRATE, s);
-    e = md_launch_last(md->n, md->vel, md->F, md->inv_mass, md->p.dt, log ? md->ke_part : nullptr, s);
-    if (e == hipSuccess && log) {
+    MdBack back{};
+    back.vel = md->vel;
+    back.inv_mass = md->inv_mass;
+    back.dt = md->p.dt;
+    back.ke_part = log ? md->ke_part : nullptr;
+    back.fuse_energy = md->small;
+    EfOpts opts;
+    opts.skip_group = md->grouped;
+    opts.md = &back;
+    st = energy_forces_impl(m, md->n, md->pos, md->species, nullptr, 1, bptr, &md->nl, md->e_pot, nullptr, md->F,
+                            md->ws_ef, md->ws_ef_bytes, s, md->flags, nullptr, nullptr, &opts);
+    if (st != NNP_OK) return st;
+    md->grouped = true;
+    if (log) {
+        prof_begin(m, NNP_STAGE_INTEGRATE, s);
         e = md_launch_log(md->n, md->ke_part, md->e_pot, md->log + 2 * (size_t)md->log_rows, s);
         md->log_rows += 1;
+        prof_end(m, NNP_STAGE_INTEGRATE, s);
     }
-    prof_end(m, NNP_STAGE_INTEGRATE, s);
     return e == hipSuccess ? NNP_OK : NNP_E_HIP;
 }
 
@@ -199,6 +224,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
         md->bx.L[k] = md->box[k];
     }
     md->r_list = model->aev.rc_r + p.skin;
+    md->small = md_front_fits(n, box_host, md->r_list);
     if (box_host)
         for (int k = 0; k < 3; ++k)
             if (!(2.f * md->r_list <= box_host[k])) {
@@ -267,6 +293,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     if (st == NNP_OK)
         st = energy_forces_impl(model, n, md->pos, md->species, nullptr, 1, box_host, &md->nl, md->e_pot, nullptr,
                                 md->F, md->ws_ef, md->ws_ef_bytes, s, md->flags);
+    if (st == NNP_OK) md->grouped = true;
     if (st == NNP_OK) {
         unsigned fl = 0;
         int64_t need = 0;

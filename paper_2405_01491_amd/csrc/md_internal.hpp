@@ -22,13 +22,134 @@ struct MdStepConst {
     uint64_t seed;
 };
 
+// ---- device helpers shared by the integrator kernels (md.hip) and the fused
+// front kernel of small systems (neighbors.hip)
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ float uniform24(uint64_t w) {
+    return ((float)(uint32_t)(w >> 40) + 0.5f) * 5.9604644775390625e-8f;   // 2^-24
+}
+
+// three Gaussian numbers of atom a at step `step`: Philox4x64-10 block with
+// counter (a + 1, step, 0, 0), key (seed, 0), then Box-Muller
+__device__ __forceinline__ void gauss3(uint64_t seed, uint64_t step, int a, float xi[3]) {
+    uint64_t c[4] = {(uint64_t)a + 1, step, 0, 0};
+    philox4x64_10(c, seed, 0);
+    const float u0 = uniform24(c[0]), u1 = uniform24(c[1]), u2 = uniform24(c[2]), u3 = uniform24(c[3]);
+    const float r0 = sqrtf(-2.f * logf(u0)), r2 = sqrtf(-2.f * logf(u2));
+    const float t1 = 6.283185307179586f * u1, t3 = 6.283185307179586f * u3;
+    xi[0] = r0 * cosf(t1);
+    xi[1] = r0 * sinf(t1);
+    xi[2] = r2 * cosf(t3);
+}
+
+// First part of a step for atom a: velocity Verlet B(dt/2) A(dt), or BAOAB
+// B(dt/2) A(dt/2) O A(dt/2).  Returns the squared displacement from ref.
+template <bool kLangevin>
+__device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, float* __restrict__ vel,
+                                               const float* __restrict__ F, const float* __restrict__ inv_mass,
+                                               const MdStepConst& c, uint64_t step, const float* __restrict__ ref) {
+    const float im = inv_mass[a];
+    const float kick = 0.5f * c.dt * kAccUnit * im;
+    float x[3], v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = vel[3 * a + k] + kick * F[3 * a + k];
+        x[k] = pos[3 * a + k];
+    }
+    if (kLangevin) {
+        float xi[3];
+        gauss3(c.seed, step, a, xi);
+        const float sig = c.c2 * sqrtf(c.kT * kAccUnit * im);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            x[k] += 0.5f * c.dt * v[k];
+            v[k] = c.c1 * v[k] + sig * xi[k];
+            x[k] += 0.5f * c.dt * v[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[k] += c.dt * v[k];
+    }
+    float d2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        vel[3 * a + k] = v[k];
+        pos[3 * a + k] = x[k];
+        const float d = x[k] - ref[3 * a + k];
+        d2 += d * d;
+    }
+    return d2;
+}
+
+// Rebuild decision (one thread): every rebuild_every steps, or earlier once an
+// atom has moved more than trigger * skin / 2 since the last build.
+__device__ __forceinline__ int md_decide(MdState* st, float max_d2, int rebuild_every, float trigger2) {
+    const int since = st->since + 1;
+    const bool due = since >= rebuild_every;
+    const bool moved = trigger2 >= 0.f && max_d2 > trigger2;
+    if (due || moved) {
+        st->gate = 1;
+        st->since = 0;
+        st->rebuilds += 1;
+        if (!due) st->early_rebuilds += 1;
+    } else {
+        st->gate = 0;
+        st->since = since;
+    }
+    st->max_d2 = 0.f;
+    return st->gate;
+}
+
+// Energy fused into the last kernel of a step (small systems): what it needs.
+struct MdEnergyIn {
+    const int32_t* prow;      // grouped row of each atom (< 0: no network energy)
+    const int32_t* species;
+    const float* E_at;        // network energies in atom order
+    double se[kMaxSpecies];   // self energies
+    double* e_pot;            // [1]
+};
+
+// Second part of a step: force gather, B(dt/2), per-block kinetic energies.
+struct MdBack {
+    float* vel;
+    const float* inv_mass;
+    float dt;
+    double* ke_part;          // [md_ke_parts(n)] or null
+    bool fuse_energy;         // sum the structure energy in the same kernel
+};
+
 hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
                            uint64_t step, const float* ref, MdState* st, bool langevin, hipStream_t s);
 hipError_t md_launch_decide(MdState* st, int rebuild_every, float trigger2, hipStream_t s);
 hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx, const MdState* st, hipStream_t s);
 int md_ke_parts(int n);
-hipError_t md_launch_last(int n, float* vel, const float* F, const float* inv_mass, float dt, double* ke_part,
-                          hipStream_t s);
+hipError_t md_launch_back(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
+                          const MdBack& b, const MdEnergyIn* e, hipStream_t s);
+// neighbors.hip: the fused front of a step for small systems
+bool md_front_fits(int n, const float* box_host, float r_list);
+nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
+                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trigger2, bool langevin,
+                           const float* box_host, float r_list, void* ws, size_t ws_bytes, unsigned* flags,
+                           hipStream_t s);
 hipError_t md_launch_log(int n, const double* ke_part, const double* e_pot, double* row, hipStream_t s);
 hipError_t md_launch_inv_mass(int n, const float* masses, float* inv_mass, unsigned* flags, hipStream_t s);
 

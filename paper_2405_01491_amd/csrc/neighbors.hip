@@ -12,6 +12,7 @@
 // The pair predicate is evaluated in float64 with every operation rounded
 // (floating-point contraction is disabled in that function), so the pair set
 // is reproducible bit for bit by any IEEE implementation.
+#include "md_internal.hpp"
 #include "nnp_internal.hpp"
 
 namespace nnp {
@@ -358,20 +359,120 @@ __global__ void k_fill_gated(int32_t* p, long n, int32_t v, const int32_t* gate)
     p[i] = v;
 }
 
-// Asynchronous builds: if the pair total exceeds the capacity, cut the row
-// pointers at the capacity (every later read stays in bounds), raise
-// NNP_FLAG_CAPACITY and record the required size.
-__global__ void k_clamp_rows(int n, int32_t* row_ptr, const int64_t* total, int64_t capacity, int64_t* need,
-                             unsigned* flags, const int32_t* gate) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n || (gate && *gate == 0)) return;
-    const long long t = *total;
-    if (t <= capacity) return;
-    if (i == 0) {
-        set_flag(flags, NNP_FLAG_CAPACITY);
-        if (need) atomicMax((unsigned long long*)need, (unsigned long long)t);
+// ---------------------------------------------------------------- MD front (small systems)
+//
+// One workgroup does, for every atom: the first part of the MD step
+// (md_first_atom), the largest displacement since the last list build, the
+// rebuild decision, and on rebuild steps the wrap into the box, the new
+// reference positions and the cell binning (counts in LDS, a block scan for
+// the cell starts, the scatter).  It replaces five to seven launches of the
+// general path for systems up to kFrontAtoms atoms and kFrontCells cells.
+constexpr int kFrontThreads = 1024;
+constexpr int kFrontAtoms = 8192;
+constexpr int kFrontCells = 4096;
+constexpr int kFrontPer = kFrontAtoms / kFrontThreads;
+
+template <bool kLangevin>
+__global__ __launch_bounds__(kFrontThreads) void k_md_front(
+    int n, float* __restrict__ pos, float* __restrict__ vel, const float* __restrict__ F,
+    const float* __restrict__ inv_mass, const MdStepConst c, uint64_t step, float* __restrict__ ref, MdState* st,
+    int rebuild_every, float trigger2, const Grid g, int n_cells, int32_t* __restrict__ cell_of,
+    int32_t* __restrict__ cell_start, int32_t* __restrict__ cell_atoms, unsigned* flags) {
+    __shared__ int s_cnt[kFrontCells + 1];
+    __shared__ float s_max[kFrontThreads / kWave];
+    __shared__ int s_wsum[kFrontThreads / kWave];
+    __shared__ int s_gate;
+    const int t = threadIdx.x, w = t / kWave, l = lane_id();
+    float d2 = 0.f;
+    for (int a = t; a < n; a += kFrontThreads) d2 = fmaxf(d2, md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref));
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
+    if (l == 0) s_max[w] = d2;
+    __syncthreads();
+    if (t == 0) {
+        float mx = 0.f;
+        for (int q = 0; q < kFrontThreads / kWave; ++q) mx = fmaxf(mx, s_max[q]);
+        s_gate = md_decide(st, mx, rebuild_every, trigger2);
     }
-    if (row_ptr[i] > capacity) row_ptr[i] = (int32_t)capacity;
+    __syncthreads();
+    if (!s_gate) return;
+    if (g.periodic)
+        for (int q = t; q <= n_cells; q += kFrontThreads) s_cnt[q] = 0;
+    __syncthreads();
+    int my_cell[kFrontPer], my_slot[kFrontPer];
+#pragma unroll
+    for (int k = 0; k < kFrontPer; ++k) {
+        const int a = t + k * kFrontThreads;
+        my_cell[k] = -1;
+        my_slot[k] = 0;
+        if (a >= n) continue;
+        float x[3];
+        bool fin = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float v = pos[3 * a + d];
+            fin = fin && isfinite(v);
+            if (g.periodic && isfinite(v)) {
+                const float L = g.Lf[d];
+                v -= L * floorf(v / L);
+                if (v >= L) v -= L;
+                if (v < 0.f) v = 0.f;
+                pos[3 * a + d] = v;
+            }
+            ref[3 * a + d] = v;
+            x[d] = v;
+        }
+        if (!fin) {
+            set_flag(flags, NNP_FLAG_NONFINITE);
+            if (g.periodic) cell_of[a] = -1;
+            continue;
+        }
+        if (g.periodic) {
+            const int cx = cell_coord(x[0], g.L[0], g.inv_cs[0], g.nc[0]);
+            const int cy = cell_coord(x[1], g.L[1], g.inv_cs[1], g.nc[1]);
+            const int cz = cell_coord(x[2], g.L[2], g.inv_cs[2], g.nc[2]);
+            const int cc = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+            my_cell[k] = cc;
+            my_slot[k] = atomicAdd(&s_cnt[cc], 1);
+            cell_of[a] = cc;
+        }
+    }
+    if (!g.periodic) return;
+    __syncthreads();
+    // exclusive scan of the cell counts: each thread owns a contiguous run of cells
+    const int per = (n_cells + kFrontThreads - 1) / kFrontThreads;
+    const int c0 = t * per, c1 = min(n_cells, c0 + per);
+    int run = 0;
+    for (int q = c0; q < c1; ++q) run += s_cnt[q];
+    int inc = run;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int u = __shfl_up(inc, d, kWave);
+        if (l >= d) inc += u;
+    }
+    if (l == kWave - 1) s_wsum[w] = inc;
+    __syncthreads();
+    int off = 0;
+    for (int q = 0; q < w; ++q) off += s_wsum[q];
+    int ex = off + inc - run;
+    __syncthreads();
+    for (int q = c0; q < c1; ++q) {
+        const int cnt = s_cnt[q];
+        s_cnt[q] = ex;
+        cell_start[q] = ex;
+        ex += cnt;
+    }
+    if (t == kFrontThreads - 1) {
+        int tot = 0;
+        for (int q = 0; q < kFrontThreads / kWave; ++q) tot += s_wsum[q];
+        cell_start[n_cells] = tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kFrontPer; ++k) {
+        const int a = t + k * kFrontThreads;
+        if (a < n && my_cell[k] >= 0) cell_atoms[s_cnt[my_cell[k]] + my_slot[k]] = a;
+    }
 }
 
 struct WsLayout {
@@ -434,6 +535,38 @@ nnp_status make_grid(const float* box_host, float r_list, Grid* g) {
 
 }  // namespace
 
+bool md_front_fits(int n, const float* box_host, float r_list) {
+    Grid g;
+    if (make_grid(box_host, r_list, &g) != NNP_OK) return false;
+    const long n_cells = g.periodic ? (long)g.nc[0] * g.nc[1] * g.nc[2] : 1;
+    return n > 0 && n <= kFrontAtoms && n_cells <= kFrontCells;
+}
+
+nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
+                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trigger2, bool langevin,
+                           const float* box_host, float r_list, void* ws, size_t ws_bytes, unsigned* flags,
+                           hipStream_t s) {
+    Grid g;
+    nnp_status stt = make_grid(box_host, r_list, &g);
+    if (stt != NNP_OK) return stt;
+    const long n_cells = g.periodic ? (long)g.nc[0] * g.nc[1] * g.nc[2] : 1;
+    if (n <= 0 || n > kFrontAtoms || n_cells > kFrontCells) return NNP_E_ARG;
+    const WsLayout L = ws_layout(n, 1, n_cells);
+    if (!ws || ws_bytes < L.end) return NNP_E_ARG;
+    char* base = (char*)ws;
+    int32_t* cell_of = (int32_t*)(base + L.cell_of);
+    int32_t* cell_start = (int32_t*)(base + L.cell_start);
+    int32_t* cell_atoms = (int32_t*)(base + L.cell_atoms);
+    if (langevin)
+        k_md_front<true><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st, rebuild_every,
+                                                     trigger2, g, (int)n_cells, cell_of, cell_start, cell_atoms, flags);
+    else
+        k_md_front<false><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st, rebuild_every,
+                                                      trigger2, g, (int)n_cells, cell_of, cell_start, cell_atoms,
+                                                      flags);
+    return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
+}
+
 size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list) {
     Grid g;
     if (make_grid(box_host, r_list, &g) != NNP_OK) return 0;
@@ -447,7 +580,7 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host,
                            void* ws, size_t ws_bytes, hipStream_t s, bool sync, unsigned* flags_override,
-                           const int32_t* gate, int64_t* need_pairs) {
+                           const int32_t* gate, int64_t* need_pairs, bool cells_ready) {
     Grid g;
     nnp_status st = make_grid(box_host, r_list, &g);
     if (st != NNP_OK) return st;
@@ -485,7 +618,9 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
             fill(mol_end, n_mol);
             k_mol_ranges<<<nb, tb, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags, gate);
         }
-        if (g.periodic) {
+        if (cells_ready) {
+            // binned (and checked for finite coordinates) by the caller's front kernel
+        } else if (g.periodic) {
             fill(cell_count, n_cells + 1);
             k_bin<<<nb, tb, 0, s>>>(pos, n, g, cell_of, cell_slot, cell_count, flags, gate);
             chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s, gate));
@@ -497,7 +632,10 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
             pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count, stage_col,
             stage_sh, flags, gate);
     }
-    chk(launch_exclusive_scan_i32(row_count, nl->row_ptr, totals, n, scan_tmp, s, gate));
+    // asynchronous builds: the row pointers are cut at the capacity if the list
+    // is longer (every later read stays in bounds), and the overflow flagged
+    const ScanClamp clamp{nl->capacity, need_pairs, flags};
+    chk(launch_exclusive_scan_i32(row_count, nl->row_ptr, totals, n, scan_tmp, s, gate, sync ? nullptr : &clamp));
     chk(hipGetLastError());
     if (he != hipSuccess) {
         prof_end(model, NNP_STAGE_NEIGHBORS, s);
@@ -511,8 +649,6 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         nl->n_atoms = n;
         nl->r_list = r_list;
         nl->n_pairs = -1;
-        k_clamp_rows<<<ceil_div(n + 1, 256), 256, 0, s>>>(n, nl->row_ptr, totals, nl->capacity, need_pairs, flags,
-                                                          gate);
         if (n > 0)
             k_compact<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
                 n, row_count, stage_col, stage_sh, nl->row_ptr, nl->col, nl->shift, nl->rev, gate);

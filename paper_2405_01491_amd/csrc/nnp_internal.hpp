@@ -139,8 +139,15 @@ struct MlpWs {
 void prof_begin(nnp_model* m, int stage, hipStream_t s);
 void prof_end(nnp_model* m, int stage, hipStream_t s);
 
+// Optional capacity clamp of an exclusive scan (capacity < 0: none).
+struct ScanClamp {
+    int64_t capacity;
+    int64_t* need;       // device: the largest total seen (atomic max), or null
+    unsigned* flags;     // device: NNP_FLAG_CAPACITY on overflow
+};
 hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
-                                     int64_t* block_tmp, hipStream_t s, const int32_t* gate = nullptr);
+                                     int64_t* block_tmp, hipStream_t s, const int32_t* gate = nullptr,
+                                     const ScanClamp* clamp = nullptr);
 size_t scan_tmp_elems(int n);
 
 size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list);
@@ -149,12 +156,21 @@ size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host,
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host, void* ws,
                            size_t ws_bytes, hipStream_t s, bool sync = true, unsigned* flags_override = nullptr,
-                           const int32_t* gate = nullptr, int64_t* need_pairs = nullptr);
+                           const int32_t* gate = nullptr, int64_t* need_pairs = nullptr, bool cells_ready = false);
+struct MdBack;
+struct MdEnergyIn;
+// Options of the MD engine's calls: skip the species grouping (species and
+// workspace unchanged since the last call) and replace the energy sum and
+// force gather by the engine's fused last kernel.
+struct EfOpts {
+    bool skip_group = false;
+    const MdBack* md = nullptr;
+};
 // nnp_energy_forces with an explicit device flags word (n_pairs of nl is not checked)
 nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
                               int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,
                               float* forces, void* ws, size_t ws_bytes, hipStream_t s, unsigned* flags,
-                              double* virial = nullptr, float* atom_virial = nullptr);
+                              double* virial = nullptr, float* atom_virial = nullptr, const EfOpts* opts = nullptr);
 nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev,
                                 int64_t* total_host);
 

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kScanThreads) void k_block_scan(const int32_t* in, 
 constexpr int kSmallThreads = 1024, kSmallItems = 8;
 
 __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int32_t* in, int n, int32_t* out,
-                                                              int64_t* total, const int32_t* gate) {
+                                                              int64_t* total, const int32_t* gate, ScanClamp cl) {
     if (gate && *gate == 0) return;
     __shared__ long long wsum[kSmallThreads / kWave];
     const int t = threadIdx.x, w = t / kWave;
@@ -115,15 +115,34 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const int32_t* in,
         all += wsum[q];
     }
     long long ex = off + inc - s;
+    // with a clamp, outputs are cut at the capacity (a list longer than its
+    // capacity is then read in bounds), the overflow flagged and its size kept
+    const long long cap = cl.capacity >= 0 ? (long long)cl.capacity : 0x7fffffffLL;
 #pragma unroll
     for (int k = 0; k < kSmallItems; ++k) {
-        if (base + k < n) out[base + k] = ex > 0x7fffffffLL ? 0x7fffffff : (int32_t)ex;
+        if (base + k < n) out[base + k] = (int32_t)(ex > cap ? cap : ex);
         ex += v[k];
     }
     if (t == 0) {
         *total = all;
-        out[n] = all > 0x7fffffffLL ? 0x7fffffff : (int32_t)all;
+        out[n] = (int32_t)(all > cap ? cap : all);
+        if (cl.capacity >= 0 && all > cl.capacity) {
+            set_flag(cl.flags, NNP_FLAG_CAPACITY);
+            if (cl.need) atomicMax((unsigned long long*)cl.need, (unsigned long long)all);
+        }
     }
+}
+
+__global__ void k_scan_clamp(int n, int32_t* out, const int64_t* total, ScanClamp cl, const int32_t* gate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n || (gate && *gate == 0)) return;
+    const long long t = *total;
+    if (t <= cl.capacity) return;
+    if (i == 0) {
+        set_flag(cl.flags, NNP_FLAG_CAPACITY);
+        if (cl.need) atomicMax((unsigned long long*)cl.need, (unsigned long long)t);
+    }
+    if (out[i] > cl.capacity) out[i] = (int32_t)cl.capacity;
 }
 
 }  // namespace
@@ -133,15 +152,18 @@ size_t scan_tmp_elems(int n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanBlock
 // out has n + 1 entries; out[n] = total (saturated to int32); *total_out (device) = exact total.
 // With a gate, every kernel does nothing while *gate == 0.
 hipError_t launch_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t* total_out, int n,
-                                     int64_t* block_tmp, hipStream_t s, const int32_t* gate) {
+                                     int64_t* block_tmp, hipStream_t s, const int32_t* gate, const ScanClamp* clamp) {
+    ScanClamp cl{-1, nullptr, nullptr};
+    if (clamp) cl = *clamp;
     if (n <= kSmallThreads * kSmallItems) {
-        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, n, out, total_out, gate);
+        k_scan_small<<<1, kSmallThreads, 0, s>>>(in, n, out, total_out, gate, cl);
         return hipGetLastError();
     }
     const int nb = ceil_div(n > 0 ? n : 1, kScanBlock);
     k_block_sums<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp, gate);
     k_scan_sums<<<1, kScanThreads, 0, s>>>(block_tmp, nb, total_out, out + n, gate);
     k_block_scan<<<nb, kScanThreads, 0, s>>>(in, n, block_tmp, out, gate);
+    if (cl.capacity >= 0) k_scan_clamp<<<ceil_div(n + 1, 256), 256, 0, s>>>(n, out, total_out, cl, gate);
     return hipGetLastError();
 }
 

@@ -198,3 +198,26 @@ def test_engine_langevin_thermalises(spec):
     want = 1.5 * w.n_atoms * nmd.KB_EV * 300.0
     print("Langevin cold start: <KE> %.4f eV, 3N kT/2 %.4f eV, info %s" % (ke, want, eng.info()))
     assert abs(ke / want - 1.0) < 0.15
+
+
+def test_engine_general_path_tracks_oracle(spec_bias):
+    """Above 8,192 atoms the engine runs the general multi-kernel step (separate
+    integrator, decision, wrap, binning and energy-sum kernels)."""
+    w = synthetic.geometry.water_box(3000, seed=21)          # 9,000 atoms
+    model = nnp.Model(spec_bias, "fp32")
+    masses = synthetic.MASSES[w.species]
+    v0 = nmd.maxwell_boltzmann(masses, 300.0, seed=22)
+    eng = _engine(model, w, v0, dt=0.5, integrator="langevin", temperature=300.0, friction=10.0, seed=5,
+                  skin=0.5, rebuild_every=3)
+    eng.run(4)
+    x, v, F, e = [t.cpu().numpy() for t in eng.state()]
+    nl = oracle.neighbor_list(w.pos, None, w.box, 5.6)
+    xr, vr, en = oracle.langevin_baoab(
+        w.pos, v0, masses, lambda y: oracle.energy_forces_f64(y, w.species, w.box, spec_bias, nl),
+        0.5, 4, 300.0, 10.0, seed=5)
+    dx = np.abs(_min_image(x - xr, w.box)).max()
+    dv = np.abs(v - vr).max()
+    print("engine general path 4 steps: max |dx| %.3g A, max |dv| %.3g A/fs, |dE| %.3g eV, info %s"
+          % (dx, dv, abs(float(e[0]) - en[-1][0]), eng.info()))
+    assert dx < 1e-4 and dv < 1e-5
+    assert abs(float(e[0]) - en[-1][0]) < 1e-5 * max(1.0, abs(en[-1][0]))
