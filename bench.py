@@ -99,10 +99,62 @@ def cpu_baseline(w, spec, budget_s=12.0):
         if time.perf_counter() - t_start > budget_s and len(times) >= 2:
             break
     t = float(np.median(times))
+    ref = oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec)
     return {"value": w.n_atoms / t, "unit": "atom-steps/s", "cores": int(cores), "kind": "oracle",
             "sample": "%d full energy+forces evaluation(s) of the same %d-atom system (neighbour list, AEV, "
                       "MLP, adjoint), median %.2f s each; numpy float64, BLAS threads = %d"
-                      % (len(times), w.n_atoms, t, cores)}
+                      % (len(times), w.n_atoms, t, cores)}, ref
+
+
+def precision_errors(models, w, ref):
+    """Errors of each precision form against the FP64 oracle on the
+    workload's starting configuration: per-atom energy (relative to
+    max(|E_i|, rms E)), structure energy (relative), max and rms force (eV/A)."""
+    import torch
+    import paper_2405_01491_amd as nnp
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(w.pos).to(dev)
+    sp = torch.from_numpy(w.species).to(dev)
+    out = {}
+    Er = ref["E_atom"]
+    rms = float(np.sqrt(np.mean(Er ** 2)))
+    for name, model in models.items():
+        nl = nnp.nnp_neighbors(model, pos, None, 1, w.box, model.spec.rc_r)
+        e, ea, F = nnp.nnp_energy_forces(model, pos, sp, None, 1, w.box, nl, e_atom=True)
+        ea = ea.cpu().numpy().astype(np.float64)
+        dF = F.cpu().numpy().astype(np.float64) - ref["F"]
+        out[name] = {"E_atom_rel": float(np.max(np.abs(ea - Er) / np.maximum(np.abs(Er), rms))),
+                     "E_mol_rel": float(abs(float(e[0]) - ref["E_mol"][0]) / max(abs(ref["E_mol"][0]), 1e-30)),
+                     "F_max_abs": float(np.abs(dF).max()), "F_rms": float(np.sqrt(np.mean(dF ** 2)))}
+    return out
+
+
+def md_form(spec, w, precision, integ, temperature, friction, skin, every, steps, warmup):
+    """Atom-steps/s of the same MD workload with another precision form."""
+    import torch
+    import paper_2405_01491_amd as nnp
+    from paper_2405_01491_amd import md as nmd
+    dev = torch.device("cuda", 0)
+    model = nnp.Model(spec, precision)
+    masses = synthetic_masses(w)
+    vel = torch.from_numpy(nmd.maxwell_boltzmann(masses, 300.0, seed=2024)).to(dev)
+    sim = nmd.MDEngine(model, torch.from_numpy(w.pos).to(dev), vel, torch.from_numpy(w.species).to(dev), masses,
+                       w.box, dt=0.5, integrator=integ, temperature=temperature, friction=friction, seed=2024,
+                       skin=skin, rebuild_every=every)
+    sim.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    info = sim.info()
+    return model, {"value": w.n_atoms * steps / dt_s, "ms_per_step": 1e3 * dt_s / steps,
+                   "rebuilds": info["rebuilds"], "dtype": "f32" if precision == "fp32" else "f32+bf16(mlp)"}
+
+
+def synthetic_masses(w):
+    import synthetic
+    return synthetic.MASSES[w.species]
 
 
 def serving_bench(model, duration_s=5.0, warmup_s=1.0, rate=2000.0, pool=600, plain_sample=300, seed=1004):
@@ -260,13 +312,20 @@ def main():
                            temperature=args.temperature, friction=args.friction, seed=2024, skin=skin,
                            rebuild_every=every)
 
+    # warm-up with every stage timed (the stage breakdown and the choice of the
+    # dominant stage), then the timed run with events around that stage only
+    nmd.profile_enable(model, True)
     if args.config == 3:
         for _ in range(args.warmup):
             step()
     else:
         sim.run(args.warmup)
     torch.cuda.synchronize()
-    nmd.profile_enable(model, True)
+    warm = nmd.profile_read(model)
+    warm_steps = max(args.warmup, 1)
+    ranked = {k: ms for k, (ms, cnt) in warm.items() if cnt > 0}
+    dom = max(ranked, key=ranked.get) if ranked else "mlp"
+    nmd.profile_enable(model, True, stages=[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if args.config == 3:
@@ -290,9 +349,8 @@ def main():
     value = N * args.steps / dt_s
 
     # roofline of the dominant stage (HIP events recorded on the stream the kernels run on)
-    per_step = {k: (ms / max(cnt, 1), cnt) for k, (ms, cnt) in stages.items()}
-    dom = max(per_step, key=lambda k: per_step[k][0] * per_step[k][1])
-    avg_ms, cnt = per_step[dom]
+    ms_dom, cnt_dom = stages[dom]
+    avg_ms = ms_dom / max(cnt_dom, 1)
     if dom == "mlp":
         flop = (fwd + adj) * N
         peak = MI355X_PEAK["bf16_TFLOPs" if precision == "bf16" else "fp32_TFLOPs"]
@@ -320,7 +378,7 @@ def main():
         "dtype": "f32" if precision == "fp32" else "f32+bf16(mlp)", "data": "synthetic",
         "config": {"workload": workload, "n_atoms": N, "precision": precision, "skin_A": skin,
                    "rebuild_every": every, "list_pairs": n_pairs},
-        "stages_ms_per_step": {k: round(v[0] * v[1] / args.steps, 5) for k, v in per_step.items()},
+        "stages_ms_per_step_warmup": {k: round(ms / warm_steps, 5) for k, (ms, cnt) in warm.items()},
         "roofline": roof,
     }
     if args.config != 3:
@@ -328,10 +386,20 @@ def main():
         result["config"]["rebuilds"] = info["rebuilds"]
         result["config"]["early_rebuilds"] = info["early_rebuilds"]
         result["config"]["list_replays"] = info["replays"]
+    models = {precision: model}
+    if args.config != 3:
+        # the other precision form on the same workload, beside the primary one
+        other = "bf16" if precision == "fp32" else "fp32"
+        om, form = md_form(spec, w, other, args.integrator, args.temperature, args.friction, skin, every,
+                           args.steps, args.warmup)
+        result["forms"] = {precision: {"value": value, "ms_per_step": result["ms_per_step"],
+                                       "dtype": result["dtype"]}, other: form}
+        models[other] = om
     if args.config == 2 and args.serving_seconds > 0:
         result["serving"] = serving_bench(model, duration_s=args.serving_seconds)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, spec)
+        result["cpu_baseline"], ref = cpu_baseline(w, spec)
+        result["precision_vs_fp64_oracle"] = precision_errors(models, w, ref)
     print(json.dumps(result))
 
 

@@ -381,6 +381,10 @@ enum {
  * enqueues (a few microseconds of host overhead per stage; intended for one
  * stream at a time).  Enabling clears the accumulated times. */
 nnp_status nnp_profile_enable(nnp_model* model, int enable);
+/* As nnp_profile_enable, timing only the stages whose bit (1 << NNP_STAGE_x)
+ * is set in mask (0 disables): fewer events in the stream when one stage's
+ * kernel time is wanted inside a timed run. */
+nnp_status nnp_profile_enable_mask(nnp_model* model, uint32_t mask);
 /* Wait for the recorded events, add their elapsed times to the running
  * totals and return them: ms[NNP_N_STAGES] (milliseconds summed over
  * launches) and count[NNP_N_STAGES] (number of timed stage executions). */

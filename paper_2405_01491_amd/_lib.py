@@ -62,6 +62,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_uint64)]),
     "nnp_server_destroy": (None, [c_void_p]),
     "nnp_profile_enable": (ctypes.c_int, [c_void_p, ctypes.c_int]),
+    "nnp_profile_enable_mask": (ctypes.c_int, [c_void_p, ctypes.c_uint32]),
     "nnp_profile_read": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 

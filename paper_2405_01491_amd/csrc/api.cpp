@@ -28,6 +28,7 @@ std::mutex g_stage_mutex;
 
 struct nnp_prof {
     bool enabled = false;
+    uint32_t mask = 0;        // stages timed while enabled
     std::mutex mu;
     std::vector<hipEvent_t> free_events;
     struct Pair { hipEvent_t a, b; int stage; };
@@ -70,7 +71,7 @@ namespace nnp {
 
 void prof_begin(nnp_model* m, int stage, hipStream_t s) {
     nnp_prof* p = m->prof;
-    if (!p || !p->enabled) return;
+    if (!p || !p->enabled || !((p->mask >> stage) & 1u)) return;
     std::lock_guard<std::mutex> lock(p->mu);
     if (p->pending.size() > 16384) p->drain();
     hipEvent_t e = p->take();
@@ -82,7 +83,7 @@ void prof_begin(nnp_model* m, int stage, hipStream_t s) {
 
 void prof_end(nnp_model* m, int stage, hipStream_t s) {
     nnp_prof* p = m->prof;
-    if (!p || !p->enabled) return;
+    if (!p || !p->enabled || !((p->mask >> stage) & 1u)) return;
     std::lock_guard<std::mutex> lock(p->mu);
     hipEvent_t a = p->open[stage];
     if (!a) return;
@@ -567,7 +568,7 @@ nnp_status nnp_md_wrap(int32_t n, float* pos, const float* box_host, void* strea
     return hip_status(launch_wrap(n, pos, box_host, (hipStream_t)stream));
 }
 
-nnp_status nnp_profile_enable(nnp_model* m, int enable) {
+nnp_status nnp_profile_enable_mask(nnp_model* m, uint32_t mask) {
     if (!m) return NNP_E_ARG;
     if (!m->prof) m->prof = new nnp_prof;
     std::lock_guard<std::mutex> lock(m->prof->mu);
@@ -576,8 +577,13 @@ nnp_status nnp_profile_enable(nnp_model* m, int enable) {
         m->prof->ms[k] = 0.0;
         m->prof->cnt[k] = 0;
     }
-    m->prof->enabled = enable != 0;
+    m->prof->mask = mask & ((1u << NNP_N_STAGES) - 1u);
+    m->prof->enabled = m->prof->mask != 0;
     return NNP_OK;
+}
+
+nnp_status nnp_profile_enable(nnp_model* m, int enable) {
+    return nnp_profile_enable_mask(m, enable ? (1u << NNP_N_STAGES) - 1u : 0u);
 }
 
 nnp_status nnp_profile_read(nnp_model* m, double* ms, int64_t* count) {

@@ -106,10 +106,9 @@ __device__ __forceinline__ void set_flag(unsigned* flags, unsigned bit) {
 
 // Round-to-nearest-even float32 -> bfloat16 bits.
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    // gfx950 converts in hardware (v_cvt_pk_bf16_f32: round to nearest even,
+    // NaN stays NaN)
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }

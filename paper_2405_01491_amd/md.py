@@ -116,8 +116,13 @@ class VelocityVerlet:
         return float(self.e_mol.sum()) + self.kinetic_energy()
 
 
-def profile_enable(model, enable=True):
-    check(lib().nnp_profile_enable(model.handle, 1 if enable else 0), "nnp_profile_enable")
+def profile_enable(model, enable=True, stages=None):
+    """Time every stage (or only the named ones) of later calls."""
+    if stages is None:
+        check(lib().nnp_profile_enable(model.handle, 1 if enable else 0), "nnp_profile_enable")
+    else:
+        mask = sum(1 << _lib.STAGES.index(s) for s in stages) if enable else 0
+        check(lib().nnp_profile_enable_mask(model.handle, mask), "nnp_profile_enable_mask")
 
 
 def profile_read(model):
