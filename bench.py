@@ -67,7 +67,7 @@ def source_digest(stage):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def load_traffic(path, stage, config, precision):
+def load_traffic(path, stage, config, precision, nets=1):
     """Measured HBM bytes per launch of the stage's kernel (FETCH_SIZE +
     WRITE_SIZE counters scaled by a plain-copy calibration), or None when no
     measurement exists or the kernel source changed since it was taken."""
@@ -76,7 +76,7 @@ def load_traffic(path, stage, config, precision):
         return None
     with open(path) as f:
         tab = json.load(f)
-    e = tab.get("%s/config%d/%s" % (stage, config, precision))
+    e = tab.get("%s/config%d/%s%s" % (stage, config, precision, "/nets%d" % nets if nets > 1 else ""))
     if not e or e.get("source_sha256") != source_digest(stage):
         return None
     return e
@@ -239,6 +239,9 @@ def main():
     ap.add_argument("--integrator", default="nve", choices=["nve", "langevin"],
                     help="nve: velocity Verlet (the configured workloads); langevin: BAOAB as in the paper's "
                          "benchmarks")
+    ap.add_argument("--nets", type=int, default=1,
+                    help="networks of the model: 1 (the paper's benchmarks use the first network of ANI-2x) or an "
+                         "ensemble of up to 16 on one shared AEV")
     ap.add_argument("--temperature", type=float, default=300.0)
     ap.add_argument("--friction", type=float, default=1.0, help="Langevin friction, 1/ps")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -268,7 +271,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    spec = synthetic.ani2x_like_spec()
+    spec = synthetic.ani2x_like_spec() if args.nets == 1 else synthetic.ani2x_like_ensemble(n_nets=args.nets)
     if args.config == 4:
         model = nnp.Model(spec, args.precision or "fp32")
         sv = serving_bench(model, duration_s=args.serving_seconds)
@@ -285,6 +288,7 @@ def main():
     sp = torch.from_numpy(w.species).to(dev)
     masses = synthetic.MASSES[w.species]
     fwd, adj = mlp_flops_per_atom(spec.widths)
+    fwd, adj = fwd * args.nets, adj * args.nets
 
     if args.config == 3:
         skin, every = 0.0, 1
@@ -366,7 +370,9 @@ def main():
                 "algorithmic_per_launch": "%.4g B" % byt}
     roof["avg_launch_ms"] = avg_ms
     roof["kernel"] = STAGE_KERNEL.get((dom, model.fused_mlp), dom)
-    tr = load_traffic(args.traffic, dom, args.config, precision)
+    if dom == "mlp" and args.nets > 1:
+        roof["kernel"] = "k_mlp_fused (per network, to d1) + k_ens_adj1 (first-layer adjoint over networks)"
+    tr = load_traffic(args.traffic, dom, args.config, precision, args.nets)
     if tr is not None:
         roof["traffic"] = tr["bytes_per_launch"]
         roof["traffic_source"] = tr["profile"]
@@ -376,8 +382,9 @@ def main():
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * dt_s / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if precision == "fp32" else "f32+bf16(mlp)", "data": "synthetic",
-        "config": {"workload": workload, "n_atoms": N, "precision": precision, "skin_A": skin,
-                   "rebuild_every": every, "list_pairs": n_pairs},
+        "config": {"workload": workload + ("; ensemble of %d networks" % args.nets if args.nets > 1 else ""),
+                   "n_atoms": N, "precision": precision, "skin_A": skin, "rebuild_every": every,
+                   "list_pairs": n_pairs, "networks": args.nets},
         "stages_ms_per_step_warmup": {k: round(ms / warm_steps, 5) for k, (ms, cnt) in warm.items()},
         "roofline": roof,
     }

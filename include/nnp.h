@@ -67,6 +67,8 @@ typedef enum {
 /* Largest neighbour-row length (pairs within the list cutoff of one atom) the
  * AEV kernels accept.  Longer rows set NNP_FLAG_ROW and contribute nothing. */
 #define NNP_MAX_ROW 256
+/* Largest ensemble nnp_model_create_ensemble accepts. */
+#define NNP_MAX_NETS 16
 /* Largest number of neighbours within the angular cutoff of one atom. */
 #define NNP_MAX_ANGULAR 96
 
@@ -128,6 +130,17 @@ typedef struct {
  * device memory owned by the model.  *out receives the handle. */
 nnp_status nnp_model_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
                             nnp_precision precision, nnp_model** out);
+/* An ensemble of n_nets networks on one shared AEV (ANI-2x is an ensemble
+ * of eight networks; the paper's benchmarks evaluate the first one only,
+ * Sec. 5.5).  nets[k] are complete network parameter sets with identical
+ * widths, which must be 1008-256-192-160-1 (the fused kernels); self
+ * energies come from nets[0].  Every entry point then works with the
+ * ensemble-mean atomic energy E_i = (1/n_nets) sum_k E_i^k (+ self energy)
+ * and its forces.  1 <= n_nets <= NNP_MAX_NETS; NNP_E_ARG otherwise. */
+nnp_status nnp_model_create_ensemble(const nnp_aev_params* aev, const nnp_mlp_params* nets,
+                                     int32_t n_nets, nnp_precision precision, nnp_model** out);
+/* Networks of the model (1 for nnp_model_create). */
+int32_t nnp_model_nets(const nnp_model* model);
 void nnp_model_destroy(nnp_model* model);
 /* Switch the precision form used by later nnp_energy_forces calls. */
 nnp_status nnp_model_set_precision(nnp_model* model, nnp_precision precision);
@@ -219,6 +232,17 @@ nnp_status nnp_energy_forces_virial(nnp_model* model, int32_t n_atoms, const flo
                                     const float* box_host, const nnp_nlist* nl, double* e_mol,
                                     float* e_atom, float* forces, double* virial,
                                     float* atom_virial, void* ws, size_t ws_bytes, void* stream);
+
+/* nnp_energy_forces of an ensemble model (n_nets >= 2) that also writes
+ * every network's structure energies (self energies included), the spread
+ * of which estimates the model's uncertainty:
+ *   e_mol_net  device float64 [n_nets][n_mol] (written; required)
+ * e_mol, e_atom, forces as nnp_energy_forces (ensemble mean). */
+nnp_status nnp_energy_forces_ensemble(nnp_model* model, int32_t n_atoms, const float* pos,
+                                      const int32_t* species, const int32_t* mol, int32_t n_mol,
+                                      const float* box_host, const nnp_nlist* nl, double* e_mol,
+                                      double* e_mol_net, float* e_atom, float* forces, void* ws,
+                                      size_t ws_bytes, void* stream);
 
 /* The AEV alone (the radial and angular features of Sec. 2.2 / App. A):
  * writes aev_out, device float32 [n_atoms][aev_stride] (aev_stride =

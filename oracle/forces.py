@@ -32,7 +32,7 @@ import numpy as np
 
 from .aev import AEVLayout, aev as aev_fn, angular_factors, angular_triplets, f64, pair_geometry, \
     switch, switch_deriv
-from .mlp import mlp_energy_and_grad
+from .mlp import mlp_energies_per_net, mlp_energy_and_grad
 from .neighbors import neighbor_list
 
 
@@ -145,7 +145,7 @@ def virial_from_edges(nl, v, G, mol=None, n_mol=1, n_atoms=None):
 
 
 def energy_forces(pos, species, mol, n_mol, box, spec, r_list=None, precision="fp64",
-                  nl=None, need_forces=True, need_virial=False):
+                  nl=None, need_forces=True, need_virial=False, need_nets=False):
     """Full evaluation.  Returns dict with E_mol [n_mol], E_atom [N],
     F [N,3] (if requested), aev [N,D], g [N,D], nl."""
     if r_list is None:
@@ -160,6 +160,13 @@ def energy_forces(pos, species, mol, n_mol, box, spec, r_list=None, precision="f
     for a in range(N):                                  # ascending atom index
         E_mol[mol[a]] += E_atom[a]
     out = dict(E_mol=E_mol, E_atom=E_atom, aev=A, g=g, nl=nl)
+    if need_nets:
+        # every network's structure energies (ascending atom order)
+        E_net = mlp_energies_per_net(A, species, spec, precision)
+        E_mol_net = np.zeros((E_net.shape[0], n_mol))
+        for a in range(N):
+            E_mol_net[:, mol[a]] += E_net[:, a]
+        out["E_mol_net"] = E_mol_net
     if need_forces or need_virial:
         G = edge_gradients(pos, species, box, nl, spec, g)
         out["G"] = G

@@ -19,6 +19,10 @@ three of the backward pass (d3, d2, d1), and the weight matrices W1..W3, are
 rounded to bfloat16 (round to nearest even, through float32), and products
 are accumulated exactly (float64).  The last layer (a dot product), the
 activations and their derivatives stay in full precision.
+
+An ensemble (ANI-2x has eight networks; Sec. 5.5 evaluates the first one)
+gives every atom the mean of its networks' energies, E_i = (1/K) sum_k E_i^k
+(+ the self energy once), and dE/da is the mean of the networks' gradients.
 """
 import numpy as np
 
@@ -40,9 +44,9 @@ def round_bf16(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def _layers(spec, s, precision):
+def _layers(spec, s, precision, weights=None):
     out = []
-    for l, (W, b) in enumerate(spec.weights[s]):
+    for l, (W, b) in enumerate((spec.weights if weights is None else weights)[s]):
         W = np.asarray(W, dtype=np.float32).astype(np.float64)
         b = np.asarray(b, dtype=np.float32).astype(np.float64)
         if precision == "bf16" and l < len(spec.weights[s]) - 1:
@@ -51,8 +55,38 @@ def _layers(spec, s, precision):
     return out
 
 
+def networks(spec):
+    """Every network's weights: the ensemble, or the single network."""
+    return spec.ensemble if getattr(spec, "ensemble", None) else [spec.weights]
+
+
 def mlp_energy_and_grad(aev, species, spec, precision="fp64", need_grad=True):
-    """Atomic energies E [N] and, if requested, dE/daev [N, D] (float64)."""
+    """Atomic energies E [N] and, if requested, dE/daev [N, D] (float64); the
+    ensemble mean for an ensemble spec."""
+    nets = networks(spec)
+    if len(nets) == 1:
+        return _single_net(aev, species, spec, precision, need_grad, nets[0])
+    se = np.zeros(spec.n_species) if spec.self_energy is None else np.asarray(spec.self_energy, np.float64)
+    E = np.zeros(len(species))
+    g = np.zeros(aev.shape) if need_grad else None
+    for w in nets:
+        Ek, gk = _single_net(aev, species, spec, precision, need_grad, w, with_self=False)
+        E += Ek
+        if need_grad:
+            g += gk
+    E /= len(nets)
+    E += se[np.asarray(species, dtype=np.int64)]
+    if need_grad:
+        g /= len(nets)
+    return E, g
+
+
+def mlp_energies_per_net(aev, species, spec, precision="fp64"):
+    """[K, N]: every network's atomic energies, self energy included."""
+    return np.stack([_single_net(aev, species, spec, precision, False, w)[0] for w in networks(spec)])
+
+
+def _single_net(aev, species, spec, precision, need_grad, weights, with_self=True):
     if precision not in ("fp64", "bf16"):
         raise ValueError(precision)
     q = round_bf16 if precision == "bf16" else (lambda x: x)
@@ -60,12 +94,12 @@ def mlp_energy_and_grad(aev, species, spec, precision="fp64", need_grad=True):
     N, D = aev.shape
     E = np.zeros(N)
     g = np.zeros((N, D)) if need_grad else None
-    se = np.zeros(spec.n_species) if spec.self_energy is None else spec.self_energy
+    se = np.zeros(spec.n_species) if spec.self_energy is None or not with_self else spec.self_energy
     for s in range(spec.n_species):
         rows = np.nonzero(np.asarray(species) == s)[0]
         if len(rows) == 0:
             continue
-        L = _layers(spec, s, precision)
+        L = _layers(spec, s, precision, weights)
         h = aev[rows]
         zs = []
         for W, b in L[:-1]:

@@ -71,25 +71,31 @@ class Model:
             radial_prefactor=spec.radial_prefactor, cos_scale=spec.cos_scale)
         n_layers = len(spec.widths) - 1
         widths = np.ascontiguousarray(np.asarray(spec.widths, dtype=np.int32))
-        Ws = (_lib.c_float_p * (spec.n_species * n_layers))()
-        bs = (_lib.c_float_p * (spec.n_species * n_layers))()
-        for s in range(spec.n_species):
-            for l in range(n_layers):
-                W, b = spec.weights[s][l]
-                Ws[s * n_layers + l] = fp(W)
-                bs[s * n_layers + l] = fp(b)
         se = None
         if getattr(spec, "self_energy", None) is not None:
             se_arr = np.ascontiguousarray(np.asarray(spec.self_energy, dtype=np.float64))
             keep.append(se_arr)
             se = se_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        mp = _lib.MlpParams(n_layers=n_layers, widths=widths.ctypes.data_as(_lib.c_int32_p), W=Ws, b=bs,
-                            celu_alpha=spec.celu_alpha, self_energy=se)
+        # an ensemble spec lists every network's weights; a plain spec has one network
+        nets = getattr(spec, "ensemble", None) or [spec.weights]
+        mps = (_lib.MlpParams * len(nets))()
+        for k, weights in enumerate(nets):
+            Ws = (_lib.c_float_p * (spec.n_species * n_layers))()
+            bs = (_lib.c_float_p * (spec.n_species * n_layers))()
+            keep.extend([Ws, bs])
+            for s in range(spec.n_species):
+                for l in range(n_layers):
+                    W, b = weights[s][l]
+                    Ws[s * n_layers + l] = fp(W)
+                    bs[s * n_layers + l] = fp(b)
+            mps[k] = _lib.MlpParams(n_layers=n_layers, widths=widths.ctypes.data_as(_lib.c_int32_p), W=Ws, b=bs,
+                                    celu_alpha=spec.celu_alpha, self_energy=se)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            check(L.nnp_model_create(ctypes.byref(ap), ctypes.byref(mp), _PRECISIONS[precision],
-                                     ctypes.byref(handle)), "nnp_model_create")
+            check(L.nnp_model_create_ensemble(ctypes.byref(ap), mps, len(nets), _PRECISIONS[precision],
+                                              ctypes.byref(handle)), "nnp_model_create_ensemble")
         self.handle = handle
+        self.n_nets = int(L.nnp_model_nets(handle))
         self.precision = precision
         self.aev_dim = L.nnp_aev_dim(handle)
         self.aev_stride = (self.aev_dim + 63) // 64 * 64
@@ -257,6 +263,29 @@ def nnp_energy_forces(model, pos, species, mol=None, n_mol=1, box=None, nl=None,
                                   ws.numel(), _stream(dev)), "nnp_energy_forces")
     out.update(e_mol=e_mol_t, e_atom=e_at, forces=F)
     return e_mol_t, e_at, F
+
+
+def nnp_energy_forces_ensemble(model, pos, species, mol=None, n_mol=1, box=None, nl=None, forces=True,
+                               e_atom=False):
+    """Ensemble-mean energies / forces plus every network's structure
+    energies (float64 [n_nets, n_mol])."""
+    L = lib()
+    n = pos.shape[0]
+    if nl is None:
+        nl = nnp_neighbors(model, pos, mol, n_mol, box)
+    dev = pos.device
+    e_mol = torch.empty(n_mol, dtype=torch.float64, device=dev)
+    e_net = torch.empty((model.n_nets, n_mol), dtype=torch.float64, device=dev)
+    e_at = torch.empty(n, dtype=torch.float32, device=dev) if e_atom else None
+    F = torch.empty((n, 3), dtype=torch.float32, device=dev) if forces else None
+    _b, bptr = _box_arg(box)
+    ws = model.workspace(L.nnp_workspace_bytes(model.handle, n, nl.capacity))
+    with torch.cuda.device(dev):
+        check(L.nnp_energy_forces_ensemble(model.handle, n, _ptr(pos), _ptr(species), _ptr(mol), int(n_mol), bptr,
+                                           ctypes.byref(nl.struct()), _ptr(e_mol), _ptr(e_net), _ptr(e_at),
+                                           _ptr(F), _ptr(ws), ws.numel(), _stream(dev)),
+              "nnp_energy_forces_ensemble")
+    return e_mol, e_net, e_at, F
 
 
 def nnp_aev(model, pos, species, box=None, nl=None):

@@ -39,6 +39,12 @@ SIGNATURES = {
     "nnp_energy_forces_virial": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
                                                 ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                                 c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
+    "nnp_model_create_ensemble": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int32, ctypes.c_int,
+                                                 ctypes.POINTER(c_void_p)]),
+    "nnp_model_nets": (ctypes.c_int32, [c_void_p]),
+    "nnp_energy_forces_ensemble": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
+                                                  ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                                  c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
     "nnp_aev": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, ctypes.c_size_t, c_void_p]),
     "nnp_mlp": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -112,6 +112,9 @@ struct EfWs {
     float* Gz;
     float* Wat;         // per-centre virials [n][9] when the caller passes none
     double* vpart;      // chunk partials of the structure virial
+    void* d1;           // ensembles: per-network dE/dh1 [n_nets][rows_max][256]
+    float* E_net;       // ensembles: per-network energies [n_nets][rows_max]
+    float* E_at_net;    // ensembles: per-network atomic energies [n_nets][n]
     size_t end;
 };
 
@@ -142,6 +145,11 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.Gz = (float*)take(sizeof(float) * c);
     W.Wat = (float*)take(sizeof(float) * 9 * (size_t)nn);
     W.vpart = (double*)take(sizeof(double) * virial_partial_doubles(nn));
+    if (m->n_nets > 1) {
+        W.d1 = take(sizeof(float) * (size_t)m->n_nets * rows_max * 256);
+        W.E_net = (float*)take(sizeof(float) * (size_t)m->n_nets * rows_max);
+        W.E_at_net = (float*)take(sizeof(float) * (size_t)m->n_nets * nn);
+    }
     W.end = o;
     return W;
 }
@@ -197,7 +205,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
                                    const int32_t* mol, int32_t n_mol, const float* box_host, const nnp_nlist* nl,
                                    double* e_mol, float* e_atom, float* forces, void* ws, size_t ws_bytes,
                                    hipStream_t s, unsigned* flags, double* virial, float* atom_virial,
-                                   const EfOpts* opts) {
+                                   const EfOpts* opts, double* e_mol_net) {
     if (!m || !nl || n < 0) return NNP_E_ARG;
     if (n > 0 && (!pos || !species)) return NNP_E_ARG;
     if (n_mol < 0 || (n > 0 && n_mol < 1) || n_mol > (n > 0 ? n : 1)) return NNP_E_ARG;
@@ -228,7 +236,10 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
         prof_end(m, NNP_STAGE_AEV, s);
         prof_begin(m, NNP_STAGE_MLP, s);
         if (e == hipSuccess) {
-            if (m->fused && !m->force_unfused)
+            if (m->n_nets > 1)
+                e = launch_mlp_ensemble(m, W.mw, W.aev, forces ? W.g : nullptr, W.E_row, W.E_at, n, W.d1, W.E_net,
+                                        e_mol_net ? W.E_at_net : nullptr, s);
+            else if (m->fused && !m->force_unfused)
                 e = launch_mlp_fused(m, W.mw, W.aev, forces ? W.g : nullptr, W.E_row, W.E_at, n, s);
             else
                 e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, W.E_at, s);
@@ -240,6 +251,10 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
         if (e == hipSuccess)
             e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at, e_mol, e_atom, flags,
                               s);
+        // ensembles: every network's structure energies (self energies included)
+        for (int k = 0; e_mol_net && k < m->n_nets && e == hipSuccess && n > 0; ++k)
+            e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at_net + (size_t)k * n,
+                              e_mol_net + (size_t)k * n_mol, nullptr, flags, s);
         prof_end(m, NNP_STAGE_ENERGY, s);
     }
     if (e == hipSuccess && forces && n > 0) {
@@ -290,7 +305,18 @@ const char* nnp_status_str(nnp_status s) {
 
 nnp_status nnp_model_create(const nnp_aev_params* a, const nnp_mlp_params* p, nnp_precision precision,
                             nnp_model** out) {
-    if (!a || !p || !out) return NNP_E_ARG;
+    return nnp_model_create_ensemble(a, p, 1, precision, out);
+}
+
+nnp_status nnp_model_create_ensemble(const nnp_aev_params* a, const nnp_mlp_params* nets, int32_t n_nets,
+                                     nnp_precision precision, nnp_model** out) {
+    if (!a || !nets || !out || n_nets < 1 || n_nets > NNP_MAX_NETS) return NNP_E_ARG;
+    const nnp_mlp_params* p = &nets[0];
+    for (int k = 1; k < n_nets; ++k) {
+        if (nets[k].n_layers != p->n_layers || !nets[k].widths || !nets[k].W || !nets[k].b) return NNP_E_ARG;
+        for (int l = 0; l <= p->n_layers; ++l)
+            if (nets[k].widths[l] != p->widths[l]) return NNP_E_ARG;
+    }
     *out = nullptr;
     if (a->n_species < 1 || a->n_species > kMaxSpecies) return NNP_E_ARG;
     if (a->n_shf_r != kNr || a->n_shf_a != kNa || a->n_shf_z != kNz) return NNP_E_ARG;
@@ -407,26 +433,80 @@ nnp_status nnp_model_create(const nnp_aev_params* a, const nnp_mlp_params* p, nn
         m->ptrs.head_w[s] = (const float*)(d + offH[s]);
     }
     m->fused = fused_mlp_shape(m->widths, L, ns);
+    m->n_nets = n_nets;
+    if (n_nets > 1 && !m->fused) {   // ensembles run on the fused kernels only
+        nnp_model_destroy(m);
+        return NNP_E_ARG;
+    }
     if (m->fused) {
+        // per network: float32 packs of every species, bfloat16 packs, then the
+        // biases and head weights (b1 [256], b2 [192], b3 [192], w4 [192], zero padded)
         const size_t per = pack_fused_species(nullptr, false, nullptr, nullptr, nullptr, dim, m->widths[3]);
         const size_t perb = pack_fused_species(nullptr, true, nullptr, nullptr, nullptr, dim, m->widths[3]);
-        std::vector<char> hp(per * ns + perb * ns);
-        for (int s = 0; s < ns; ++s) {
-            const float* W1 = p->W[s * L + 0];
-            const float* W2 = p->W[s * L + 1];
-            const float* W3 = p->W[s * L + 2];
-            pack_fused_species(hp.data() + per * s, false, W1, W2, W3, dim, m->widths[3]);
-            pack_fused_species(hp.data() + per * ns + perb * s, true, W1, W2, W3, dim, m->widths[3]);
+        const int hw[4] = {256, 192, 192, 192};
+        size_t vec_bytes = 0;
+        for (int k = 0; k < 4; ++k) vec_bytes += align256(sizeof(float) * hw[k]);
+        const size_t net_bytes = (per + perb + vec_bytes) * ns;
+        std::vector<char> hp(net_bytes * n_nets, 0);
+        for (int k = 0; k < n_nets; ++k) {
+            const nnp_mlp_params* q = &nets[k];
+            char* nb = hp.data() + net_bytes * k;
+            for (int s = 0; s < ns; ++s) {
+                const float* W1 = q->W[s * L + 0];
+                const float* W2 = q->W[s * L + 1];
+                const float* W3 = q->W[s * L + 2];
+                const float* w4 = q->W[s * L + 3];
+                if (!W1 || !W2 || !W3 || !w4 || !q->b[s * L + 0] || !q->b[s * L + 1] || !q->b[s * L + 2] ||
+                    !q->b[s * L + 3]) {
+                    nnp_model_destroy(m);
+                    return NNP_E_ARG;
+                }
+                pack_fused_species(nb + per * s, false, W1, W2, W3, dim, m->widths[3]);
+                pack_fused_species(nb + per * ns + perb * s, true, W1, W2, W3, dim, m->widths[3]);
+                char* v = nb + (per + perb) * ns + vec_bytes * s;
+                const float* src[4] = {q->b[s * L + 0], q->b[s * L + 1], q->b[s * L + 2], w4};
+                const int len[4] = {m->widths[1], m->widths[2], m->widths[3], m->widths[3]};
+                for (int j = 0; j < 4; ++j) {
+                    std::memcpy(v, src[j], sizeof(float) * len[j]);
+                    v += align256(sizeof(float) * hw[j]);
+                }
+            }
         }
         if (hipMalloc(&m->fused_dev, hp.size()) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
         if (hipMemcpy(m->fused_dev, hp.data(), hp.size(), hipMemcpyHostToDevice) != hipSuccess) {
             nnp_model_destroy(m);
             return NNP_E_HIP;
         }
-        for (int s = 0; s < ns; ++s) {
-            m->fused_fp32[s] = (char*)m->fused_dev + per * s;
-            m->fused_bf16[s] = (char*)m->fused_dev + per * ns + perb * s;
+        // device tables: [n_nets] float32 entries, then [n_nets] bfloat16 entries
+        const size_t eb = fused_net_bytes();
+        std::vector<char> tab(eb * 2 * n_nets);
+        for (int k = 0; k < n_nets; ++k) {
+            const char* nb = (const char*)m->fused_dev + net_bytes * k;
+            const char* pf[kMaxSpecies];
+            const char* pb[kMaxSpecies];
+            const float *b1[kMaxSpecies], *b2[kMaxSpecies], *b3[kMaxSpecies], *w4[kMaxSpecies];
+            float b4[kMaxSpecies];
+            for (int s = 0; s < ns; ++s) {
+                pf[s] = nb + per * s;
+                pb[s] = nb + per * ns + perb * s;
+                const char* v = nb + (per + perb) * ns + vec_bytes * s;
+                const float** dst[4] = {&b1[s], &b2[s], &b3[s], &w4[s]};
+                for (int j = 0; j < 4; ++j) {
+                    *dst[j] = (const float*)v;
+                    v += align256(sizeof(float) * hw[j]);
+                }
+                b4[s] = nets[k].b[s * L + L - 1][0];
+            }
+            fused_net_entry(tab.data() + eb * k, ns, pf, b1, b2, b3, w4, b4, false);
+            fused_net_entry(tab.data() + eb * (n_nets + k), ns, pb, b1, b2, b3, w4, b4, true);
         }
+        if (hipMalloc(&m->fused_tab, tab.size()) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
+        if (hipMemcpy(m->fused_tab, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            nnp_model_destroy(m);
+            return NNP_E_HIP;
+        }
+        m->fused_tab_fp32 = m->fused_tab;
+        m->fused_tab_bf16 = (char*)m->fused_tab + eb * n_nets;
     }
     if (hipMalloc(&m->flags, 256) != hipSuccess) { nnp_model_destroy(m); return NNP_E_NOMEM; }
     if (hipMemset(m->flags, 0, 256) != hipSuccess) { nnp_model_destroy(m); return NNP_E_HIP; }
@@ -439,6 +519,7 @@ void nnp_model_destroy(nnp_model* m) {
     if (!m) return;
     if (m->dev_weights) (void)hipFree(m->dev_weights);
     if (m->fused_dev) (void)hipFree(m->fused_dev);
+    if (m->fused_tab) (void)hipFree(m->fused_tab);
     if (m->flags) (void)hipFree(m->flags);
     if (m->host_stage) (void)hipHostFree(m->host_stage);
     delete m->prof;
@@ -456,7 +537,7 @@ int32_t nnp_aev_dim(const nnp_model* m) { return m ? m->aev.dim : 0; }
 int32_t nnp_model_fused_mlp(const nnp_model* m) { return m && m->fused && !m->force_unfused ? 1 : 0; }
 
 nnp_status nnp_model_set_fused_mlp(nnp_model* m, int32_t allow) {
-    if (!m) return NNP_E_ARG;
+    if (!m || (allow == 0 && m->n_nets > 1)) return NNP_E_ARG;
     m->force_unfused = allow == 0;
     return NNP_OK;
 }
@@ -514,6 +595,18 @@ nnp_status nnp_energy_forces_virial(nnp_model* m, int32_t n, const float* pos, c
                               (hipStream_t)stream, m->flags, virial, atom_virial);
 }
 
+nnp_status nnp_energy_forces_ensemble(nnp_model* m, int32_t n, const float* pos, const int32_t* species,
+                                      const int32_t* mol, int32_t n_mol, const float* box_host, const nnp_nlist* nl,
+                                      double* e_mol, double* e_mol_net, float* e_atom, float* forces, void* ws,
+                                      size_t ws_bytes, void* stream) {
+    if (!m || !nl || n < 0 || m->n_nets < 2 || !e_mol_net) return NNP_E_ARG;
+    if (nl->n_atoms != n || nl->n_pairs > nl->capacity) return NNP_E_ARG;
+    return energy_forces_impl(m, n, pos, species, mol, n_mol, box_host, nl, e_mol, e_atom, forces, ws, ws_bytes,
+                              (hipStream_t)stream, m->flags, nullptr, nullptr, nullptr, e_mol_net);
+}
+
+int32_t nnp_model_nets(const nnp_model* m) { return m ? m->n_nets : 0; }
+
 nnp_status nnp_aev(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const float* box_host,
                    const nnp_nlist* nl, float* aev_out, void* ws, size_t ws_bytes, void* stream) {
     (void)ws;
@@ -532,8 +625,8 @@ nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float*
     if (n == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
     const EfWs W = ef_layout(m, n, 0, (char*)ws);
-    const bool fused = m->fused && !m->force_unfused;
-    const bool bfa = fused && m->precision == NNP_BF16_MLP;   // the fused BF16 kernel reads bf16 rows
+    const bool fused = m->fused && (!m->force_unfused || m->n_nets > 1);
+    const bool bfa = fused && m->precision == NNP_BF16_MLP;   // the fused BF16 kernels read bf16 rows
     void* rows = W.aev;
     hipError_t e = launch_species_group(m, n, species, W.mw, m->flags, s);
     if (e == hipSuccess) e = launch_zero_pad_rows(W.mw, m->aev.stride, rows, bfa, s);
@@ -542,7 +635,10 @@ nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float*
         else e = launch_permute_rows(true, W.mw.prow, n, m->aev.stride, aev_in, (float*)W.aev, s);
     }
     if (e == hipSuccess) {
-        if (fused) e = launch_mlp_fused(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, s);
+        if (m->n_nets > 1)
+            e = launch_mlp_ensemble(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, W.d1, W.E_net,
+                                    nullptr, s);
+        else if (fused) e = launch_mlp_fused(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, s);
         else e = launch_mlp(m, W.mw, W.aev, false, W.h, daev_out ? W.g : nullptr, W.E_row, nullptr, s);
     }
     if (e == hipSuccess) e = launch_gather_e(W.mw.prow, n, species, self_e(m), W.E_row, e_atom, s);

@@ -21,6 +21,7 @@
 //   BF16 form: v_mfma_f32_16x16x32_bf16 (float32 accumulation)
 // Only the AEV tile is read from and dE/dAEV written to HBM; activations
 // never leave the CU.
+#include <cstring>
 #include <type_traits>
 
 #include "nnp_internal.hpp"
@@ -78,14 +79,16 @@ __device__ __forceinline__ f32x4 mfma_step<true>(const uint16_t* act, int ld, in
 // FP32 pack: [nb][K/16][64 lanes][4]   BF16 pack: [nb][K/32][64 lanes][8]
 // The next k-step's B fragments are loaded before the current step's MFMAs
 // (register double buffering), so their latency hides behind the MFMAs.
-template <bool BF, int MB, int NCB, int K>
+template <bool BF, int MB, int NCB, int K, bool kZero = true>
 __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int ld, const void* Bpack, int nb0,
                                          f32x4 (&acc)[MB][NCB]) {
     const int l = lane_id();
+    if (kZero) {
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
     if (!BF) {
         constexpr int NK = K / 16;
         const float4* B = (const float4*)Bpack;
@@ -148,7 +151,10 @@ __device__ __forceinline__ void put_act<false>(float* act, int idx, float v) { a
 template <>
 __device__ __forceinline__ void put_act<true>(uint16_t* act, int idx, float v) { act[idx] = f32_to_bf16(v); }
 
-struct FusedArgs {
+}  // namespace
+
+// One network's weights for every species (device table, one entry per network).
+struct FusedNet {
     const void* Bf1[kMaxSpecies];   // forward packs
     const void* Bf2[kMaxSpecies];
     const void* Bf3[kMaxSpecies];
@@ -160,6 +166,12 @@ struct FusedArgs {
     const float* b3[kMaxSpecies];
     const float* w4[kMaxSpecies];   // head weights, padded to N3
     float b4[kMaxSpecies];
+};
+
+namespace {
+
+struct FusedArgs {
+    const FusedNet* nets;            // [n_nets] (device)
     const int32_t* meta;
     const int32_t* row_atom;
     const void* aev;                 // [rows][K0] float32 or bf16
@@ -168,9 +180,16 @@ struct FusedArgs {
     float* E_atomo;                  // [n] atom order or null
     float alpha;
     int ns;
+    // ensemble front (kEns): per network, d1 = dE/dh1 [n_nets][rows][N1] (act type) and E [n_nets][rows]
+    void* d1_out;
+    float* E_net;
+    int rows;
 };
 
-template <bool BF, int TM>
+// kEns: network blockIdx.y of an ensemble; stops after d1 (the adjoint of the
+// first layer sums over networks, k_ens_adj1) and writes this network's
+// energies to E_net.
+template <bool BF, int TM, bool kEns>
 __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     typedef typename Cfg<BF>::act_t act_t;
     constexpr int MB = TM / 16;
@@ -192,6 +211,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     if (row0 >= meta[8 + s] + meta[s]) return;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     const float alpha = A.alpha;
+    const int net = kEns ? blockIdx.y : 0;
+    const FusedNet& NT = A.nets[net];
 
     // ---------------- layer 1: K0 -> N1, A streamed from HBM through LDS
     f32x4 h1[MB][4];
@@ -223,8 +244,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 }
             }
         };
-        const float4* Bf = (const float4*)A.Bf1[s];
-        const u16x8* Bb = (const u16x8*)A.Bf1[s];
+        const float4* Bf = (const float4*)NT.Bf1[s];
+        const u16x8* Bb = (const u16x8*)NT.Bf1[s];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -291,7 +312,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     }
     // epilogue 1: h1 = CELU(z1 + b1) (kept), act = h1
     {
-        const float* b1 = A.b1[s];
+        const float* b1 = NT.b1[s];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -308,10 +329,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     __syncthreads();
     // ---------------- layer 2: N1 -> N2
     f32x4 h2[MB][3];
-    gemm_act<BF, MB, 3, N1>(act, LD, A.Bf2[s], 3 * w, h2);
+    gemm_act<BF, MB, 3, N1>(act, LD, NT.Bf2[s], 3 * w, h2);
     __syncthreads();
     {
-        const float* b2 = A.b2[s];
+        const float* b2 = NT.b2[s];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -329,10 +350,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     // ---------------- layer 3: N2 -> N3 (160 padded to 192), head, d3
     {
         f32x4 z3[MB][3];
-        gemm_act<BF, MB, 3, N2>(act, LD, A.Bf3[s], 3 * w, z3);
+        gemm_act<BF, MB, 3, N2>(act, LD, NT.Bf3[s], 3 * w, z3);
         __syncthreads();
-        const float* b3 = A.b3[s];
-        const float* w4 = A.w4[s];
+        const float* b3 = NT.b3[s];
+        const float* w4 = NT.w4[s];
         float part[MB][4];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -364,17 +385,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     }
     __syncthreads();
     if (t < TM) {
-        const float e = ((epart[t][0] + epart[t][1]) + (epart[t][2] + epart[t][3])) + A.b4[s];
+        const float e = ((epart[t][0] + epart[t][1]) + (epart[t][2] + epart[t][3])) + NT.b4[s];
         const int row = row0 + t;
-        A.E_row[row] = e;
-        const int a = A.row_atom[row];
-        if (a >= 0 && A.E_atomo) A.E_atomo[a] = e;
+        if (kEns) {
+            A.E_net[(size_t)net * A.rows + row] = e;
+        } else {
+            A.E_row[row] = e;
+            const int a = A.row_atom[row];
+            if (a >= 0 && A.E_atomo) A.E_atomo[a] = e;
+        }
     }
     if (!A.g_out) return;
     // ---------------- adjoint 3: d2 = (W3^T d3) * CELU'(h2)
     {
         f32x4 d[MB][3];
-        gemm_act<BF, MB, 3, N3>(act, LD, A.Ba3[s], 3 * w, d);
+        gemm_act<BF, MB, 3, N3>(act, LD, NT.Ba3[s], 3 * w, d);
         __syncthreads();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -391,7 +416,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     // ---------------- adjoint 2: d1 = (W2^T d2) * CELU'(h1)
     {
         f32x4 d[MB][4];
-        gemm_act<BF, MB, 4, N2>(act, LD, A.Ba2[s], 4 * w, d);
+        gemm_act<BF, MB, 4, N2>(act, LD, NT.Ba2[s], 4 * w, d);
         __syncthreads();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -405,11 +430,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
             }
     }
     __syncthreads();
+    if (kEns) {
+        // d1 tile out (this network's slice); the first layer's adjoint sums over networks
+        act_t* dst = (act_t*)A.d1_out + ((size_t)net * A.rows + row0) * N1;
+        for (int q = t; q < TM * N1; q += kThreads) dst[q] = act[(q / N1) * LD + (q % N1)];
+        return;
+    }
     // ---------------- adjoint 1: g = W1^T d1, 1024 columns, 4 passes of 64 per wave
     for (int pass = 0; pass < 4; ++pass) {
         f32x4 gacc[MB][4];
         const int nb0 = 16 * w + 4 * pass;
-        gemm_act<BF, MB, 4, N1>(act, LD, A.Ba1[s], nb0, gacc);
+        gemm_act<BF, MB, 4, N1>(act, LD, NT.Ba1[s], nb0, gacc);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -419,6 +450,68 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 for (int r = 0; r < 4; ++r)
                     A.g_out[(size_t)(row0 + 16 * mb + 4 * (l >> 4) + r) * K0 + col] = gacc[mb][nb][r];
             }
+    }
+}
+
+// Ensemble, first layer's adjoint summed over networks:
+//   g = (1 / n_nets) sum_net W1_net^T d1_net    (one GEMM with K = 256 n_nets)
+// and the ensemble-mean energies.  Block (tile, pass): 16-column blocks
+// 16 w + 4 pass .. + 3 of each wave, as in the single-network kernel.
+template <bool BF, int TM>
+__global__ __launch_bounds__(kThreads, 2) void k_ens_adj1(const FusedArgs A, int n_nets, float inv_nets,
+                                                         float* E_atom_net, int n_atoms) {
+    typedef typename Cfg<BF>::act_t act_t;
+    constexpr int MB = TM / 16;
+    constexpr int LD = Cfg<BF>::kLd;
+    __shared__ __attribute__((aligned(16))) act_t act[TM * LD];
+    const int row0 = blockIdx.x * TM, pass = blockIdx.y;
+    const int32_t* meta = A.meta;
+    if (row0 >= meta[8 + A.ns]) return;
+    int s = 0;
+    for (int q = 1; q < A.ns; ++q)
+        if (meta[8 + q] <= row0) s = q;
+    if (row0 >= meta[8 + s] + meta[s]) return;
+    const int t = threadIdx.x, w = t / kWave, l = lane_id();
+    constexpr int kVec = 16 / (int)sizeof(act_t);
+    typedef typename std::conditional<BF, u16x8, float4>::type vec_t;
+    f32x4 acc[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int nb0 = 16 * w + 4 * pass;
+    for (int net = 0; A.g_out && net < n_nets; ++net) {
+        const act_t* src = (const act_t*)A.d1_out + ((size_t)net * A.rows + row0) * N1;
+        for (int q = t * kVec; q < TM * N1; q += kThreads * kVec)
+            *(vec_t*)(act + (q / N1) * LD + (q % N1)) = *(const vec_t*)(src + q);
+        __syncthreads();
+        gemm_act<BF, MB, 4, N1, false>(act, LD, A.nets[net].Ba1[s], nb0, acc);
+        __syncthreads();
+    }
+    if (A.g_out) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int col = 16 * (nb0 + nb) + (l & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    A.g_out[(size_t)(row0 + 16 * mb + 4 * (l >> 4) + r) * K0 + col] = acc[mb][nb][r] * inv_nets;
+            }
+    }
+    if (pass == 0 && t < TM) {
+        const int row = row0 + t;
+        float e = 0.f;
+        for (int net = 0; net < n_nets; ++net) e += A.E_net[(size_t)net * A.rows + row];
+        e *= inv_nets;
+        A.E_row[row] = e;
+        const int a = A.row_atom[row];
+        if (a >= 0) {
+            if (A.E_atomo) A.E_atomo[a] = e;
+            if (E_atom_net)
+                for (int net = 0; net < n_nets; ++net)
+                    E_atom_net[(size_t)net * n_atoms + a] = A.E_net[(size_t)net * A.rows + row];
+        }
     }
 }
 
@@ -489,27 +582,46 @@ size_t pack_fused_species(char* dst, bool bf16, const float* W1, const float* W2
     return off;
 }
 
-hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,
-                            float* E_atomo, int n_atoms, hipStream_t s) {
-    const bool bf = m->precision == NNP_BF16_MLP;
-    FusedArgs A;
-    const int ns = m->aev.ns;
+size_t fused_net_bytes() { return sizeof(FusedNet); }
+
+// Fills the device-table entry of one network (host copy) from its packs and
+// bias / head arrays.
+void fused_net_entry(void* out, int ns, const char* const* packs, const float* const* b1, const float* const* b2,
+                     const float* const* b3, const float* const* w4, const float* b4, bool bf16) {
+    FusedNet& E = *(FusedNet*)out;
+    std::memset(&E, 0, sizeof(E));
+    const size_t unit = bf16 ? 2 : 4;
+    const int KN[6][2] = {{K0, N1}, {N1, N2}, {N2, N3}, {N3, N2}, {N2, N1}, {N1, K0}};
+    const void** dst[6] = {E.Bf1, E.Bf2, E.Bf3, E.Ba3, E.Ba2, E.Ba1};
     for (int q = 0; q < ns; ++q) {
-        const char* base = (const char*)(bf ? m->fused_bf16[q] : m->fused_fp32[q]);
-        const size_t unit = bf ? 2 : 4;
         size_t off = 0;
-        const int KN[6][2] = {{K0, N1}, {N1, N2}, {N2, N3}, {N3, N2}, {N2, N1}, {N1, K0}};
-        const void** dst[6] = {A.Bf1, A.Bf2, A.Bf3, A.Ba3, A.Ba2, A.Ba1};
         for (int k = 0; k < 6; ++k) {
-            dst[k][q] = base + off;
+            dst[k][q] = packs[q] + off;
             off += ((size_t)KN[k][0] * KN[k][1] * unit + 255) & ~(size_t)255;
         }
-        A.b1[q] = m->ptrs.b[q][0];
-        A.b2[q] = m->ptrs.b[q][1];
-        A.b3[q] = m->ptrs.b[q][2];
-        A.w4[q] = m->ptrs.head_w[q];
-        A.b4[q] = m->ptrs.head_b[q];
+        E.b1[q] = b1[q];
+        E.b2[q] = b2[q];
+        E.b3[q] = b3[q];
+        E.w4[q] = w4[q];
+        E.b4[q] = b4[q];
     }
+}
+
+namespace {
+
+// tile height: enough tiles to fill the chip twice over (the FP32 form stops at
+// 32 rows: its 64-row tile does not fit the register file)
+int fused_tile_rows(int n_atoms, bool bf) {
+    int tm = n_atoms >= 48 * 1024 ? 64 : (n_atoms >= 12 * 1024 ? 32 : 16);
+    if (!bf && tm > 32) tm = 32;
+    return tm;
+}
+
+FusedArgs fused_args(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row, float* E_atomo) {
+    const bool bf = m->precision == NNP_BF16_MLP;
+    FusedArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.nets = (const FusedNet*)(bf ? m->fused_tab_bf16 : m->fused_tab_fp32);
     A.meta = W.meta;
     A.row_atom = W.row_atom;
     A.aev = aev;
@@ -517,19 +629,64 @@ hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev,
     A.E_row = E_row;
     A.E_atomo = E_atomo;
     A.alpha = m->celu_alpha;
-    A.ns = ns;
-    // tile height: enough tiles to fill the chip twice over (the FP32 form stops at
-    // 32 rows: its 64-row tile does not fit the register file)
-    int tm = n_atoms >= 48 * 1024 ? 64 : (n_atoms >= 12 * 1024 ? 32 : 16);
-    if (!bf && tm > 32) tm = 32;
+    A.ns = m->aev.ns;
+    A.rows = W.rows_max;
+    return A;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,
+                            float* E_atomo, int n_atoms, hipStream_t s) {
+    const bool bf = m->precision == NNP_BF16_MLP;
+    const FusedArgs A = fused_args(m, W, aev, g_out, E_row, E_atomo);
+    const int tm = fused_tile_rows(n_atoms, bf);
     const int grid = ceil_div(W.rows_max, tm);
     if (bf) {
-        if (tm == 64) k_mlp_fused<true, 64><<<grid, kThreads, 0, s>>>(A);
-        else if (tm == 32) k_mlp_fused<true, 32><<<grid, kThreads, 0, s>>>(A);
-        else k_mlp_fused<true, 16><<<grid, kThreads, 0, s>>>(A);
+        if (tm == 64) k_mlp_fused<true, 64, false><<<grid, kThreads, 0, s>>>(A);
+        else if (tm == 32) k_mlp_fused<true, 32, false><<<grid, kThreads, 0, s>>>(A);
+        else k_mlp_fused<true, 16, false><<<grid, kThreads, 0, s>>>(A);
     } else {
-        if (tm == 32) k_mlp_fused<false, 32><<<grid, kThreads, 0, s>>>(A);
-        else k_mlp_fused<false, 16><<<grid, kThreads, 0, s>>>(A);
+        if (tm == 32) k_mlp_fused<false, 32, false><<<grid, kThreads, 0, s>>>(A);
+        else k_mlp_fused<false, 16, false><<<grid, kThreads, 0, s>>>(A);
+    }
+    return hipGetLastError();
+}
+
+// Ensemble of m->n_nets networks on the shared features: every network's
+// forward and adjoint down to d1 (grid.y = network), then the first layer's
+// adjoint summed over networks and the mean energies.  d1_scratch:
+// [n_nets][rows_max][256] (float32-sized), E_net: [n_nets][rows_max];
+// E_atom_net: [n_nets][n_atoms] per-network atomic energies or null.
+hipError_t launch_mlp_ensemble(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,
+                               float* E_atomo, int n_atoms, void* d1_scratch, float* E_net, float* E_atom_net,
+                               hipStream_t s) {
+    const bool bf = m->precision == NNP_BF16_MLP;
+    FusedArgs A = fused_args(m, W, aev, g_out, E_row, E_atomo);
+    A.d1_out = d1_scratch;
+    A.E_net = E_net;
+    const int tm = fused_tile_rows(n_atoms, bf);
+    const dim3 g1(ceil_div(W.rows_max, tm), m->n_nets), g2(ceil_div(W.rows_max, tm), g_out ? 4 : 1);
+    const float inv = 1.f / (float)m->n_nets;
+    if (bf) {
+        if (tm == 64) {
+            k_mlp_fused<true, 64, true><<<g1, kThreads, 0, s>>>(A);
+            k_ens_adj1<true, 64><<<g2, kThreads, 0, s>>>(A, m->n_nets, inv, E_atom_net, n_atoms);
+        } else if (tm == 32) {
+            k_mlp_fused<true, 32, true><<<g1, kThreads, 0, s>>>(A);
+            k_ens_adj1<true, 32><<<g2, kThreads, 0, s>>>(A, m->n_nets, inv, E_atom_net, n_atoms);
+        } else {
+            k_mlp_fused<true, 16, true><<<g1, kThreads, 0, s>>>(A);
+            k_ens_adj1<true, 16><<<g2, kThreads, 0, s>>>(A, m->n_nets, inv, E_atom_net, n_atoms);
+        }
+    } else {
+        if (tm == 32) {
+            k_mlp_fused<false, 32, true><<<g1, kThreads, 0, s>>>(A);
+            k_ens_adj1<false, 32><<<g2, kThreads, 0, s>>>(A, m->n_nets, inv, E_atom_net, n_atoms);
+        } else {
+            k_mlp_fused<false, 16, true><<<g1, kThreads, 0, s>>>(A);
+            k_ens_adj1<false, 16><<<g2, kThreads, 0, s>>>(A, m->n_nets, inv, E_atom_net, n_atoms);
+        }
     }
     return hipGetLastError();
 }

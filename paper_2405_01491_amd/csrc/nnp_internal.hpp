@@ -68,9 +68,11 @@ struct nnp_model {
     void* host_stage;                 // pinned host staging for synchronous reads
     bool fused;                       // widths match the fused 1008-256-192-160-1 kernel
     bool force_unfused;               // use the per-layer GEMM path (testing / comparison)
-    void* fused_dev;
-    const void* fused_fp32[nnp::kMaxSpecies];   // fragment-ordered weight packs (float32)
-    const void* fused_bf16[nnp::kMaxSpecies];   // (bfloat16)
+    int n_nets;                       // networks of the ensemble (1: a single network)
+    void* fused_dev;                  // fragment-ordered weight packs, biases, head weights of every network
+    void* fused_tab;                  // device tables of per-network pointers (float32 and bfloat16 forms)
+    const void* fused_tab_fp32;
+    const void* fused_tab_bf16;
     struct nnp_prof* prof;            // per-stage event timing (host side)
 };
 
@@ -169,7 +171,8 @@ struct EfOpts {
 nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
                               int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,
                               float* forces, void* ws, size_t ws_bytes, hipStream_t s, unsigned* flags,
-                              double* virial = nullptr, float* atom_virial = nullptr, const EfOpts* opts = nullptr);
+                              double* virial = nullptr, float* atom_virial = nullptr, const EfOpts* opts = nullptr,
+                              double* e_mol_net = nullptr);
 nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev,
                                 int64_t* total_host);
 
@@ -186,6 +189,12 @@ hipError_t launch_zero_pad_rows(const MlpWs& W, int stride, void* aev, bool bf16
 hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool aev_bf16, float* const* h,
                       float* g_out, float* E_row, float* E_atomo, hipStream_t s);
 bool fused_mlp_shape(const int* widths, int n_layers, int ns);
+size_t fused_net_bytes();
+void fused_net_entry(void* out, int ns, const char* const* packs, const float* const* b1, const float* const* b2,
+                     const float* const* b3, const float* const* w4, const float* b4, bool bf16);
+hipError_t launch_mlp_ensemble(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,
+                               float* E_atomo, int n_atoms, void* d1_scratch, float* E_net, float* E_atom_net,
+                               hipStream_t s);
 size_t pack_fused_species(char* dst, bool bf16, const float* W1, const float* W2, const float* W3, int n_in, int n3);
 uint16_t host_bf16_bits(float f);
 hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,

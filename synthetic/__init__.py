@@ -9,7 +9,7 @@ that computes the method.
 Units: Angstrom, femtosecond, amu, eV.  Species are indices 0..6 in the order
 H, C, N, O, F, S, Cl.
 """
-from .params import ModelSpec, ani2x_like_spec, SPECIES, SPECIES_INDEX, MASSES
+from .params import ModelSpec, ani2x_like_spec, ani2x_like_ensemble, SPECIES, SPECIES_INDEX, MASSES
 from .geometry import (
     Workload,
     water_cluster,
@@ -23,7 +23,7 @@ from .geometry import (
 from .weights import glorot_weights
 
 __all__ = [
-    "ModelSpec", "ani2x_like_spec", "SPECIES", "SPECIES_INDEX", "MASSES",
+    "ModelSpec", "ani2x_like_spec", "ani2x_like_ensemble", "SPECIES", "SPECIES_INDEX", "MASSES",
     "Workload", "water_cluster", "water_box", "organic_box", "serving_molecule",
     "serving_stream", "workload", "adversarial_cases", "glorot_weights",
 ]

@@ -35,6 +35,7 @@ class ModelSpec:
     celu_alpha: float
     weights: list = field(default_factory=list)   # [species][layer] -> (W [out,in] f32, b [out] f32)
     self_energy: np.ndarray = None                 # [n_species] f64
+    ensemble: list = None                          # [net] -> weights as above (net 0 is `weights`)
 
     @property
     def n_shf_r(self):
@@ -83,4 +84,15 @@ def ani2x_like_spec(weight_seed=123456, bias_scale=0.0, self_energy=None):
     spec.weights = glorot_weights(7, widths, weight_seed, bias_scale)
     spec.self_energy = (np.zeros(7) if self_energy is None
                         else np.asarray(self_energy, dtype=np.float64))
+    return spec
+
+
+def ani2x_like_ensemble(n_nets=8, weight_seed=123456, bias_scale=0.0, self_energy=None):
+    """An ensemble of n_nets networks of the same shape on one AEV (ANI-2x
+    has eight).  Network k draws its weights from seed weight_seed + k, so
+    network 0 is the single network of ani2x_like_spec(weight_seed)."""
+    from .weights import glorot_weights
+    spec = ani2x_like_spec(weight_seed, bias_scale, self_energy)
+    spec.ensemble = [spec.weights] + [glorot_weights(spec.n_species, spec.widths, weight_seed + k, bias_scale)
+                                      for k in range(1, n_nets)]
     return spec

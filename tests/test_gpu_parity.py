@@ -266,3 +266,44 @@ def test_virial_parity(spec_bias, case):
     # the forces of the virial call are those of the plain call
     _, _, F = nnp.nnp_energy_forces(m, pos, sp, mol, w.n_mol, w.box, nl)
     assert torch.equal(F, out["forces"])
+
+
+@pytest.mark.parametrize("case", ["organic_box", "batch"])
+def test_ensemble_parity(case):
+    """Ensemble of eight networks on one AEV: mean energies and forces and
+    every network's structure energies against the oracle (FP32)."""
+    spec = synthetic.ani2x_like_ensemble(n_nets=8, weight_seed=4242, bias_scale=0.05,
+                                         self_energy=np.array([-0.6, -38.0, -54.7, -75.1, -99.8, -398.1, -460.1]))
+    w = organic(1500) if case == "organic_box" else synthetic.workload(4, n_mol=10)
+    m = nnp.Model(spec, "fp32")
+    assert m.n_nets == 8 and m.fused_mlp
+    pos, sp, mol = to_dev(w)
+    nl = nnp.nnp_neighbors(m, pos, mol, w.n_mol, w.box, 5.1)
+    e_mol, e_net, e_atom, F = nnp.nnp_energy_forces_ensemble(m, pos, sp, mol, w.n_mol, w.box, nl, e_atom=True)
+    ref = oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec,
+                               need_nets=True)
+    ee = energy_error(e_atom.cpu().numpy(), ref["E_atom"])
+    fe = np.abs(F.cpu().numpy() - ref["F"]).max()
+    ne = np.abs(e_net.cpu().numpy() - ref["E_mol_net"]).max() / np.abs(ref["E_mol_net"]).max()
+    me = np.abs(e_mol.cpu().numpy() - ref["E_mol"]).max() / np.abs(ref["E_mol"]).max()
+    print("ensemble %s: E_atom err %.3g, E_mol rel %.3g, per-net E_mol rel %.3g, F max %.3g"
+          % (case, ee, me, ne, fe))
+    assert ee < E_ATOM_REL and me < 1e-5 and ne < 1e-5 and fe < F_MAX_ABS
+    # the plain entry point gives the same mean energies and forces
+    e2, _, F2 = nnp.nnp_energy_forces(m, pos, sp, mol, w.n_mol, w.box, nl)
+    assert torch.equal(e2, e_mol) and torch.equal(F2, F)
+
+
+def test_ensemble_bf16_matches_emulation():
+    spec = synthetic.ani2x_like_ensemble(n_nets=4, weight_seed=99, bias_scale=0.05)
+    w = organic(1200)
+    m = nnp.Model(spec, "bf16")
+    pos, sp, _ = to_dev(w)
+    nl = nnp.nnp_neighbors(m, pos, None, 1, w.box, 5.1)
+    _, e_atom, F = nnp.nnp_energy_forces(m, pos, sp, None, 1, w.box, nl, e_atom=True)
+    emu = oracle.energy_forces(w.pos, w.species, None, 1, w.box, spec, precision="bf16")
+    rms = np.sqrt(np.mean(emu["E_atom"] ** 2))
+    emed, emax = bf16_flip_error(e_atom.cpu().numpy(), emu["E_atom"], rms)
+    fe = np.abs(F.cpu().numpy() - emu["F"]).max()
+    print("ensemble bf16 vs emulation (median, max): E/rms %.3g %.3g, F max %.3g" % (emed, emax, fe))
+    assert emed < 1e-5 and emax < 1e-2 and fe < 2e-2

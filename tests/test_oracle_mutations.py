@@ -124,3 +124,13 @@ def test_mutant_virial_sign(monkeypatch, spec_bias):
         return orig(nl, -v, G, mol, n_mol, n_atoms)
     monkeypatch.setattr(oforces, "virial_from_edges", bad)
     assert _fails(pins.test_virial_of_open_structure_is_sum_x_outer_F, spec_bias)
+
+
+def test_mutant_ensemble_self_energy_per_network(monkeypatch):
+    # the self energy kept in every network's energy and added again after the mean
+    orig = omlp._single_net
+
+    def bad(aev, species, spec, precision, need_grad, weights, with_self=True):
+        return orig(aev, species, spec, precision, need_grad, weights, with_self=True)
+    monkeypatch.setattr(omlp, "_single_net", bad)
+    assert _fails(pins.test_ensemble_is_the_mean_of_its_networks)

@@ -545,3 +545,52 @@ def test_baoab_free_particles(spec):
     z = v * np.sqrt(masses[:, None] / (oracle.md.KB_EV * T * oracle.md.ACC_UNIT))
     want = 1.0 - np.exp(-2 * 200.0 * 1e-3 * 1.0 * 40)
     assert abs(z.var() - want) < 6 * np.sqrt(2 / (3 * n))
+
+
+# ---------------------------------------------------------------- ensemble
+
+def _ensemble_spec(k, seed=321):
+    return synthetic.ani2x_like_ensemble(n_nets=k, weight_seed=seed, bias_scale=0.1,
+                                         self_energy=np.array([-0.6, -38.0, -54.7, -75.1, -99.8, -398.1, -460.1]))
+
+
+def _single(spec, k):
+    import copy
+    s = copy.copy(spec)
+    s.weights = spec.ensemble[k]
+    s.ensemble = None
+    return s
+
+
+def test_ensemble_is_the_mean_of_its_networks():
+    """Energies, atomic energies, forces and per-network structure energies of
+    a 3-network ensemble against three separate single-network evaluations."""
+    spec = _ensemble_spec(3)
+    w = synthetic.workload(4, n_mol=3)
+    ens = oracle.energy_forces(w.pos, w.species, w.mol, w.n_mol, None, spec, need_nets=True)
+    singles = [oracle.energy_forces(w.pos, w.species, w.mol, w.n_mol, None, _single(spec, k)) for k in range(3)]
+    for key in ("E_mol", "E_atom", "F"):
+        ref = np.mean([o[key] for o in singles], axis=0)
+        assert np.max(np.abs(ens[key] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), key
+    net = np.stack([o["E_mol"] for o in singles])
+    assert np.max(np.abs(ens["E_mol_net"] - net)) <= 1e-12 * np.max(np.abs(net))
+
+
+def test_ensemble_of_identical_networks_is_the_network():
+    spec = _ensemble_spec(1)
+    spec.ensemble = [spec.weights] * 4
+    w = synthetic.workload(1)
+    a = oracle.energy_forces(w.pos, w.species, None, 1, None, spec)
+    b = oracle.energy_forces(w.pos, w.species, None, 1, None, _single(spec, 0))
+    assert abs(a["E_mol"][0] - b["E_mol"][0]) <= 1e-12 * abs(b["E_mol"][0])
+    assert np.max(np.abs(a["F"] - b["F"])) <= 1e-12
+
+
+def test_ensemble_forces_match_finite_differences():
+    spec = _ensemble_spec(2, seed=77)
+    w = synthetic.workload(1)
+    out = oracle.energy_forces(w.pos, w.species, None, 1, None, spec)
+    nl = oracle.neighbor_list(w.pos, None, None, 7.0)
+    atoms = [0, 11, 40, 71]
+    F_fd = _fd_forces(w.pos.astype(np.float64), w.species, None, spec, nl, atoms)
+    assert np.max(np.abs(out["F"][atoms] - F_fd)) <= 1e-7 * max(1.0, np.max(np.abs(F_fd)))
