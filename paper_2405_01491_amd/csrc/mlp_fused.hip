@@ -36,6 +36,7 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr int K0 = 1024, N1 = 256, N2 = 192, N3 = 192;
 constexpr int kThreads = 256;
 
+
 template <bool BF>
 struct Cfg;
 template <>
@@ -212,7 +213,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     const float alpha = A.alpha;
     const int net = kEns ? blockIdx.y : 0;
-    const FusedNet& NT = A.nets[net];
+    // this network's and species' pointers, loaded once (the table is read-only)
+    const FusedNet* __restrict__ tab = A.nets + net;
+    const void* const pBf1 = tab->Bf1[s];
+    const void* const pBf2 = tab->Bf2[s];
+    const void* const pBf3 = tab->Bf3[s];
+    const void* const pBa3 = tab->Ba3[s];
+    const void* const pBa2 = tab->Ba2[s];
+    const void* const pBa1 = tab->Ba1[s];
+    const float* const pb1 = tab->b1[s];
+    const float* const pb2 = tab->b2[s];
+    const float* const pb3 = tab->b3[s];
+    const float* const pw4 = tab->w4[s];
+    const float hb4 = tab->b4[s];
 
     // ---------------- layer 1: K0 -> N1, A streamed from HBM through LDS
     f32x4 h1[MB][4];
@@ -244,8 +257,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 }
             }
         };
-        const float4* Bf = (const float4*)NT.Bf1[s];
-        const u16x8* Bb = (const u16x8*)NT.Bf1[s];
+        const float4* Bf = (const float4*)pBf1;
+        const u16x8* Bb = (const u16x8*)pBf1;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -312,7 +325,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     }
     // epilogue 1: h1 = CELU(z1 + b1) (kept), act = h1
     {
-        const float* b1 = NT.b1[s];
+        const float* b1 = pb1;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -329,10 +342,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     __syncthreads();
     // ---------------- layer 2: N1 -> N2
     f32x4 h2[MB][3];
-    gemm_act<BF, MB, 3, N1>(act, LD, NT.Bf2[s], 3 * w, h2);
+    gemm_act<BF, MB, 3, N1>(act, LD, pBf2, 3 * w, h2);
     __syncthreads();
     {
-        const float* b2 = NT.b2[s];
+        const float* b2 = pb2;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -350,10 +363,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     // ---------------- layer 3: N2 -> N3 (160 padded to 192), head, d3
     {
         f32x4 z3[MB][3];
-        gemm_act<BF, MB, 3, N2>(act, LD, NT.Bf3[s], 3 * w, z3);
+        gemm_act<BF, MB, 3, N2>(act, LD, pBf3, 3 * w, z3);
         __syncthreads();
-        const float* b3 = NT.b3[s];
-        const float* w4 = NT.w4[s];
+        const float* b3 = pb3;
+        const float* w4 = pw4;
         float part[MB][4];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -385,7 +398,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     }
     __syncthreads();
     if (t < TM) {
-        const float e = ((epart[t][0] + epart[t][1]) + (epart[t][2] + epart[t][3])) + NT.b4[s];
+        const float e = ((epart[t][0] + epart[t][1]) + (epart[t][2] + epart[t][3])) + hb4;
         const int row = row0 + t;
         if (kEns) {
             A.E_net[(size_t)net * A.rows + row] = e;
@@ -399,7 +412,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     // ---------------- adjoint 3: d2 = (W3^T d3) * CELU'(h2)
     {
         f32x4 d[MB][3];
-        gemm_act<BF, MB, 3, N3>(act, LD, NT.Ba3[s], 3 * w, d);
+        gemm_act<BF, MB, 3, N3>(act, LD, pBa3, 3 * w, d);
         __syncthreads();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -416,7 +429,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     // ---------------- adjoint 2: d1 = (W2^T d2) * CELU'(h1)
     {
         f32x4 d[MB][4];
-        gemm_act<BF, MB, 4, N2>(act, LD, NT.Ba2[s], 4 * w, d);
+        gemm_act<BF, MB, 4, N2>(act, LD, pBa2, 4 * w, d);
         __syncthreads();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -440,7 +453,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     for (int pass = 0; pass < 4; ++pass) {
         f32x4 gacc[MB][4];
         const int nb0 = 16 * w + 4 * pass;
-        gemm_act<BF, MB, 4, N1>(act, LD, NT.Ba1[s], nb0, gacc);
+        gemm_act<BF, MB, 4, N1>(act, LD, pBa1, nb0, gacc);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
