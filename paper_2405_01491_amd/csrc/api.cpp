@@ -145,7 +145,7 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.Gz = (float*)take(sizeof(float) * c);
     W.Wat = (float*)take(sizeof(float) * 9 * (size_t)nn);
     W.vpart = (double*)take(sizeof(double) * virial_partial_doubles(nn));
-    if (m->n_nets > 1) {
+    if (mlp_split(m, nn)) {
         W.d1 = take(sizeof(float) * (size_t)m->n_nets * rows_max * 256);
         W.E_net = (float*)take(sizeof(float) * (size_t)m->n_nets * rows_max);
         W.E_at_net = (float*)take(sizeof(float) * (size_t)m->n_nets * nn);
@@ -236,7 +236,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
         prof_end(m, NNP_STAGE_AEV, s);
         prof_begin(m, NNP_STAGE_MLP, s);
         if (e == hipSuccess) {
-            if (m->n_nets > 1)
+            if (mlp_split(m, n) && !(m->force_unfused && m->n_nets == 1))
                 e = launch_mlp_ensemble(m, W.mw, W.aev, forces ? W.g : nullptr, W.E_row, W.E_at, n, W.d1, W.E_net,
                                         e_mol_net ? W.E_at_net : nullptr, s);
             else if (m->fused && !m->force_unfused)
@@ -635,7 +635,7 @@ nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float*
         else e = launch_permute_rows(true, W.mw.prow, n, m->aev.stride, aev_in, (float*)W.aev, s);
     }
     if (e == hipSuccess) {
-        if (m->n_nets > 1)
+        if (fused && mlp_split(m, n))
             e = launch_mlp_ensemble(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, W.d1, W.E_net,
                                     nullptr, s);
         else if (fused) e = launch_mlp_fused(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, s);

@@ -30,8 +30,14 @@ namespace nnp {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Weight packs are read through global-address-space pointers: their
+// addresses come from a table in memory, and as generic (flat) pointers the
+// loads would also count against the LDS wait counter, so every wait for an
+// LDS read would wait for the prefetched weights as well.
+typedef __attribute__((address_space(1))) const f32x4 gfloat4;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(1))) const u16x8 gu16x8;
 
 constexpr int K0 = 1024, N1 = 256, N2 = 192, N3 = 192;
 constexpr int kThreads = 256;
@@ -92,8 +98,8 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
     }
     if (!BF) {
         constexpr int NK = K / 16;
-        const float4* B = (const float4*)Bpack;
-        float4 b[NCB], bn[NCB];
+        const gfloat4* B = (const gfloat4*)Bpack;
+        f32x4 b[NCB], bn[NCB];
 #pragma unroll
         for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * NK + 0) * 64 + l];
         for (int kq = 0; kq < NK; ++kq) {
@@ -120,7 +126,7 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
         }
     } else {
         constexpr int NK = K / 32;
-        const u16x8* B = (const u16x8*)Bpack;
+        const gu16x8* B = (const gu16x8*)Bpack;
         u16x8 b[NCB], bn[NCB];
 #pragma unroll
         for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * NK + 0) * 64 + l];
@@ -257,8 +263,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 }
             }
         };
-        const float4* Bf = (const float4*)pBf1;
-        const u16x8* Bb = (const u16x8*)pBf1;
+        const gfloat4* Bf = (const gfloat4*)pBf1;
+        const gu16x8* Bb = (const gu16x8*)pBf1;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -266,9 +272,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         // B fragments of global k-step t (FP32: 16 k per step; BF16: 32), prefetched one step ahead
         constexpr int KS = BF ? 32 : 16;
         constexpr int NT = K0 / KS, TPC = CH / KS;
-        float4 bf[4], bfn[4];
+        f32x4 bf[4], bfn[4];
         u16x8 bb[4], bbn[4];
-        auto loadB = [&](int t, float4 (&df)[4], u16x8 (&db)[4]) {
+        auto loadB = [&](int t, f32x4 (&df)[4], u16x8 (&db)[4]) {
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) {
                 if (!BF) df[nb] = Bf[((size_t)(4 * w + nb) * NT + t) * 64 + l];
@@ -596,6 +602,15 @@ size_t pack_fused_species(char* dst, bool bf16, const float* W1, const float* W2
 }
 
 size_t fused_net_bytes() { return sizeof(FusedNet); }
+
+// Ensembles run as the two-kernel split (every network's forward and adjoint
+// down to d1, then the first-layer adjoint summed over networks).  For one
+// network the split measured within a few per cent of the fused kernel at
+// 2,048-8,192 atoms (and slower in BF16), so a single network stays fused.
+bool mlp_split(const nnp_model* m, int n_atoms) {
+    (void)n_atoms;
+    return m->fused && m->n_nets > 1;
+}
 
 // Fills the device-table entry of one network (host copy) from its packs and
 // bias / head arrays.

@@ -190,6 +190,7 @@ hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool 
                       float* g_out, float* E_row, float* E_atomo, hipStream_t s);
 bool fused_mlp_shape(const int* widths, int n_layers, int ns);
 size_t fused_net_bytes();
+bool mlp_split(const nnp_model* m, int n_atoms);
 void fused_net_entry(void* out, int ns, const char* const* packs, const float* const* b1, const float* const* b2,
                      const float* const* b3, const float* const* w4, const float* b4, bool bf16);
 hipError_t launch_mlp_ensemble(const nnp_model* m, const MlpWs& W, const void* aev, float* g_out, float* E_row,
