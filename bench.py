@@ -392,7 +392,6 @@ def main():
         result["config"]["integrator"] = args.integrator
         result["config"]["rebuilds"] = info["rebuilds"]
         result["config"]["early_rebuilds"] = info["early_rebuilds"]
-        result["config"]["list_replays"] = info["replays"]
     models = {precision: model}
     if args.config != 3:
         # the other precision form on the same workload, beside the primary one

@@ -308,15 +308,13 @@ typedef struct {
     float trigger;            /* early rebuild threshold in units of skin / 2     */
     int32_t log_every;        /* > 0: record (E_pot, E_kin) every log_every steps */
     int32_t log_capacity;     /* rows kept (later rows are dropped)               */
-    float capacity_slack;     /* list capacity = pairs needed * (1 + slack)      */
 } nnp_md_params;
 
 typedef struct {
     int64_t steps;            /* steps taken since creation                       */
     int64_t rebuilds;         /* list builds, the one at creation included        */
     int64_t early_rebuilds;   /* builds triggered by displacement                 */
-    int64_t replays;          /* runs replayed after a list regrow                */
-    int64_t capacity;         /* current list capacity (pairs)                    */
+    int64_t capacity;         /* list slots: n_atoms * NNP_MAX_ROW                */
     float r_list;
 } nnp_md_stats;
 
@@ -325,18 +323,20 @@ typedef struct nnp_md nnp_md;
 /* Create an engine for n_atoms atoms: pos, vel (A/fs) device float32
  * [n][3], species device int32 [n], masses device float32 [n] (amu, > 0),
  * box_host host float32 [3] or NULL.  Inputs are copied; the engine owns
- * its device memory (allocated here and when the list regrows).  Builds the
- * list (synchronously) and the starting forces.  The model must outlive it.
- * NNP_E_BOX if a box side is below 2 (cutoff + skin); NNP_E_NONFINITE for
- * non-finite positions or non-positive masses. */
+ * its device memory, all of it allocated here: the list is kept as
+ * fixed-stride rows of NNP_MAX_ROW slots per atom, so it never regrows.
+ * Builds the list and the starting forces (synchronises once).  The model
+ * must outlive it.  NNP_E_BOX if a box side is below 2 (cutoff + skin);
+ * NNP_E_NONFINITE for non-finite positions or non-positive masses;
+ * NNP_E_ROW if an atom has more than NNP_MAX_ROW neighbours. */
 nnp_status nnp_md_create(nnp_model* model, int32_t n_atoms, const float* pos, const float* vel,
                          const int32_t* species, const float* masses, const float* box_host,
                          const nnp_md_params* params, void* stream, nnp_md** out);
 /* Advance n_steps steps.  The steps are enqueued without waiting; the call
- * synchronises `stream` once at the end to read the error flags.  If a list
- * rebuild needed more room than the list has, the run is rolled back to its
- * start, the list regrown and the run replayed (same result).  Errors:
- * NNP_E_NONFINITE, NNP_E_ROW, NNP_E_CAPACITY (regrowth failed). */
+ * synchronises `stream` once at the end to read the error flags.  Errors
+ * (the state is then that of a run that went on with the faulty values;
+ * the step counter is not advanced): NNP_E_NONFINITE, NNP_E_ROW (a rebuild
+ * found an atom with more than NNP_MAX_ROW neighbours). */
 nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream);
 /* Copy the current state into caller device buffers (any may be NULL):
  * pos, vel, forces float32 [n][3], e_pot float64 [1].  Asynchronous. */

@@ -105,14 +105,14 @@ class MdParams(ctypes.Structure):
         ("integrator", ctypes.c_int32), ("dt", ctypes.c_float), ("temperature", ctypes.c_float),
         ("friction", ctypes.c_float), ("seed", ctypes.c_uint64), ("skin", ctypes.c_float),
         ("rebuild_every", ctypes.c_int32), ("trigger", ctypes.c_float), ("log_every", ctypes.c_int32),
-        ("log_capacity", ctypes.c_int32), ("capacity_slack", ctypes.c_float),
+        ("log_capacity", ctypes.c_int32),
     ]
 
 
 class MdStats(ctypes.Structure):
     _fields_ = [
         ("steps", ctypes.c_int64), ("rebuilds", ctypes.c_int64), ("early_rebuilds", ctypes.c_int64),
-        ("replays", ctypes.c_int64), ("capacity", ctypes.c_int64), ("r_list", ctypes.c_float),
+        ("capacity", ctypes.c_int64), ("r_list", ctypes.c_float),
     ]
 
 

@@ -74,11 +74,10 @@ struct Row {
 // Load the row and classify every slot.  Returns false (and flags) if the
 // row is longer than the kernels support.
 __device__ __forceinline__ bool load_row(Row& R, const AevConst& P, int i, const float* __restrict__ pos,
-                                         const int32_t* __restrict__ species, const BoxConst& bx,
-                                         const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                         const int8_t* __restrict__ shift, unsigned* flags) {
+                                         const int32_t* __restrict__ species, const BoxConst& bx, const RowsView& rows,
+                                         unsigned* flags) {
     const int l = lane_id();
-    const int b = row_ptr[i], e = row_ptr[i + 1];
+    const int b = rows.begin(i), e = rows.end(i);
     R.b = b;
     R.len = e - b;
     if (R.len > kMaxR) {
@@ -94,12 +93,8 @@ __device__ __forceinline__ bool load_row(Row& R, const AevConst& P, int i, const
         j[q] = -1;
         sx[q] = sy[q] = sz[q] = 0.f;
         if (p < e) {
-            j[q] = col[p];
-            if (bx.periodic) {
-                sx[q] = (float)shift[3 * p];
-                sy[q] = (float)shift[3 * p + 1];
-                sz[q] = (float)shift[3 * p + 2];
-            }
+            j[q] = rows.col[p];
+            if (bx.periodic) rows.shift3(p, sx[q], sy[q], sz[q]);
         }
     }
     const float rc_r2 = P.rc_r * P.rc_r, rc_a2 = P.rc_a * P.rc_a;
@@ -186,21 +181,36 @@ struct FwdLds {
 template <typename OutT>
 __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int8_t* __restrict__ shift,
-    const int32_t* __restrict__ out_row, OutT* __restrict__ out, unsigned* flags) {
+    const RowsView rows, const int32_t* __restrict__ out_row, OutT* __restrict__ out, unsigned* flags,
+    int32_t* __restrict__ rev_out, const int32_t* __restrict__ gate) {
     __shared__ FwdLds lds[kWaves];
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
     const int i = blockIdx.x * kWaves + w;
     if (i >= n) return;
     FwdLds& S = lds[w];
+    // fixed-stride rows just rebuilt: the reverse index of this row (the rows
+    // are sorted by neighbour, so j's slot of i is found by bisection)
+    if (rev_out && (!gate || *gate)) {
+        const int b = rows.begin(i), e = rows.end(i);
+        for (int p = b + l; p < e; p += kWave) {
+            const int j = rows.col[p];
+            const int bj = rows.begin(j);
+            int lo = bj, hi = rows.end(j);
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rows.col[mid] < i) lo = mid + 1; else hi = mid;
+            }
+            rev_out[p] = (lo < rows.end(j) && rows.col[lo] == i) ? lo : p;
+        }
+    }
     const int row = out_row ? out_row[i] : i;
     if (row < 0) return;   // atom without a grouped row (invalid species, flagged elsewhere)
     OutT* orow = out + (size_t)row * P.stride;
     const int ns = P.ns;
     Row R;
     int pr_[kQ], pa_[kQ];
-    if (!load_row(R, P, i, pos, species, bx, row_ptr, col, shift, flags) ||
+    if (!load_row(R, P, i, pos, species, bx, rows, flags) ||
         !group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, flags)) {
         for (int c = l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
         return;
@@ -306,9 +316,8 @@ struct BwdLds {
 template <bool kVir>
 __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int8_t* __restrict__ shift,
-    const int32_t* __restrict__ g_row, const float* __restrict__ g, float* __restrict__ Gx, float* __restrict__ Gy,
-    float* __restrict__ Gz, float* __restrict__ Wat, unsigned* flags) {
+    const RowsView rows, const int32_t* __restrict__ g_row, const float* __restrict__ g, float* __restrict__ Gx,
+    float* __restrict__ Gy, float* __restrict__ Gz, float* __restrict__ Wat, unsigned* flags) {
     __shared__ BwdLds lds[kWaves];
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
@@ -319,10 +328,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     Row R;
     int pr_[kQ], pa_[kQ];
     const int row = g_row ? g_row[i] : i;
-    const bool ok = load_row(R, P, i, pos, species, bx, row_ptr, col, shift, flags) &&
+    const bool ok = load_row(R, P, i, pos, species, bx, rows, flags) &&
                     group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, flags) && row >= 0;
     if (!ok) {
-        const int b = row_ptr[i], e = row_ptr[i + 1];
+        const int b = rows.begin(i), e = rows.end(i);
         for (int p = b + l; p < e; p += kWave) Gx[p] = Gy[p] = Gz[p] = 0.f;
         if (kVir && l < 9) Wat[9 * (size_t)i + l] = 0.f;
         return;
@@ -523,30 +532,30 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
 }  // namespace
 
 hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const nnp_nlist* nl, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
-                          hipStream_t s) {
+                          const RowsView& rows, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
+                          hipStream_t s, int32_t* rev_out, const int32_t* gate) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
     if (bf16)
-        k_aev_fwd<uint16_t><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift,
-                                                            out_row, (uint16_t*)out, flags);
+        k_aev_fwd<uint16_t><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, out_row, (uint16_t*)out,
+                                                            flags, rev_out, gate);
     else
-        k_aev_fwd<float><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift,
-                                                         out_row, (float*)out, flags);
+        k_aev_fwd<float><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, out_row, (float*)out, flags,
+                                                         rev_out, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const nnp_nlist* nl, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
+                          const RowsView& rows, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
                           float* atom_virial, unsigned* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
     if (atom_virial)
-        k_aev_bwd<true><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift, g_row,
-                                                        g, Gx, Gy, Gz, atom_virial, flags);
+        k_aev_bwd<true><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, Gx, Gy, Gz,
+                                                        atom_virial, flags);
     else
-        k_aev_bwd<false><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, nl->row_ptr, nl->col, nl->shift,
-                                                         g_row, g, Gx, Gy, Gz, nullptr, flags);
+        k_aev_bwd<false><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, Gx, Gy, Gz, nullptr,
+                                                         flags);
     return hipGetLastError();
 }
 

@@ -222,6 +222,8 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     hipError_t e = hipSuccess;
     const MdBack* md = opts ? opts->md : nullptr;
     if (md && (!forces || virial || atom_virial)) return NNP_E_ARG;
+    const RowsView rows = opts && opts->rows ? *opts->rows : rows_csr(nl);
+    if (opts && opts->rows && nl->capacity < (int64_t)n * NNP_MAX_ROW) return NNP_E_ARG;
     if (n > 0 && !(opts && opts->skip_group)) {
         prof_begin(m, NNP_STAGE_GROUP, s);
         e = launch_species_group(m, n, species, W.mw, flags, s);
@@ -232,7 +234,8 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     }
     if (n > 0) {
         prof_begin(m, NNP_STAGE_AEV, s);
-        if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.aev, bf, flags, s);
+        if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.aev, bf, flags, s,
+                               opts ? opts->rev_out : nullptr, opts ? opts->gate : nullptr);
         prof_end(m, NNP_STAGE_AEV, s);
         prof_begin(m, NNP_STAGE_MLP, s);
         if (e == hipSuccess) {
@@ -260,7 +263,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     if (e == hipSuccess && forces && n > 0) {
         prof_begin(m, NNP_STAGE_AEV_ADJ, s);
         float* wat = virial || atom_virial ? (atom_virial ? atom_virial : W.Wat) : nullptr;
-        e = launch_aev_bwd(m->aev, n, pos, species, bx, nl, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, wat, flags, s);
+        e = launch_aev_bwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, wat, flags, s);
         prof_end(m, NNP_STAGE_AEV_ADJ, s);
         prof_begin(m, NNP_STAGE_FORCES, s);
         if (e == hipSuccess) {
@@ -272,9 +275,9 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
                 ein.E_at = W.E_at;
                 for (int k = 0; k < kMaxSpecies; ++k) ein.se[k] = m->self_energy[k];
                 ein.e_pot = e_mol;
-                e = md_launch_back(n, nl, W.Gx, W.Gy, W.Gz, forces, *md, &ein, s);
+                e = md_launch_back(n, rows, W.Gx, W.Gy, W.Gz, forces, *md, &ein, s);
             } else {
-                e = launch_force_gather(n, nl, W.Gx, W.Gy, W.Gz, forces, s);
+                e = launch_force_gather(n, rows, W.Gx, W.Gy, W.Gz, forces, s);
             }
         }
         prof_end(m, NNP_STAGE_FORCES, s);
@@ -613,7 +616,7 @@ nnp_status nnp_aev(nnp_model* m, int32_t n, const float* pos, const int32_t* spe
     (void)ws_bytes;
     if (!m || !nl || n < 0 || (n > 0 && (!pos || !species || !aev_out))) return NNP_E_ARG;
     if (nl->n_atoms != n) return NNP_E_ARG;
-    return hip_status(launch_aev_fwd(m->aev, n, pos, species, box_const(box_host), nl, nullptr, aev_out, false,
+    return hip_status(launch_aev_fwd(m->aev, n, pos, species, box_const(box_host), rows_csr(nl), nullptr, aev_out, false,
                                      m->flags, (hipStream_t)stream));
 }
 

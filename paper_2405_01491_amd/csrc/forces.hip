@@ -13,7 +13,7 @@ namespace {
 
 constexpr int kLanesPerAtom = 16;
 
-__global__ __launch_bounds__(256) void k_force_gather(int n, const int32_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(256) void k_force_gather(int n, const RowsView rows,
                                                      const int32_t* __restrict__ rev, const float* __restrict__ Gx,
                                                      const float* __restrict__ Gy, const float* __restrict__ Gz,
                                                      float* __restrict__ F) {
@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, const int32_t* __re
     const int sub = threadIdx.x % kLanesPerAtom;
     float fx = 0.f, fy = 0.f, fz = 0.f;
     if (a < n) {
-        const int b = row_ptr[a], e = row_ptr[a + 1];
+        const int b = rows.begin(a), e = rows.end(a);
         for (int p = b + sub; p < e; p += kLanesPerAtom) {
             const int q = rev[p];
             fx += Gx[p] - Gx[q];
@@ -153,10 +153,10 @@ hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_force_gather(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
+hipError_t launch_force_gather(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz, float* F,
                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_force_gather<<<ceil_div((long)n * kLanesPerAtom, 256), 256, 0, s>>>(n, nl->row_ptr, nl->rev, Gx, Gy, Gz, F);
+    k_force_gather<<<ceil_div((long)n * kLanesPerAtom, 256), 256, 0, s>>>(n, rows, rows.rev, Gx, Gy, Gz, F);
     return hipGetLastError();
 }
 

@@ -67,20 +67,20 @@ __global__ void k_md_wrap_ref(int n, float* pos, float* ref, BoxConst bx, const 
 
 // Force gather (16 lanes per atom over its row, F_a = sum_j G_aj - G_ja, as
 // in k_force_gather), the last half kick and per-block float64 kinetic
-// energies (eV), in one kernel.  With kEnergy, block 0 first sums the
-// structure energy in float64 (per-thread sums in ascending atom order, then
-// a fixed tree).
+// energies (eV), in one kernel.  With kEnergy, one extra block (the last)
+// sums the structure energy in float64 (per-thread sums in ascending atom
+// order, then a fixed tree) while the others gather.
 constexpr int kBackThreads = 256, kBackLanes = 16, kBackAtoms = kBackThreads / kBackLanes;
 
 template <bool kEnergy>
-__global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const int32_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const RowsView rows,
                                                          const int32_t* __restrict__ rev, const float* __restrict__ Gx,
                                                          const float* __restrict__ Gy, const float* __restrict__ Gz,
                                                          float* __restrict__ F, float* __restrict__ vel,
                                                          const float* __restrict__ inv_mass, float dt, double* ke_part,
                                                          const MdEnergyIn E) {
     __shared__ double red[kBackThreads];
-    if (kEnergy && blockIdx.x == 0) {
+    if (kEnergy && (int)blockIdx.x == (int)gridDim.x - 1) {
         double acc = 0.0;
         for (int a = threadIdx.x; a < n; a += kBackThreads)
             if (E.prow[a] >= 0) acc += (double)E.E_at[a] + E.se[E.species[a]];
@@ -91,13 +91,13 @@ __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const int32_t* 
             __syncthreads();
         }
         if (threadIdx.x == 0) *E.e_pot = red[0];
-        __syncthreads();
+        return;
     }
     const int a = blockIdx.x * kBackAtoms + threadIdx.x / kBackLanes;
     const int sub = threadIdx.x % kBackLanes;
     float fx = 0.f, fy = 0.f, fz = 0.f;
     if (a < n) {
-        const int b = row_ptr[a], e = row_ptr[a + 1];
+        const int b = rows.begin(a), e = rows.end(a);
         for (int p = b + sub; p < e; p += kBackLanes) {
             const int q = rev[p];
             fx += Gx[p] - Gx[q];
@@ -180,15 +180,15 @@ hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx,
 
 int md_ke_parts(int n) { return ceil_div(n > 0 ? n : 1, kBackAtoms); }
 
-hipError_t md_launch_back(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
+hipError_t md_launch_back(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s) {
     MdEnergyIn E{};
     if (e) E = *e;
     if (b.fuse_energy && e)
-        k_md_back<true><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, nl->row_ptr, nl->rev, Gx, Gy, Gz, F, b.vel,
-                                                                b.inv_mass, b.dt, b.ke_part, E);
+        k_md_back<true><<<md_ke_parts(n) + 1, kBackThreads, 0, s>>>(n, rows, rows.rev, Gx, Gy, Gz, F, b.vel,
+                                                                    b.inv_mass, b.dt, b.ke_part, E);
     else
-        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, nl->row_ptr, nl->rev, Gx, Gy, Gz, F, b.vel,
+        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, rows, rows.rev, Gx, Gy, Gz, F, b.vel,
                                                                  b.inv_mass, b.dt, b.ke_part, E);
     return hipGetLastError();
 }

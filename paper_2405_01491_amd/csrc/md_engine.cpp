@@ -6,13 +6,12 @@
 // every few steps).
 //
 // A run of K steps is enqueued in one go and synchronises once, at its end,
-// to read the error flags.  The list is built without reading its pair count
-// back; if a build needs more than the list's capacity the build is cut short
-// in bounds and flagged, and the run is rolled back to its starting state
-// (saved on the device at the start of the run), the list regrown and the run
-// replayed.  The replay draws the same noise (counter-based generator keyed
-// by step and atom), so the result does not depend on whether a regrow
-// happened.
+// to read the error flags.  The engine keeps the builder's fixed-stride rows
+// (row i at i * NNP_MAX_ROW, sorted by neighbour) instead of a compacted
+// list: a rebuild never needs the pair count, so nothing is read back and no
+// capacity can run out (a row longer than NNP_MAX_ROW is an error, as for
+// every list).  The reverse index of the rows is taken by the AEV kernel on
+// rebuild steps.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -34,7 +33,6 @@ struct nnp_md {
     MdStepConst c{};
     float trigger2 = -1.f;
     uint64_t step = 0;
-    uint64_t replays = 0;
     bool small = false;       // fused front / back kernels (md_front_fits)
     bool grouped = false;     // species grouping in ws_ef is current
     // device state
@@ -43,18 +41,15 @@ struct nnp_md {
     double* e_pot = nullptr;
     MdState* st = nullptr;
     unsigned* flags = nullptr;
-    int64_t* need = nullptr;
     double* ke_part = nullptr;
-    // snapshot for rollback
-    float *pos0 = nullptr, *vel0 = nullptr, *F0 = nullptr, *ref0 = nullptr;
-    double* e_pot0 = nullptr;
-    MdState* st0 = nullptr;
     // energy log [log_cap][2]
     double* log = nullptr;
     int log_cap = 0;
     int log_rows = 0;
-    // neighbour list and workspaces
+    // neighbour rows (in ws_nb), their reverse index (nl.rev) and workspaces;
+    // nl carries the list's extent for the energy call
     nnp_nlist nl{};
+    RowsView rows{};
     void* ws_nb = nullptr;
     size_t ws_nb_bytes = 0;
     void* ws_ef = nullptr;
@@ -69,25 +64,11 @@ hipError_t dmalloc(T** p, size_t count) {
     return hipMalloc((void**)p, sizeof(T) * (count > 0 ? count : 1));
 }
 
-void free_list(nnp_md* md) {
-    (void)hipFree(md->nl.col);
-    (void)hipFree(md->nl.shift);
-    (void)hipFree(md->nl.rev);
-    (void)hipFree(md->ws_ef);
-    md->nl.col = nullptr;
-    md->nl.shift = nullptr;
-    md->nl.rev = nullptr;
-    md->ws_ef = nullptr;
-}
-
-nnp_status alloc_list(nnp_md* md, int64_t capacity) {
-    free_list(md);
+nnp_status alloc_rows(nnp_md* md) {
+    const int64_t capacity = (int64_t)md->n * NNP_MAX_ROW;
     md->nl.capacity = capacity;
-    if (dmalloc(&md->nl.col, (size_t)capacity) != hipSuccess || dmalloc(&md->nl.shift, 3 * (size_t)capacity) != hipSuccess ||
-        dmalloc(&md->nl.rev, (size_t)capacity) != hipSuccess)
-        return NNP_E_NOMEM;
+    if (dmalloc(&md->nl.rev, (size_t)capacity) != hipSuccess) return NNP_E_NOMEM;
     md->ws_ef_bytes = nnp_workspace_bytes(md->model, md->n, capacity);
-    md->grouped = false;
     if (hipMalloc(&md->ws_ef, md->ws_ef_bytes) != hipSuccess) return NNP_E_NOMEM;
     return NNP_OK;
 }
@@ -95,37 +76,15 @@ nnp_status alloc_list(nnp_md* md, int64_t capacity) {
 nnp_status status_of_flags(unsigned fl) {
     if (fl & NNP_FLAG_NONFINITE) return NNP_E_NONFINITE;
     if (fl & NNP_FLAG_ROW) return NNP_E_ROW;
-    if (fl & NNP_FLAG_CAPACITY) return NNP_E_CAPACITY;
     return fl ? NNP_E_ARG : NNP_OK;
-}
-
-int64_t grown(const nnp_md* md, int64_t need) {
-    const int64_t c = need + (int64_t)((double)need * (double)md->p.capacity_slack);
-    return c > 1 ? c : 1;
-}
-
-// synchronous build from positions x that regrows until the list fits
-nnp_status build_sync(nnp_md* md, const float* x, hipStream_t s) {
-    const float* bptr = md->bx.periodic ? md->box : nullptr;
-    for (int attempt = 0; attempt < 8; ++attempt) {
-        int64_t need = 0;
-        nnp_status st = build_neighbors(md->model, md->n, x, nullptr, 1, bptr, md->r_list, &md->nl, &need,
-                                        md->ws_nb, md->ws_nb_bytes, s, true);
-        if (st == NNP_OK) return NNP_OK;
-        if (st != NNP_E_CAPACITY) return st;
-        // room for the list to grow as the system moves
-        st = alloc_list(md, grown(md, need));
-        if (st != NNP_OK) return st;
-    }
-    return NNP_E_CAPACITY;
 }
 
 // One step.  Small systems (md_front_fits): a fused front kernel (first half
 // step, displacement, rebuild decision, wrap and cell binning), the gated
-// row / scan / compaction kernels, AEV, networks, AEV adjoint, and a fused
-// back kernel (structure energy, force gather, last half kick): eight
-// launches.  Larger systems use the general multi-kernel path for the front
-// and the energy sum.
+// row kernel, AEV (with the reverse index on rebuild steps), networks, AEV
+// adjoint, and a fused back kernel (structure energy, force gather, last half
+// kick): six launches.  Larger systems use the general multi-kernel path for
+// the front, the cell binning and the energy sum.
 nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     nnp_model* m = md->model;
     const bool langevin = md->p.integrator == NNP_MD_LANGEVIN;
@@ -145,8 +104,10 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     prof_end(m, NNP_STAGE_INTEGRATE, s);
     if (e != hipSuccess) return NNP_E_HIP;
     nnp_status st = build_neighbors(m, md->n, md->pos, nullptr, 1, bptr, md->r_list, &md->nl, nullptr, md->ws_nb,
-                                    md->ws_nb_bytes, s, false, md->flags, &md->st->gate, md->need, md->small);
+                                    md->ws_nb_bytes, s, false, md->flags, &md->st->gate, nullptr, md->small,
+                                    &md->rows);
     if (st != NNP_OK) return st;
+    md->rows.rev = md->nl.rev;
     const bool log = md->p.log_every > 0 && ((step + 1) % (uint64_t)md->p.log_every) == 0 &&
                      md->log_rows < md->log_cap;
     MdBack back{};
@@ -158,6 +119,9 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     EfOpts opts;
     opts.skip_group = md->grouped;
     opts.md = &back;
+    opts.rows = &md->rows;
+    opts.rev_out = md->nl.rev;
+    opts.gate = &md->st->gate;
     st = energy_forces_impl(m, md->n, md->pos, md->species, nullptr, 1, bptr, &md->nl, md->e_pot, nullptr, md->F,
                             md->ws_ef, md->ws_ef_bytes, s, md->flags, nullptr, nullptr, &opts);
     if (st != NNP_OK) return st;
@@ -171,30 +135,12 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     return e == hipSuccess ? NNP_OK : NNP_E_HIP;
 }
 
-hipError_t copy_state(nnp_md* md, bool save, hipStream_t s) {
-    const size_t v3 = sizeof(float) * 3 * (size_t)md->n;
-    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
-    auto cp = [&](void* a, void* b, size_t bytes) {   // save: a -> b
-        return save ? hipMemcpyAsync(b, a, bytes, k, s) : hipMemcpyAsync(a, b, bytes, k, s);
-    };
-    hipError_t e = cp(md->pos, md->pos0, v3);
-    if (e == hipSuccess) e = cp(md->vel, md->vel0, v3);
-    if (e == hipSuccess) e = cp(md->F, md->F0, v3);
-    if (e == hipSuccess) e = cp(md->ref, md->ref0, v3);
-    if (e == hipSuccess) e = cp(md->e_pot, md->e_pot0, sizeof(double));
-    if (e == hipSuccess) e = cp(md->st, md->st0, sizeof(MdState));
-    return e;
-}
-
-// reads and clears the engine's flags and the required list size
-nnp_status read_flags(nnp_md* md, hipStream_t s, unsigned* fl, int64_t* need) {
-    char* h = (char*)md->host;
-    if (hipMemcpyAsync(h, md->flags, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(h + 8, md->need, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+// reads and clears the engine's flags
+nnp_status read_flags(nnp_md* md, hipStream_t s, unsigned* fl) {
+    if (hipMemcpyAsync(md->host, md->flags, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return NNP_E_HIP;
-    std::memcpy(fl, h, sizeof(unsigned));
-    std::memcpy(need, h + 8, sizeof(int64_t));
+    std::memcpy(fl, md->host, sizeof(unsigned));
     if (*fl && hipMemsetAsync(md->flags, 0, sizeof(unsigned), s) != hipSuccess) return NNP_E_HIP;
     return NNP_OK;
 }
@@ -210,7 +156,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     const nnp_md_params& p = *params;
     if (p.integrator != NNP_MD_NVE && p.integrator != NNP_MD_LANGEVIN) return NNP_E_ARG;
     if (!(p.dt > 0.f) || !std::isfinite(p.dt) || p.rebuild_every < 1 || !(p.skin >= 0.f) || p.log_every < 0 ||
-        p.log_capacity < 0 || !(p.capacity_slack >= 0.f))
+        p.log_capacity < 0)
         return NNP_E_ARG;
     if (p.integrator == NNP_MD_LANGEVIN && (!(p.temperature >= 0.f) || !(p.friction >= 0.f))) return NNP_E_ARG;
     hipStream_t s = (hipStream_t)stream;
@@ -250,12 +196,8 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
               dmalloc(&md->F, v3) == hipSuccess && dmalloc(&md->ref, v3) == hipSuccess &&
               dmalloc(&md->inv_mass, (size_t)n) == hipSuccess && dmalloc(&md->species, (size_t)n) == hipSuccess &&
               dmalloc(&md->e_pot, 1) == hipSuccess && dmalloc(&md->st, 1) == hipSuccess &&
-              dmalloc(&md->flags, 1) == hipSuccess && dmalloc(&md->need, 1) == hipSuccess &&
-              dmalloc(&md->ke_part, (size_t)md_ke_parts(n)) == hipSuccess && dmalloc(&md->pos0, v3) == hipSuccess &&
-              dmalloc(&md->vel0, v3) == hipSuccess && dmalloc(&md->F0, v3) == hipSuccess &&
-              dmalloc(&md->ref0, v3) == hipSuccess && dmalloc(&md->e_pot0, 1) == hipSuccess &&
-              dmalloc(&md->st0, 1) == hipSuccess && dmalloc(&md->log, 2 * (size_t)(md->log_cap > 0 ? md->log_cap : 1)) == hipSuccess &&
-              dmalloc(&md->nl.row_ptr, (size_t)n + 1) == hipSuccess &&
+              dmalloc(&md->flags, 1) == hipSuccess && dmalloc(&md->ke_part, (size_t)md_ke_parts(n)) == hipSuccess &&
+              dmalloc(&md->log, 2 * (size_t)(md->log_cap > 0 ? md->log_cap : 1)) == hipSuccess &&
               hipHostMalloc(&md->host, 64, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         nnp_md_destroy(md);
@@ -271,7 +213,6 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     if (e == hipSuccess) e = hipMemcpyAsync(md->species, species, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(md->st, 0, sizeof(MdState), s);
     if (e == hipSuccess) e = hipMemsetAsync(md->flags, 0, sizeof(unsigned), s);
-    if (e == hipSuccess) e = hipMemsetAsync(md->need, 0, sizeof(int64_t), s);
     if (e == hipSuccess) e = md_launch_inv_mass(n, masses, md->inv_mass, md->flags, s);
     // the starting configuration: wrapped, reference for displacements, list, forces
     MdState st0{};
@@ -285,19 +226,25 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     }
     st0.gate = 0;
     st0.rebuilds = 1;
-    nnp_status st = alloc_list(md, 1);
-    if (st == NNP_OK) st = build_sync(md, md->pos, s);
+    nnp_status st = alloc_rows(md);
+    if (st == NNP_OK)
+        st = build_neighbors(model, n, md->pos, nullptr, 1, box_host, md->r_list, &md->nl, nullptr, md->ws_nb,
+                             md->ws_nb_bytes, s, false, md->flags, nullptr, nullptr, false, &md->rows);
+    md->rows.rev = md->nl.rev;
     if (st == NNP_OK &&
         hipMemcpyAsync(md->st, &st0, sizeof(MdState), hipMemcpyHostToDevice, s) != hipSuccess)
         st = NNP_E_HIP;
-    if (st == NNP_OK)
+    if (st == NNP_OK) {
+        EfOpts opts;
+        opts.rows = &md->rows;
+        opts.rev_out = md->nl.rev;
         st = energy_forces_impl(model, n, md->pos, md->species, nullptr, 1, box_host, &md->nl, md->e_pot, nullptr,
-                                md->F, md->ws_ef, md->ws_ef_bytes, s, md->flags);
+                                md->F, md->ws_ef, md->ws_ef_bytes, s, md->flags, nullptr, nullptr, &opts);
+    }
     if (st == NNP_OK) md->grouped = true;
     if (st == NNP_OK) {
         unsigned fl = 0;
-        int64_t need = 0;
-        st = read_flags(md, s, &fl, &need);
+        st = read_flags(md, s, &fl);
         if (st == NNP_OK) st = status_of_flags(fl);
     }
     if (st != NNP_OK) {
@@ -312,35 +259,16 @@ nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream) {
     if (!md || n_steps < 0) return NNP_E_ARG;
     if (n_steps == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
-    if (copy_state(md, true, s) != hipSuccess) return NNP_E_HIP;
-    const int log_rows0 = md->log_rows;
-    for (int attempt = 0; attempt < 8; ++attempt) {
-        for (int k = 0; k < n_steps; ++k) {
-            nnp_status st = enqueue_step(md, md->step + (uint64_t)k, s);
-            if (st != NNP_OK) return st;
-        }
-        unsigned fl = 0;
-        int64_t need = 0;
-        nnp_status st = read_flags(md, s, &fl, &need);
+    for (int k = 0; k < n_steps; ++k) {
+        nnp_status st = enqueue_step(md, md->step + (uint64_t)k, s);
         if (st != NNP_OK) return st;
-        if (!(fl & NNP_FLAG_CAPACITY)) {
-            if (fl) return status_of_flags(fl);
-            md->step += (uint64_t)n_steps;
-            return NNP_OK;
-        }
-        if (fl & ~NNP_FLAG_CAPACITY) return status_of_flags(fl & ~NNP_FLAG_CAPACITY);
-        // roll back, regrow, rebuild the list the saved state was using (it was
-        // built from the reference positions, so it is reproduced exactly), replay
-        if (copy_state(md, false, s) != hipSuccess) return NNP_E_HIP;
-        md->log_rows = log_rows0;
-        if (hipStreamSynchronize(s) != hipSuccess) return NNP_E_HIP;
-        st = alloc_list(md, grown(md, need));
-        if (st == NNP_OK) st = build_sync(md, md->ref, s);
-        if (st != NNP_OK) return st;
-        if (hipMemsetAsync(md->need, 0, sizeof(int64_t), s) != hipSuccess) return NNP_E_HIP;
-        md->replays += 1;
     }
-    return NNP_E_CAPACITY;
+    unsigned fl = 0;
+    nnp_status st = read_flags(md, s, &fl);
+    if (st != NNP_OK) return st;
+    if (fl) return status_of_flags(fl);
+    md->step += (uint64_t)n_steps;
+    return NNP_OK;
 }
 
 nnp_status nnp_md_get(nnp_md* md, float* pos, float* vel, float* forces, double* e_pot, void* stream) {
@@ -380,7 +308,6 @@ nnp_status nnp_md_info(nnp_md* md, nnp_md_stats* out, void* stream) {
     out->steps = (int64_t)md->step;
     out->rebuilds = (int64_t)st.rebuilds;
     out->early_rebuilds = (int64_t)st.early_rebuilds;
-    out->replays = (int64_t)md->replays;
     out->capacity = md->nl.capacity;
     out->r_list = md->r_list;
     return NNP_OK;
@@ -388,10 +315,8 @@ nnp_status nnp_md_info(nnp_md* md, nnp_md_stats* out, void* stream) {
 
 void nnp_md_destroy(nnp_md* md) {
     if (!md) return;
-    free_list(md);
     void* bufs[] = {md->pos, md->vel, md->F, md->ref, md->inv_mass, md->species, md->e_pot, md->st, md->flags,
-                    md->need, md->ke_part, md->pos0, md->vel0, md->F0, md->ref0, md->e_pot0, md->st0, md->log,
-                    md->nl.row_ptr, md->ws_nb};
+                    md->ke_part, md->log, md->nl.rev, md->ws_ef, md->ws_nb};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (md->host) (void)hipHostFree(md->host);

@@ -66,7 +66,8 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t step, int a, floa
 template <bool kLangevin>
 __device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, float* __restrict__ vel,
                                                const float* __restrict__ F, const float* __restrict__ inv_mass,
-                                               const MdStepConst& c, uint64_t step, const float* __restrict__ ref) {
+                                               const MdStepConst& c, uint64_t step, const float* __restrict__ ref,
+                                               float* xout = nullptr) {
     const float im = inv_mass[a];
     const float kick = 0.5f * c.dt * kAccUnit * im;
     float x[3], v[3];
@@ -94,6 +95,7 @@ __device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, f
     for (int k = 0; k < 3; ++k) {
         vel[3 * a + k] = v[k];
         pos[3 * a + k] = x[k];
+        if (xout) xout[k] = x[k];
         const float d = x[k] - ref[3 * a + k];
         d2 += d * d;
     }
@@ -142,7 +144,7 @@ hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const 
 hipError_t md_launch_decide(MdState* st, int rebuild_every, float trigger2, hipStream_t s);
 hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx, const MdState* st, hipStream_t s);
 int md_ke_parts(int n);
-hipError_t md_launch_back(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
+hipError_t md_launch_back(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s);
 // neighbors.hip: the fused front of a step for small systems
 bool md_front_fits(int n, const float* box_host, float r_list);

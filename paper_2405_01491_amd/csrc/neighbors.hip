@@ -384,7 +384,12 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     __shared__ int s_gate;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     float d2 = 0.f;
-    for (int a = t; a < n; a += kFrontThreads) d2 = fmaxf(d2, md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref));
+    float xs[kFrontPer][3];   // this thread's atoms after the half step (kept for the wrap and binning)
+#pragma unroll
+    for (int k = 0; k < kFrontPer; ++k) {
+        const int a = t + k * kFrontThreads;
+        if (a < n) d2 = fmaxf(d2, md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref, xs[k]));
+    }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
     if (l == 0) s_max[w] = d2;
@@ -410,7 +415,7 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
         bool fin = true;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            float v = pos[3 * a + d];
+            float v = xs[k][d];
             fin = fin && isfinite(v);
             if (g.periodic && isfinite(v)) {
                 const float L = g.Lf[d];
@@ -580,7 +585,7 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host,
                            void* ws, size_t ws_bytes, hipStream_t s, bool sync, unsigned* flags_override,
-                           const int32_t* gate, int64_t* need_pairs, bool cells_ready) {
+                           const int32_t* gate, int64_t* need_pairs, bool cells_ready, RowsView* rows_out) {
     Grid g;
     nnp_status st = make_grid(box_host, r_list, &g);
     if (st != NNP_OK) return st;
@@ -631,6 +636,19 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         k_rows<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
             pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count, stage_col,
             stage_sh, flags, gate);
+    }
+    if (rows_out) {
+        RowsView r{};
+        r.count = row_count;
+        r.col = stage_col;
+        r.shift_packed = stage_sh;
+        *rows_out = r;
+        nl->n_atoms = n;
+        nl->r_list = r_list;
+        nl->n_pairs = -1;
+        prof_end(model, NNP_STAGE_NEIGHBORS, s);
+        chk(hipGetLastError());
+        return he == hipSuccess ? NNP_OK : NNP_E_HIP;
     }
     // asynchronous builds: the row pointers are cut at the capacity if the list
     // is longer (every later read stays in bounds), and the overflow flagged

@@ -154,10 +154,15 @@ size_t scan_tmp_elems(int n);
 size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host, float r_list);
 // sync == false: no pair-count readback (the caller guarantees the capacity),
 // device flags go to flags_override (or the model's flags if null).
+// rows_out: stop at the builder's fixed-stride rows (in ws) and describe them
+// there instead of compacting into nl (its CSR arrays are not touched; the
+// reverse index is left to the caller).
+struct RowsView;
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host, void* ws,
                            size_t ws_bytes, hipStream_t s, bool sync = true, unsigned* flags_override = nullptr,
-                           const int32_t* gate = nullptr, int64_t* need_pairs = nullptr, bool cells_ready = false);
+                           const int32_t* gate = nullptr, int64_t* need_pairs = nullptr, bool cells_ready = false,
+                           RowsView* rows_out = nullptr);
 struct MdBack;
 struct MdEnergyIn;
 // Options of the MD engine's calls: skip the species grouping (species and
@@ -166,6 +171,12 @@ struct MdEnergyIn;
 struct EfOpts {
     bool skip_group = false;
     const MdBack* md = nullptr;
+    // fixed-stride rows in place of nl's CSR arrays (nl->capacity must cover
+    // n * NNP_MAX_ROW); their reverse index is written to rev_out by the AEV
+    // kernel while gate is null or *gate != 0
+    const RowsView* rows = nullptr;
+    int32_t* rev_out = nullptr;
+    const int32_t* gate = nullptr;
 };
 // nnp_energy_forces with an explicit device flags word (n_pairs of nl is not checked)
 nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
@@ -176,11 +187,51 @@ nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const i
 nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int64_t* total_dev,
                                 int64_t* total_host);
 
+// Neighbour rows as the kernels read them: the ABI's CSR list, or the
+// builder's fixed-stride rows (the MD engine), where row i holds count[i]
+// pairs at i * NNP_MAX_ROW and each image shift is packed into one int32
+// ((x & 0xff) | (y & 0xff) << 8 | (z & 0xff) << 16).
+struct RowsView {
+    const int32_t* row_ptr;        // CSR, or null for fixed-stride rows
+    const int32_t* count;          // fixed-stride rows
+    const int32_t* col;
+    const int8_t* shift;           // CSR: int8 [pairs][3]
+    const int32_t* shift_packed;   // fixed-stride rows
+    const int32_t* rev;            // slot of the reverse pair
+    __device__ __forceinline__ int begin(int i) const { return row_ptr ? row_ptr[i] : i * NNP_MAX_ROW; }
+    __device__ __forceinline__ int end(int i) const {
+        return row_ptr ? row_ptr[i + 1] : i * NNP_MAX_ROW + count[i];
+    }
+    __device__ __forceinline__ void shift3(int p, float& x, float& y, float& z) const {
+        if (row_ptr) {
+            x = (float)shift[3 * p];
+            y = (float)shift[3 * p + 1];
+            z = (float)shift[3 * p + 2];
+        } else {
+            const int v = shift_packed[p];
+            x = (float)(int8_t)(v & 0xff);
+            y = (float)(int8_t)((v >> 8) & 0xff);
+            z = (float)(int8_t)((v >> 16) & 0xff);
+        }
+    }
+};
+
+inline RowsView rows_csr(const nnp_nlist* nl) {
+    RowsView r{};
+    r.row_ptr = nl->row_ptr;
+    r.col = nl->col;
+    r.shift = nl->shift;
+    r.rev = nl->rev;
+    return r;
+}
+
+// rev_out (fixed-stride rows only, may be null): the reverse index of each
+// row, written while gate is null or *gate != 0 (the rows were rebuilt)
 hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const nnp_nlist* nl, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
-                          hipStream_t s);
+                          const RowsView& rows, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
+                          hipStream_t s, int32_t* rev_out = nullptr, const int32_t* gate = nullptr);
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const nnp_nlist* nl, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
+                          const RowsView& rows, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
                           float* atom_virial, unsigned* flags, hipStream_t s);
 
 hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, unsigned* flags,
@@ -213,8 +264,8 @@ hipError_t launch_gather_e(const int32_t* prow, int n, const int32_t* species, c
 size_t virial_partial_doubles(int n);
 hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t* mend, const float* Wat, double* part,
                          double* virial, hipStream_t s);
-hipError_t launch_force_gather(int n, const nnp_nlist* nl, const float* Gx, const float* Gy, const float* Gz, float* F,
-                               hipStream_t s);
+hipError_t launch_force_gather(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz,
+                               float* F, hipStream_t s);
 hipError_t launch_kick_drift(int n, float* pos, float* vel, const float* F, const float* inv_mass, float dt,
                              const float* ref, float* max_d2, hipStream_t s);
 hipError_t launch_kick(int n, float* vel, const float* F, const float* inv_mass, float dt, hipStream_t s);

@@ -138,8 +138,7 @@ class MDEngine:
     synchronises once.  State lives in the engine; ``state()`` copies it out."""
 
     def __init__(self, model, pos, vel, species, masses, box=None, dt=0.5, integrator="nve", temperature=300.0,
-                 friction=1.0, seed=0, skin=0.0, rebuild_every=1, trigger=0.8, log_every=0, log_capacity=0,
-                 capacity_slack=0.25):
+                 friction=1.0, seed=0, skin=0.0, rebuild_every=1, trigger=0.8, log_every=0, log_capacity=0):
         L = lib()
         self.model = model
         self.dev = pos.device
@@ -149,7 +148,7 @@ class MDEngine:
         p.integrator = {"nve": 0, "langevin": 1}[integrator]
         p.dt, p.temperature, p.friction, p.seed = float(dt), float(temperature), float(friction), int(seed)
         p.skin, p.rebuild_every, p.trigger = float(skin), int(rebuild_every), float(trigger)
-        p.log_every, p.log_capacity, p.capacity_slack = int(log_every), int(log_capacity), float(capacity_slack)
+        p.log_every, p.log_capacity = int(log_every), int(log_capacity)
         self.params = p
         self.box = None if box is None else np.asarray(box, dtype=np.float32)
         bptr = None if box is None else (ctypes.c_float * 3)(*self.box.tolist())

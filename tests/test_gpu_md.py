@@ -144,22 +144,23 @@ def test_engine_langevin_tracks_oracle(spec_bias, precision):
     assert dx < 1e-4 * tol and dv < 1e-5 * tol
 
 
-def test_engine_replay_after_regrow_is_exact(spec):
-    """A list that must regrow mid-run rolls the run back and replays it: the
-    result is bit-identical to a run that never regrew."""
+def test_engine_split_runs_are_exact(spec):
+    """A run cut into pieces gives bit-for-bit the state of one run of the
+    same length: the noise is keyed by (step, atom), the rebuild decision and
+    the list rows live on the device across calls."""
     w = synthetic.geometry.small_water_box(64)
     masses = synthetic.MASSES[w.species]
     v0 = nmd.maxwell_boltzmann(masses, 600.0, seed=9)
     out = []
-    for slack in (0.0, 0.5):
+    for pieces in ((30,), (10, 7, 13)):
         model = nnp.Model(spec, "fp32")
         eng = _engine(model, w, v0, dt=0.5, integrator="langevin", temperature=600.0, friction=5.0, seed=3,
-                      rebuild_every=1, capacity_slack=slack)
-        for _ in range(3):
-            eng.run(10)
+                      skin=0.4, rebuild_every=5)
+        for k in pieces:
+            eng.run(k)
         out.append(([t.cpu() for t in eng.state()], eng.info()))
-    print("replays with no slack: %d, with slack: %d" % (out[0][1]["replays"], out[1][1]["replays"]))
-    assert out[1][1]["replays"] == 0
+    print("info: one run %s, pieces %s" % (out[0][1], out[1][1]))
+    assert out[0][1]["rebuilds"] == out[1][1]["rebuilds"] and out[0][1]["steps"] == 30
     for a, b in zip(out[0][0], out[1][0]):
         assert torch.equal(a, b)
 
