@@ -36,6 +36,15 @@ constexpr int kWaves = 4;                 // waves (atoms) per block
 
 __device__ __forceinline__ float cutoff_fc(float r, float pi_rc) { return 0.5f * __cosf(pi_rc * r) + 0.5f; }
 
+// The hardware's own approximations (v_sqrt_f32, v_rcp_f32, v_log_f32,
+// v_exp_f32, about 1 ulp each) without the library's denormal range
+// handling: every argument here is a normal number or zero, and a result
+// below the normal range is negligible next to the terms it is summed with.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
 __device__ __forceinline__ int species_pair(int s, int t, int ns) {
     if (s > t) { int u = s; s = t; t = u; }
     return s * ns - (s * (s - 1)) / 2 + (t - s);
@@ -44,7 +53,7 @@ __device__ __forceinline__ int species_pair(int s, int t, int ns) {
 // (j, k) of the v-th unordered pair (j < k) of c items in row-major triangle order
 __device__ __forceinline__ void tri_decode(int v, int c, int& j, int& k) {
     const float tc = (float)(2 * c - 1);
-    int jj = (int)((tc - sqrtf(fmaxf(tc * tc - 8.0f * (float)v, 0.f))) * 0.5f);
+    int jj = (int)((tc - hw_sqrt(fmaxf(tc * tc - 8.0f * (float)v, 0.f))) * 0.5f);
     jj = max(0, min(jj, c - 2));
     while (jj > 0 && (jj * (2 * c - jj - 1)) / 2 > v) --jj;
     while (jj + 1 <= c - 2 && ((jj + 1) * (2 * c - jj - 2)) / 2 <= v) ++jj;
@@ -52,9 +61,9 @@ __device__ __forceinline__ void tri_decode(int v, int c, int& j, int& k) {
     k = jj + 1 + (v - (jj * (2 * c - jj - 1)) / 2);
 }
 
-__device__ __forceinline__ float pow_zeta(float base, float zeta) {
-    return base > 0.f ? exp2f(zeta * __log2f(base)) : 0.f;
-}
+// base^zeta for base in [0, 1] (log2 0 = -inf gives 0; a base rounded below
+// zero is clamped)
+__device__ __forceinline__ float pow_zeta(float base, float zeta) { return hw_exp2(zeta * hw_log2(fmaxf(base, 0.f))); }
 
 template <typename OutT>
 __device__ __forceinline__ void store_out(OutT* p, float v);
@@ -218,11 +227,11 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         if (pr_[q] >= 0) {
-            const float r = sqrtf(R.r2[q]);
+            const float r = hw_sqrt(R.r2[q]);
             S.rr[pr_[q]] = r;
             S.rfc[pr_[q]] = cutoff_fc(r, P.pi_rc_r);
             if (pa_[q] >= 0) {
-                const float inv = r > 0.f ? 1.f / r : 0.f;
+                const float inv = r > 0.f ? hw_rcp(r) : 0.f;
                 S.au[pa_[q]] = make_float4(R.vx[q] * inv, R.vy[q] * inv, R.vz[q] * inv, r);
                 S.afc[pa_[q]] = cutoff_fc(r, P.pi_rc_a);
             }
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
                     float c = A.x * B.x + A.y * B.y + A.z * B.z;
                     c = fminf(1.f, fmaxf(-1.f, c));
                     const float uu = P.cs * c;
-                    const float sq = sqrtf(1.f - uu * uu);
+                    const float sq = hw_sqrt(1.f - uu * uu);
                     const float rbar = 0.5f * (A.w + B.w);
                     const float w2 = 2.f * S.afc[ja] * S.afc[ka];
 #pragma unroll
@@ -347,10 +356,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     float r_[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-        r_[q] = sqrtf(R.r2[q]);
+        r_[q] = hw_sqrt(R.r2[q]);
         if (pa_[q] >= 0) {
             const float r = r_[q];
-            const float inv = r > 0.f ? 1.f / r : 0.f;
+            const float inv = r > 0.f ? hw_rcp(r) : 0.f;
             S.au[pa_[q]] = make_float4(R.vx[q] * inv, R.vy[q] * inv, R.vz[q] * inv, r);
             S.afc[pa_[q]] = cutoff_fc(r, P.pi_rc_a);
             S.adfc[pa_[q]] = -0.5f * P.pi_rc_a * __sinf(P.pi_rc_a * r);
@@ -376,7 +385,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
                 dEdr += gs[k] * ek * (-2.f * P.eta_r * d * fc + dfc);
             }
             dEdr *= P.pr;
-            const float inv = r > 0.f ? 1.f / r : 0.f;
+            const float inv = r > 0.f ? hw_rcp(r) : 0.f;
             gx[q] = dEdr * R.vx[q] * inv;
             gy[q] = dEdr * R.vy[q] * inv;
             gz[q] = dEdr * R.vz[q] * inv;
@@ -396,7 +405,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
             float c = A.x * B.x + A.y * B.y + A.z * B.z;
             c = fminf(1.f, fmaxf(-1.f, c));
             const float uu = P.cs * c;
-            const float sq = sqrtf(1.f - uu * uu);
+            const float sq = hw_sqrt(1.f - uu * uu);
             const float rj = A.w, rk = B.w;
             const float rbar = 0.5f * (rj + rk);
             const float fj = S.afc[ja], fk = S.afc[ka];
@@ -412,16 +421,14 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
             }
             float Rz[kNa] = {0.f, 0.f, 0.f, 0.f};
             float sum_c = 0.f, Ssum = 0.f;
-            const float inv_sq = 1.f / sq;
+            const float inv_sq = hw_rcp(sq);
 #pragma unroll
             for (int z = 0; z < kNz; ++z) {
-                const float base = 0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]);
-                float F1 = 0.f, dF1 = 0.f;
-                if (base > 0.f) {
-                    const float lg = __log2f(base);
-                    F1 = exp2f(P.zeta * lg);
-                    dF1 = 0.5f * P.zeta * exp2f((P.zeta - 1.f) * lg);
-                }
+                // base^zeta and its derivative; base = 0 gives log2 = -inf and both 0
+                const float base = fmaxf(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), 0.f);
+                const float lg = hw_log2(base);
+                const float F1 = hw_exp2(P.zeta * lg);
+                const float dF1 = 0.5f * P.zeta * hw_exp2((P.zeta - 1.f) * lg);
                 const float dwdu = P.cos_z[z] - uu * P.sin_z[z] * inv_sq;
                 float Q = 0.f;
 #pragma unroll
@@ -441,8 +448,8 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
             const float dEdrbar = ff * sum_r;
             const float sj = 0.5f * dEdrbar + 2.f * fk * Ssum * dfj;
             const float sk = 0.5f * dEdrbar + 2.f * fj * Ssum * dfk;
-            const float ij = rj > 0.f ? 1.f / rj : 0.f;
-            const float ik = rk > 0.f ? 1.f / rk : 0.f;
+            const float ij = rj > 0.f ? hw_rcp(rj) : 0.f;
+            const float ik = rk > 0.f ? hw_rcp(rk) : 0.f;
             S.pb[l][0] = dEdc * (B.x - c * A.x) * ij + sj * A.x;
             S.pb[l][1] = dEdc * (B.y - c * A.y) * ij + sj * A.y;
             S.pb[l][2] = dEdc * (B.z - c * A.z) * ij + sj * A.z;
