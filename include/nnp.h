@@ -339,7 +339,9 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n_atoms, const float* pos, co
  * found an atom with more than NNP_MAX_ROW neighbours). */
 nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream);
 /* Copy the current state into caller device buffers (any may be NULL):
- * pos, vel, forces float32 [n][3], e_pot float64 [1].  Asynchronous. */
+ * pos, vel, forces float32 [n][3], e_pot float64 [1] (the potential energy
+ * of the current positions: a run sums it on its last step and on logged
+ * steps only).  Asynchronous. */
 nnp_status nnp_md_get(nnp_md* md, float* pos, float* vel, float* forces, double* e_pot,
                       void* stream);
 /* Copy up to max_rows logged rows {E_pot, E_kin} (eV, float64) to host

@@ -20,8 +20,9 @@
 //             per lane (8 angle factors, 4 radial factors) into a 64-pair LDS
 //             tile, reduced by lanes as (a, z) columns in two halves.
 //   adjoint:  radial gradient by the lane that holds the slot; angular pair
-//             gradients one pair per lane into an LDS tile, gathered per
-//             neighbour in a fixed order.
+//             gradients one pair per lane into an LDS tile of up to 192
+//             pairs, then summed per angular neighbour in a fixed order (one
+//             pass over the tile, the same trip count for every lane).
 // Every sum runs in a fixed order (no atomics), so results do not depend on
 // scheduling or on the other atoms of a batch.
 #include "nnp_internal.hpp"
@@ -308,13 +309,17 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
 
 // ---------------------------------------------------------------- adjoint
 
+constexpr int kPairTile = 3 * kWave;     // angular pairs held at once by the adjoint
+
 struct BwdLds {
     float g[1280];              // dE/dAEV row of the atom
     float4 au[kMaxA];           // angular list: unit vector, r
     float afc[kMaxA], adfc[kMaxA];
     int azs[kMaxA];             // species | slot << 8
-    float pb[kWave][7];         // pair tile: contributions to the two edges
-    float ga[kMaxA][3];         // angular gradient per angular neighbour
+    union {
+        float pb[kPairTile][6]; // pair tile: contributions to the two edges
+        float ga[kMaxA][3];     // then: angular gradient per angular neighbour
+    };
     unsigned char amap[kMaxR];  // slot -> angular index (255: none)
     int seg_r[kMaxSpecies + 1];
     int seg_a[kMaxSpecies + 1];
@@ -391,98 +396,99 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
             gz[q] = dEdr * R.vz[q] * inv;
         }
     }
-    // ---- angular: unordered pairs in triangle order over the species-grouped list
+    // ---- angular: unordered pairs (j < k) of the species-grouped list in
+    // triangle order, one per lane, into a tile of up to kPairTile pairs; then
+    // every angular neighbour m sums its contributions from the tile in a
+    // fixed order: pairs (j, m) by ascending j, then pairs (m, k) by ascending k
     const int n_a = S.seg_a[ns];
     const int total = n_a * (n_a - 1) / 2;
     float ax_[2] = {0.f, 0.f}, ay_[2] = {0.f, 0.f}, az_[2] = {0.f, 0.f};
-    int jptr[2] = {0, 0};
-    for (int u0 = 0; u0 < total; u0 += kWave) {
-        const int u = u0 + l;
-        if (u < total) {
-            int ja, ka;
-            tri_decode(u, n_a, ja, ka);
-            const float4 A = S.au[ja], B = S.au[ka];
-            float c = A.x * B.x + A.y * B.y + A.z * B.z;
-            c = fminf(1.f, fmaxf(-1.f, c));
-            const float uu = P.cs * c;
-            const float sq = hw_sqrt(1.f - uu * uu);
-            const float rj = A.w, rk = B.w;
-            const float rbar = 0.5f * (rj + rk);
-            const float fj = S.afc[ja], fk = S.afc[ka];
-            const float dfj = S.adfc[ja], dfk = S.adfc[ka];
-            const int pp = species_pair(S.azs[ja] & 0xff, S.azs[ka] & 0xff, ns);
-            const float* gp = &S.g[P.radial_dim + 32 * pp];
-            float F2[kNa], dF2[kNa];
-#pragma unroll
-            for (int a = 0; a < kNa; ++a) {
-                const float d = rbar - P.shf_a[a];
-                F2[a] = __expf(-P.eta_a * d * d);
-                dF2[a] = -2.f * P.eta_a * d * F2[a];
-            }
-            float Rz[kNa] = {0.f, 0.f, 0.f, 0.f};
-            float sum_c = 0.f, Ssum = 0.f;
-            const float inv_sq = hw_rcp(sq);
-#pragma unroll
-            for (int z = 0; z < kNz; ++z) {
-                // base^zeta and its derivative; base = 0 gives log2 = -inf and both 0
-                const float base = fmaxf(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), 0.f);
-                const float lg = hw_log2(base);
-                const float F1 = hw_exp2(P.zeta * lg);
-                const float dF1 = 0.5f * P.zeta * hw_exp2((P.zeta - 1.f) * lg);
-                const float dwdu = P.cos_z[z] - uu * P.sin_z[z] * inv_sq;
-                float Q = 0.f;
+    for (int c0 = 0; c0 < total; c0 += kPairTile) {
+        const int c1 = min(c0 + kPairTile, total);
+        for (int u0 = c0; u0 < c1; u0 += kWave) {
+            const int u = u0 + l;
+            if (u < c1) {
+                int ja, ka;
+                tri_decode(u, n_a, ja, ka);
+                const float4 A = S.au[ja], B = S.au[ka];
+                float c = A.x * B.x + A.y * B.y + A.z * B.z;
+                c = fminf(1.f, fmaxf(-1.f, c));
+                const float uu = P.cs * c;
+                const float sq = hw_sqrt(1.f - uu * uu);
+                const float rj = A.w, rk = B.w;
+                const float rbar = 0.5f * (rj + rk);
+                const float fj = S.afc[ja], fk = S.afc[ka];
+                const float dfj = S.adfc[ja], dfk = S.adfc[ka];
+                const int pp = species_pair(S.azs[ja] & 0xff, S.azs[ka] & 0xff, ns);
+                const float* gp = &S.g[P.radial_dim + 32 * pp];
+                float F2[kNa], dF2[kNa];
 #pragma unroll
                 for (int a = 0; a < kNa; ++a) {
-                    const float gaz = gp[8 * a + z];
-                    Q += gaz * F2[a];
-                    Rz[a] += gaz * F1;
+                    const float d = rbar - P.shf_a[a];
+                    F2[a] = __expf(-P.eta_a * d * d);
+                    dF2[a] = -2.f * P.eta_a * d * F2[a];
                 }
-                sum_c += Q * dF1 * dwdu;
-                Ssum += Q * F1;
-            }
-            float sum_r = 0.f;
+                float Rz[kNa] = {0.f, 0.f, 0.f, 0.f};
+                float sum_c = 0.f, Ssum = 0.f;
+                const float inv_sq = hw_rcp(sq);
 #pragma unroll
-            for (int a = 0; a < kNa; ++a) sum_r += Rz[a] * dF2[a];
-            const float ff = 2.f * fj * fk;
-            const float dEdc = ff * sum_c * P.cs;
-            const float dEdrbar = ff * sum_r;
-            const float sj = 0.5f * dEdrbar + 2.f * fk * Ssum * dfj;
-            const float sk = 0.5f * dEdrbar + 2.f * fj * Ssum * dfk;
-            const float ij = rj > 0.f ? hw_rcp(rj) : 0.f;
-            const float ik = rk > 0.f ? hw_rcp(rk) : 0.f;
-            S.pb[l][0] = dEdc * (B.x - c * A.x) * ij + sj * A.x;
-            S.pb[l][1] = dEdc * (B.y - c * A.y) * ij + sj * A.y;
-            S.pb[l][2] = dEdc * (B.z - c * A.z) * ij + sj * A.z;
-            S.pb[l][3] = dEdc * (A.x - c * B.x) * ik + sk * B.x;
-            S.pb[l][4] = dEdc * (A.y - c * B.y) * ik + sk * B.y;
-            S.pb[l][5] = dEdc * (A.z - c * B.z) * ik + sk * B.z;
+                for (int z = 0; z < kNz; ++z) {
+                    // base^zeta and its derivative; base = 0 gives log2 = -inf and both 0
+                    const float base = fmaxf(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), 0.f);
+                    const float lg = hw_log2(base);
+                    const float F1 = hw_exp2(P.zeta * lg);
+                    const float dF1 = 0.5f * P.zeta * hw_exp2((P.zeta - 1.f) * lg);
+                    const float dwdu = P.cos_z[z] - uu * P.sin_z[z] * inv_sq;
+                    float Q = 0.f;
+#pragma unroll
+                    for (int a = 0; a < kNa; ++a) {
+                        const float gaz = gp[8 * a + z];
+                        Q += gaz * F2[a];
+                        Rz[a] += gaz * F1;
+                    }
+                    sum_c += Q * dF1 * dwdu;
+                    Ssum += Q * F1;
+                }
+                float sum_r = 0.f;
+#pragma unroll
+                for (int a = 0; a < kNa; ++a) sum_r += Rz[a] * dF2[a];
+                const float ff = 2.f * fj * fk;
+                const float dEdc = ff * sum_c * P.cs;
+                const float dEdrbar = ff * sum_r;
+                const float sj = 0.5f * dEdrbar + 2.f * fk * Ssum * dfj;
+                const float sk = 0.5f * dEdrbar + 2.f * fj * Ssum * dfk;
+                const float ij = rj > 0.f ? hw_rcp(rj) : 0.f;
+                const float ik = rk > 0.f ? hw_rcp(rk) : 0.f;
+                S.pb[u - c0][0] = dEdc * (B.x - c * A.x) * ij + sj * A.x;
+                S.pb[u - c0][1] = dEdc * (B.y - c * A.y) * ij + sj * A.y;
+                S.pb[u - c0][2] = dEdc * (B.z - c * A.z) * ij + sj * A.z;
+                S.pb[u - c0][3] = dEdc * (A.x - c * B.x) * ik + sk * B.x;
+                S.pb[u - c0][4] = dEdc * (A.y - c * B.y) * ik + sk * B.y;
+                S.pb[u - c0][5] = dEdc * (A.z - c * B.z) * ik + sk * B.z;
+            }
         }
         wave_sync();
-        // gather per angular neighbour, fixed order: pairs (m, k > m) then pairs (j < m, m)
-        const int u1 = min(u0 + kWave, total);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
+            if (q * kWave >= n_a) break;   // wave-uniform
             const int m = l + q * kWave;
-            if (m < n_a) {
-                const int t0 = m * (2 * n_a - m - 1) / 2, t1 = t0 + (n_a - m - 1);
-                for (int t = max(t0, u0); t < min(t1, u1); ++t) {
-                    ax_[q] += S.pb[t - u0][0];
-                    ay_[q] += S.pb[t - u0][1];
-                    az_[q] += S.pb[t - u0][2];
+            const int Tm = m * (2 * n_a - m - 1) / 2;   // first pair (m, m + 1)
+            int Tj = 0;                                 // first pair (j, j + 1)
+            for (int j = 0; j + 1 < n_a; ++j) {
+                const bool before = j < m;              // pair (j, m), else pair (m, j + 1)
+                const int t = before ? Tj + (m - j - 1) : Tm + (j - m);
+                if (m < n_a && t >= c0 && t < c1) {
+                    const float* e = &S.pb[t - c0][before ? 3 : 0];
+                    ax_[q] += e[0];
+                    ay_[q] += e[1];
+                    az_[q] += e[2];
                 }
-                while (jptr[q] < m) {
-                    const int jj = jptr[q];
-                    const int t = jj * (2 * n_a - jj - 1) / 2 + (m - jj - 1);
-                    if (t >= u1) break;
-                    ax_[q] += S.pb[t - u0][3];
-                    ay_[q] += S.pb[t - u0][4];
-                    az_[q] += S.pb[t - u0][5];
-                    ++jptr[q];
-                }
+                Tj += n_a - j - 1;
             }
         }
         wave_sync();
     }
+    // the tile is dead: its space now holds the per-neighbour sums
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int m = l + q * kWave;

@@ -249,7 +249,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
         }
         prof_end(m, NNP_STAGE_MLP, s);
     }
-    if (!(md && md->fuse_energy)) {
+    if (!(md && md->fuse_energy) && !(opts && opts->skip_energy)) {
         prof_begin(m, NNP_STAGE_ENERGY, s);
         if (e == hipSuccess)
             e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at, e_mol, e_atom, flags,

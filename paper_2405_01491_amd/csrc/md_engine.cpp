@@ -82,10 +82,12 @@ nnp_status status_of_flags(unsigned fl) {
 // One step.  Small systems (md_front_fits): a fused front kernel (first half
 // step, displacement, rebuild decision, wrap and cell binning), the gated
 // row kernel, AEV (with the reverse index on rebuild steps), networks, AEV
-// adjoint, and a fused back kernel (structure energy, force gather, last half
-// kick): six launches.  Larger systems use the general multi-kernel path for
-// the front, the cell binning and the energy sum.
-nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
+// adjoint, and a fused back kernel (force gather, last half kick and, when
+// wanted, the structure energy): six launches.  Larger systems use the
+// general multi-kernel path for the front, the cell binning and the energy
+// sum.  The potential energy is summed only on logged steps and on the last
+// step of a run (the one nnp_md_get reports).
+nnp_status enqueue_step(nnp_md* md, uint64_t step, bool last, hipStream_t s) {
     nnp_model* m = md->model;
     const bool langevin = md->p.integrator == NNP_MD_LANGEVIN;
     const float* bptr = md->bx.periodic ? md->box : nullptr;
@@ -110,14 +112,16 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     md->rows.rev = md->nl.rev;
     const bool log = md->p.log_every > 0 && ((step + 1) % (uint64_t)md->p.log_every) == 0 &&
                      md->log_rows < md->log_cap;
+    const bool energy = log || last;
     MdBack back{};
     back.vel = md->vel;
     back.inv_mass = md->inv_mass;
     back.dt = md->p.dt;
     back.ke_part = log ? md->ke_part : nullptr;
-    back.fuse_energy = md->small;
+    back.fuse_energy = md->small && energy;
     EfOpts opts;
     opts.skip_group = md->grouped;
+    opts.skip_energy = !energy;
     opts.md = &back;
     opts.rows = &md->rows;
     opts.rev_out = md->nl.rev;
@@ -260,7 +264,7 @@ nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream) {
     if (n_steps == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
     for (int k = 0; k < n_steps; ++k) {
-        nnp_status st = enqueue_step(md, md->step + (uint64_t)k, s);
+        nnp_status st = enqueue_step(md, md->step + (uint64_t)k, k + 1 == n_steps, s);
         if (st != NNP_OK) return st;
     }
     unsigned fl = 0;

@@ -58,7 +58,7 @@ struct Cfg<true> {                  // BF16
     typedef uint16_t act_t;
     static constexpr int kStep = 32;
     static constexpr int kLd = N1 + 8;
-    static constexpr int kChunk = 64;
+    static constexpr int kChunk = 256;
     static constexpr int kChunkLd = kChunk + 8;
 };
 

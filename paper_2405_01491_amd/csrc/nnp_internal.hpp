@@ -170,6 +170,7 @@ struct MdEnergyIn;
 // force gather by the engine's fused last kernel.
 struct EfOpts {
     bool skip_group = false;
+    bool skip_energy = false;   // no structure energies (e_mol untouched)
     const MdBack* md = nullptr;
     // fixed-stride rows in place of nl's CSR arrays (nl->capacity must cover
     // n * NNP_MAX_ROW); their reverse index is written to rev_out by the AEV
