@@ -330,8 +330,8 @@ struct BwdLds {
 template <bool kVir>
 __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
-    const RowsView rows, const int32_t* __restrict__ g_row, const float* __restrict__ g, float* __restrict__ Gx,
-    float* __restrict__ Gy, float* __restrict__ Gz, float* __restrict__ Wat, unsigned* flags) {
+    const RowsView rows, const int32_t* __restrict__ g_row, const float* __restrict__ g, float4* __restrict__ G,
+    float* __restrict__ Wat, unsigned* flags) {
     __shared__ BwdLds lds[kWaves];
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
                     group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, flags) && row >= 0;
     if (!ok) {
         const int b = rows.begin(i), e = rows.end(i);
-        for (int p = b + l; p < e; p += kWave) Gx[p] = Gy[p] = Gz[p] = 0.f;
+        for (int p = b + l; p < e; p += kWave) G[p] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (kVir && l < 9) Wat[9 * (size_t)i + l] = 0.f;
         return;
     }
@@ -420,7 +420,17 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
                 const float fj = S.afc[ja], fk = S.afc[ka];
                 const float dfj = S.adfc[ja], dfk = S.adfc[ka];
                 const int pp = species_pair(S.azs[ja] & 0xff, S.azs[ka] & 0xff, ns);
-                const float* gp = &S.g[P.radial_dim + 32 * pp];
+                // this bin's 32 coefficients, [a][z] (radial_dim is a multiple of 16)
+            const float4* gp4 = (const float4*)&S.g[P.radial_dim + 32 * pp];
+            float gp[kNa * kNz];
+#pragma unroll
+            for (int v = 0; v < kNa * kNz / 4; ++v) {
+                const float4 q4 = gp4[v];
+                gp[4 * v] = q4.x;
+                gp[4 * v + 1] = q4.y;
+                gp[4 * v + 2] = q4.z;
+                gp[4 * v + 3] = q4.w;
+            }
                 float F2[kNa], dF2[kNa];
 #pragma unroll
                 for (int a = 0; a < kNa; ++a) {
@@ -516,9 +526,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
                 z += S.ga[am][2];
             }
             const int p = R.b + slot;
-            Gx[p] = x;
-            Gy[p] = y;
-            Gz[p] = z;
+            G[p] = make_float4(x, y, z, 0.f);
             if (kVir) {
                 const float v[3] = {R.vx[q], R.vy[q], R.vz[q]}, G[3] = {x, y, z};
 #pragma unroll
@@ -559,15 +567,15 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
 }
 
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const RowsView& rows, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
+                          const RowsView& rows, const int32_t* g_row, const float* g, float4* G,
                           float* atom_virial, unsigned* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
     if (atom_virial)
-        k_aev_bwd<true><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, Gx, Gy, Gz,
+        k_aev_bwd<true><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, G,
                                                         atom_virial, flags);
     else
-        k_aev_bwd<false><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, Gx, Gy, Gz, nullptr,
+        k_aev_bwd<false><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, G, nullptr,
                                                          flags);
     return hipGetLastError();
 }

@@ -107,9 +107,7 @@ struct EfWs {
     float* h[kMaxLayers];
     float* E_row;
     float* E_at;        // network energies in atom order
-    float* Gx;
-    float* Gy;
-    float* Gz;
+    float4* G;      // edge gradients dE/dv_ij, one (x, y, z, 0) per list slot
     float* Wat;         // per-centre virials [n][9] when the caller passes none
     double* vpart;      // chunk partials of the structure virial
     void* d1;           // ensembles: per-network dE/dh1 [n_nets][rows_max][256]
@@ -140,9 +138,7 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.E_row = (float*)take(sizeof(float) * rows_max);
     W.E_at = (float*)take(sizeof(float) * nn);
     const int64_t c = cap > 0 ? cap : 1;
-    W.Gx = (float*)take(sizeof(float) * c);
-    W.Gy = (float*)take(sizeof(float) * c);
-    W.Gz = (float*)take(sizeof(float) * c);
+    W.G = (float4*)take(sizeof(float4) * c);
     W.Wat = (float*)take(sizeof(float) * 9 * (size_t)nn);
     W.vpart = (double*)take(sizeof(double) * virial_partial_doubles(nn));
     if (mlp_split(m, nn)) {
@@ -263,7 +259,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     if (e == hipSuccess && forces && n > 0) {
         prof_begin(m, NNP_STAGE_AEV_ADJ, s);
         float* wat = virial || atom_virial ? (atom_virial ? atom_virial : W.Wat) : nullptr;
-        e = launch_aev_bwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.g, W.Gx, W.Gy, W.Gz, wat, flags, s);
+        e = launch_aev_bwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.g, W.G, wat, flags, s);
         prof_end(m, NNP_STAGE_AEV_ADJ, s);
         prof_begin(m, NNP_STAGE_FORCES, s);
         if (e == hipSuccess) {
@@ -275,9 +271,9 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
                 ein.E_at = W.E_at;
                 for (int k = 0; k < kMaxSpecies; ++k) ein.se[k] = m->self_energy[k];
                 ein.e_pot = e_mol;
-                e = md_launch_back(n, rows, W.Gx, W.Gy, W.Gz, forces, *md, &ein, s);
+                e = md_launch_back(n, rows, W.G, forces, *md, &ein, s);
             } else {
-                e = launch_force_gather(n, rows, W.Gx, W.Gy, W.Gz, forces, s);
+                e = launch_force_gather(n, rows, W.G, forces, s);
             }
         }
         prof_end(m, NNP_STAGE_FORCES, s);

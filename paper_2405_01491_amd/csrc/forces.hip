@@ -14,8 +14,7 @@ namespace {
 constexpr int kLanesPerAtom = 16;
 
 __global__ __launch_bounds__(256) void k_force_gather(int n, const RowsView rows,
-                                                     const int32_t* __restrict__ rev, const float* __restrict__ Gx,
-                                                     const float* __restrict__ Gy, const float* __restrict__ Gz,
+                                                     const int32_t* __restrict__ rev, const float4* __restrict__ G,
                                                      float* __restrict__ F) {
     const int a = (blockIdx.x * blockDim.x + threadIdx.x) / kLanesPerAtom;
     const int sub = threadIdx.x % kLanesPerAtom;
@@ -24,9 +23,10 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, const RowsView rows
         const int b = rows.begin(a), e = rows.end(a);
         for (int p = b + sub; p < e; p += kLanesPerAtom) {
             const int q = rev[p];
-            fx += Gx[p] - Gx[q];
-            fy += Gy[p] - Gy[q];
-            fz += Gz[p] - Gz[q];
+            const float4 gp = G[p], gq = G[q];
+            fx += gp.x - gq.x;
+            fy += gp.y - gq.y;
+            fz += gp.z - gq.z;
         }
     }
 #pragma unroll
@@ -153,10 +153,10 @@ hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_force_gather(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz, float* F,
+hipError_t launch_force_gather(int n, const RowsView& rows, const float4* G, float* F,
                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_force_gather<<<ceil_div((long)n * kLanesPerAtom, 256), 256, 0, s>>>(n, rows, rows.rev, Gx, Gy, Gz, F);
+    k_force_gather<<<ceil_div((long)n * kLanesPerAtom, 256), 256, 0, s>>>(n, rows, rows.rev, G, F);
     return hipGetLastError();
 }
 

@@ -27,24 +27,47 @@
 namespace nnp {
 namespace {
 
+constexpr int kFirstThreads = 256;
+
+// First part of the step; the largest squared displacement of each block
+// goes to d2_part[block] (one write per block, no contended atomics).
 template <bool kLangevin>
-__global__ __launch_bounds__(256) void k_md_first(int n, float* __restrict__ pos, float* __restrict__ vel,
-                                                 const float* __restrict__ F, const float* __restrict__ inv_mass,
-                                                 const MdStepConst c, uint64_t step, const float* __restrict__ ref,
-                                                 MdState* st) {
+__global__ __launch_bounds__(kFirstThreads) void k_md_first(int n, float* __restrict__ pos, float* __restrict__ vel,
+                                                           const float* __restrict__ F,
+                                                           const float* __restrict__ inv_mass, const MdStepConst c,
+                                                           uint64_t step, const float* __restrict__ ref,
+                                                           float* __restrict__ d2_part) {
+    __shared__ float s_max[kFirstThreads / kWave];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     float d2 = 0.f;
     if (a < n) d2 = md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref);
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
-    if (lane_id() == 0 && d2 > 0.f) atomicMax((unsigned*)&st->max_d2, __float_as_uint(d2));
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = d2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mx = s_max[0];
+        for (int q = 1; q < kFirstThreads / kWave; ++q) mx = fmaxf(mx, s_max[q]);
+        d2_part[blockIdx.x] = mx;
+    }
 }
 
-// Rebuild decision for this step (large systems; small ones decide in the
-// fused front kernel of the neighbour builder).
-__global__ void k_md_decide(MdState* st, int rebuild_every, float trigger2) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    md_decide(st, st->max_d2, rebuild_every, trigger2);
+// Rebuild decision for this step from the blocks' displacements (large
+// systems; small ones decide in the fused front kernel of the neighbour
+// builder).  One block.
+__global__ __launch_bounds__(256) void k_md_decide(MdState* st, const float* __restrict__ d2_part, int n_parts,
+                                                   int rebuild_every, float trigger2) {
+    __shared__ float s_max[256 / kWave];
+    float mx = 0.f;
+    for (int q = threadIdx.x; q < n_parts; q += 256) mx = fmaxf(mx, d2_part[q]);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, shfl_xor(mx, m));
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 256 / kWave; ++q) mx = fmaxf(mx, s_max[q]);
+        md_decide(st, mx, rebuild_every, trigger2);
+    }
 }
 
 // On rebuild steps: wrap into the box (periodic) and take the new reference.
@@ -74,8 +97,7 @@ constexpr int kBackThreads = 256, kBackLanes = 16, kBackAtoms = kBackThreads / k
 
 template <bool kEnergy>
 __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const RowsView rows,
-                                                         const int32_t* __restrict__ rev, const float* __restrict__ Gx,
-                                                         const float* __restrict__ Gy, const float* __restrict__ Gz,
+                                                         const int32_t* __restrict__ rev, const float4* __restrict__ G,
                                                          float* __restrict__ F, float* __restrict__ vel,
                                                          const float* __restrict__ inv_mass, float dt, double* ke_part,
                                                          const MdEnergyIn E) {
@@ -100,9 +122,10 @@ __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const RowsView 
         const int b = rows.begin(a), e = rows.end(a);
         for (int p = b + sub; p < e; p += kBackLanes) {
             const int q = rev[p];
-            fx += Gx[p] - Gx[q];
-            fy += Gy[p] - Gy[q];
-            fz += Gz[p] - Gz[q];
+            const float4 gp = G[p], gq = G[q];
+            fx += gp.x - gq.x;
+            fy += gp.y - gq.y;
+            fz += gp.z - gq.z;
         }
     }
 #pragma unroll
@@ -159,16 +182,19 @@ __global__ void k_md_inv_mass(int n, const float* masses, float* inv_mass, unsig
 
 }  // namespace
 
+int md_first_parts(int n) { return ceil_div(n > 0 ? n : 1, kFirstThreads); }
+
 hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
-                           uint64_t step, const float* ref, MdState* st, bool langevin, hipStream_t s) {
-    const int nb = ceil_div(n > 0 ? n : 1, 256);
-    if (langevin) k_md_first<true><<<nb, 256, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st);
-    else k_md_first<false><<<nb, 256, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st);
+                           uint64_t step, const float* ref, float* d2_part, bool langevin, hipStream_t s) {
+    const int nb = md_first_parts(n);
+    if (langevin) k_md_first<true><<<nb, kFirstThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, d2_part);
+    else k_md_first<false><<<nb, kFirstThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, d2_part);
     return hipGetLastError();
 }
 
-hipError_t md_launch_decide(MdState* st, int rebuild_every, float trigger2, hipStream_t s) {
-    k_md_decide<<<1, 64, 0, s>>>(st, rebuild_every, trigger2);
+hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trigger2,
+                            hipStream_t s) {
+    k_md_decide<<<1, 256, 0, s>>>(st, d2_part, n_parts, rebuild_every, trigger2);
     return hipGetLastError();
 }
 
@@ -180,15 +206,15 @@ hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx,
 
 int md_ke_parts(int n) { return ceil_div(n > 0 ? n : 1, kBackAtoms); }
 
-hipError_t md_launch_back(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz, float* F,
+hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s) {
     MdEnergyIn E{};
     if (e) E = *e;
     if (b.fuse_energy && e)
-        k_md_back<true><<<md_ke_parts(n) + 1, kBackThreads, 0, s>>>(n, rows, rows.rev, Gx, Gy, Gz, F, b.vel,
+        k_md_back<true><<<md_ke_parts(n) + 1, kBackThreads, 0, s>>>(n, rows, rows.rev, G, F, b.vel,
                                                                     b.inv_mass, b.dt, b.ke_part, E);
     else
-        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, rows, rows.rev, Gx, Gy, Gz, F, b.vel,
+        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, rows, rows.rev, G, F, b.vel,
                                                                  b.inv_mass, b.dt, b.ke_part, E);
     return hipGetLastError();
 }

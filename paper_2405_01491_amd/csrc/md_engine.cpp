@@ -42,6 +42,7 @@ struct nnp_md {
     MdState* st = nullptr;
     unsigned* flags = nullptr;
     double* ke_part = nullptr;
+    float* d2_part = nullptr;   // per-block displacements (general path)
     // energy log [log_cap][2]
     double* log = nullptr;
     int log_cap = 0;
@@ -99,8 +100,10 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, bool last, hipStream_t s) {
                                         md->ws_nb_bytes, md->flags, s);
         if (st != NNP_OK) return st;
     } else {
-        e = md_launch_first(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->st, langevin, s);
-        if (e == hipSuccess) e = md_launch_decide(md->st, md->p.rebuild_every, md->trigger2, s);
+        e = md_launch_first(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->d2_part,
+                            langevin, s);
+        if (e == hipSuccess)
+            e = md_launch_decide(md->st, md->d2_part, md_first_parts(md->n), md->p.rebuild_every, md->trigger2, s);
         if (e == hipSuccess) e = md_launch_wrap_ref(md->n, md->pos, md->ref, md->bx, md->st, s);
     }
     prof_end(m, NNP_STAGE_INTEGRATE, s);
@@ -201,6 +204,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
               dmalloc(&md->inv_mass, (size_t)n) == hipSuccess && dmalloc(&md->species, (size_t)n) == hipSuccess &&
               dmalloc(&md->e_pot, 1) == hipSuccess && dmalloc(&md->st, 1) == hipSuccess &&
               dmalloc(&md->flags, 1) == hipSuccess && dmalloc(&md->ke_part, (size_t)md_ke_parts(n)) == hipSuccess &&
+              dmalloc(&md->d2_part, (size_t)md_first_parts(n)) == hipSuccess &&
               dmalloc(&md->log, 2 * (size_t)(md->log_cap > 0 ? md->log_cap : 1)) == hipSuccess &&
               hipHostMalloc(&md->host, 64, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -320,7 +324,7 @@ nnp_status nnp_md_info(nnp_md* md, nnp_md_stats* out, void* stream) {
 void nnp_md_destroy(nnp_md* md) {
     if (!md) return;
     void* bufs[] = {md->pos, md->vel, md->F, md->ref, md->inv_mass, md->species, md->e_pot, md->st, md->flags,
-                    md->ke_part, md->log, md->nl.rev, md->ws_ef, md->ws_nb};
+                    md->ke_part, md->d2_part, md->log, md->nl.rev, md->ws_ef, md->ws_nb};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (md->host) (void)hipHostFree(md->host);

@@ -62,7 +62,9 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t step, int a, floa
 }
 
 // First part of a step for atom a: velocity Verlet B(dt/2) A(dt), or BAOAB
-// B(dt/2) A(dt/2) O A(dt/2).  Returns the squared displacement from ref.
+// B(dt/2) A(dt/2) O A(dt/2).  Returns the squared displacement from ref
+// (+inf if it is not finite, so that the list is rebuilt and the rebuild
+// flags the coordinates).
 template <bool kLangevin>
 __device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, float* __restrict__ vel,
                                                const float* __restrict__ F, const float* __restrict__ inv_mass,
@@ -99,7 +101,7 @@ __device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, f
         const float d = x[k] - ref[3 * a + k];
         d2 += d * d;
     }
-    return d2;
+    return d2 <= INFINITY ? d2 : INFINITY;
 }
 
 // Rebuild decision (one thread): every rebuild_every steps, or earlier once an
@@ -139,12 +141,15 @@ struct MdBack {
     bool fuse_energy;         // sum the structure energy in the same kernel
 };
 
+// d2_part: [md_first_parts(n)] per-block largest squared displacements
+int md_first_parts(int n);
 hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
-                           uint64_t step, const float* ref, MdState* st, bool langevin, hipStream_t s);
-hipError_t md_launch_decide(MdState* st, int rebuild_every, float trigger2, hipStream_t s);
+                           uint64_t step, const float* ref, float* d2_part, bool langevin, hipStream_t s);
+hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trigger2,
+                            hipStream_t s);
 hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx, const MdState* st, hipStream_t s);
 int md_ke_parts(int n);
-hipError_t md_launch_back(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz, float* F,
+hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s);
 // neighbors.hip: the fused front of a step for small systems
 bool md_front_fits(int n, const float* box_host, float r_list);

@@ -232,7 +232,7 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
                           const RowsView& rows, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
                           hipStream_t s, int32_t* rev_out = nullptr, const int32_t* gate = nullptr);
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const RowsView& rows, const int32_t* g_row, const float* g, float* Gx, float* Gy, float* Gz,
+                          const RowsView& rows, const int32_t* g_row, const float* g, float4* G,
                           float* atom_virial, unsigned* flags, hipStream_t s);
 
 hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, unsigned* flags,
@@ -265,7 +265,7 @@ hipError_t launch_gather_e(const int32_t* prow, int n, const int32_t* species, c
 size_t virial_partial_doubles(int n);
 hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t* mend, const float* Wat, double* part,
                          double* virial, hipStream_t s);
-hipError_t launch_force_gather(int n, const RowsView& rows, const float* Gx, const float* Gy, const float* Gz,
+hipError_t launch_force_gather(int n, const RowsView& rows, const float4* G,
                                float* F, hipStream_t s);
 hipError_t launch_kick_drift(int n, float* pos, float* vel, const float* F, const float* inv_mass, float dt,
                              const float* ref, float* max_d2, hipStream_t s);
