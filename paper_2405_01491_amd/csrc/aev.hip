@@ -137,12 +137,25 @@ __device__ __forceinline__ bool load_row(Row& R, const AevConst& P, int i, const
 }
 
 // Stable positions of the slots in species-grouped lists (radial and angular).
-// seg_r / seg_a receive the species offsets (ns + 1 entries).  Returns false if
-// more than kMaxA neighbours fall inside the angular cutoff.
+// seg_r / seg_a receive the species offsets (ns + 1 entries); *present gets
+// the wave-uniform masks of the species found inside the radial cutoff (bits
+// 0-7) and inside the angular cutoff (bits 8-15).  Absent species cost no
+// ballots.  Returns false if more than kMaxA neighbours fall inside the
+// angular cutoff.
 __device__ __forceinline__ bool group_species(const Row& R, int ns, int* pos_r, int* pos_a, int* seg_r,
-                                              int* seg_a, unsigned* flags) {
+                                              int* seg_a, unsigned* present, unsigned* flags) {
     const int l = lane_id();
     const int nq = (R.len + kWave - 1) / kWave;
+    int bits = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        if (q < nq && R.in_r[q]) bits |= 1 << R.z[q];
+        if (q < nq && R.in_a[q]) bits |= 0x100 << R.z[q];
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) bits |= shfl_xor(bits, m);
+    const unsigned mask = __builtin_amdgcn_readfirstlane((unsigned)bits);
+    *present = mask;
     int off_r = 0, off_a = 0;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) pos_r[q] = pos_a[q] = -1;
@@ -151,6 +164,7 @@ __device__ __forceinline__ bool group_species(const Row& R, int ns, int* pos_r, 
             seg_r[s] = off_r;
             seg_a[s] = off_a;
         }
+        if (!((mask >> s) & 1u)) continue;   // wave-uniform
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             if (q < nq) {
@@ -220,8 +234,9 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     const int ns = P.ns;
     Row R;
     int pr_[kQ], pa_[kQ];
+    unsigned present = 0;
     if (!load_row(R, P, i, pos, species, bx, rows, flags) ||
-        !group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, flags)) {
+        !group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, &present, flags)) {
         for (int c = l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
         return;
     }
@@ -244,6 +259,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
         const int k = l & 15, q = l >> 4;
         const float rk = P.shf_r[k];
         for (int s = 0; s < ns; ++s) {
+            if (!((present >> s) & 1u)) {   // wave-uniform: no neighbour of this species
+                if (q == 0) store_out(orow + 16 * s + k, 0.f);
+                continue;
+            }
             const int sb = S.seg_r[s], se = S.seg_r[s + 1];
             float acc = 0.f;
             for (int m = sb + q; m < se; m += 4) {
@@ -262,6 +281,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     for (int s = 0; s < ns; ++s) {
         const int bs = S.seg_a[s], cs_ = S.seg_a[s + 1] - bs;
         for (int t = s; t < ns; ++t, ++p) {
+            if (!((present >> (8 + s)) & (present >> (8 + t)) & 1u)) {   // wave-uniform: an empty bin
+                if (half == 0) store_out(orow + P.radial_dim + 32 * p + az, 0.f);
+                continue;
+            }
             const int bt = S.seg_a[t], ct = S.seg_a[t + 1] - bt;
             const int np_ = (s == t) ? cs_ * (cs_ - 1) / 2 : cs_ * ct;
             float acc = 0.f;
@@ -341,9 +364,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     const int ns = P.ns;
     Row R;
     int pr_[kQ], pa_[kQ];
+    unsigned present = 0;
     const int row = g_row ? g_row[i] : i;
     const bool ok = load_row(R, P, i, pos, species, bx, rows, flags) &&
-                    group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, flags) && row >= 0;
+                    group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, &present, flags) && row >= 0;
     if (!ok) {
         const int b = rows.begin(i), e = rows.end(i);
         for (int p = b + l; p < e; p += kWave) G[p] = make_float4(0.f, 0.f, 0.f, 0.f);
