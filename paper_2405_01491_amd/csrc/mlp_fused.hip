@@ -50,8 +50,8 @@ struct Cfg<false> {                 // FP32
     typedef float act_t;
     static constexpr int kStep = 4;     // k per MFMA
     static constexpr int kLd = N1 + 4;  // act row stride (elements)
-    static constexpr int kChunk = 32;   // layer-1 K chunk
-    static constexpr int kChunkLd = kChunk + 4;
+    static constexpr int kChunk = 64;   // layer-1 K chunk (32 for tiles above 16 rows)
+    static constexpr int kPad = 4;      // chunk row padding
 };
 template <>
 struct Cfg<true> {                  // BF16
@@ -59,7 +59,7 @@ struct Cfg<true> {                  // BF16
     static constexpr int kStep = 32;
     static constexpr int kLd = N1 + 8;
     static constexpr int kChunk = 256;
-    static constexpr int kChunkLd = kChunk + 8;
+    static constexpr int kPad = 8;
 };
 
 __device__ __forceinline__ float celu(float v, float alpha) { return v > 0.f ? v : alpha * (__expf(v / alpha) - 1.f); }
@@ -82,13 +82,72 @@ __device__ __forceinline__ f32x4 mfma_step<true>(const uint16_t* act, int ld, in
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, *(const bf16x8*)bfrag, c, 0, 0, 0);
 }
 
+// B fragments of one k-step (FP32: 16 k, four MFMA k-steps; BF16: 32 k)
+template <bool BF>
+struct Frag;
+template <>
+struct Frag<false> {
+    typedef f32x4 reg_t;
+    typedef gfloat4 mem_t;
+    static constexpr int kK = 16;
+};
+template <>
+struct Frag<true> {
+    typedef u16x8 reg_t;
+    typedef gu16x8 mem_t;
+    static constexpr int kK = 32;
+};
+
+// The MFMAs of k-step kq: acc[mb][nb] += A[16 mb.., kq] B[kq, nb] with A from
+// LDS (row stride ld) and the B fragments given.
+template <bool BF, int MB, int NCB>
+__device__ __forceinline__ void mfma_kstep(const typename Cfg<BF>::act_t* act, int ld, int kq,
+                                           const typename Frag<BF>::reg_t (&b)[NCB], f32x4 (&acc)[MB][NCB]) {
+    const int l = lane_id();
+    if (!BF) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 16 * kq + 4 * j + (l >> 4);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const float a = ((const float*)act)[(16 * mb + (l & 15)) * ld + k];
+#pragma unroll
+                for (int nb = 0; nb < NCB; ++nb) {
+                    const f32x4 bq = __builtin_bit_cast(f32x4, b[nb]);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq[j], acc[mb][nb], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+        const int k = 32 * kq + 8 * (l >> 4);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const bf16x8 a = *(const bf16x8*)((const uint16_t*)act + (16 * mb + (l & 15)) * ld + k);
+#pragma unroll
+            for (int nb = 0; nb < NCB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b[nb]),
+                                                                      acc[mb][nb], 0, 0, 0);
+        }
+    }
+}
+
+// Ring of B-fragment registers for k-steps whose count is a multiple of the
+// ring size: k-step t lives in slot t % RS and is loaded two k-steps ahead.
+// The slots are indexed at compile time (the k loop is unrolled by RS), so
+// no register moves tie a k-step to the completion of later loads.
+template <int NK>
+constexpr int ring_slots() { return NK % 3 == 0 ? 3 : 4; }
+
 // C[TM x (NCB*16 columns of this wave)] = A[TM x K] (LDS, stride ld) * B (packed, global)
 // FP32 pack: [nb][K/16][64 lanes][4]   BF16 pack: [nb][K/32][64 lanes][8]
-// The next k-step's B fragments are loaded before the current step's MFMAs
-// (register double buffering), so their latency hides behind the MFMAs.
 template <bool BF, int MB, int NCB, int K, bool kZero = true>
 __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int ld, const void* Bpack, int nb0,
                                          f32x4 (&acc)[MB][NCB]) {
+    typedef typename Frag<BF>::reg_t reg_t;
+    typedef typename Frag<BF>::mem_t mem_t;
+    constexpr int NK = K / Frag<BF>::kK;
+    constexpr int RS = ring_slots<NK>();
+    static_assert(NK % RS == 0 && NK >= 2, "k-steps must fill whole rings");
     const int l = lane_id();
     if (kZero) {
 #pragma unroll
@@ -96,57 +155,23 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
 #pragma unroll
             for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
-    if (!BF) {
-        constexpr int NK = K / 16;
-        const gfloat4* B = (const gfloat4*)Bpack;
-        f32x4 b[NCB], bn[NCB];
+    const mem_t* B = (const mem_t*)Bpack;
+    reg_t rb[RS][NCB];
 #pragma unroll
-        for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * NK + 0) * 64 + l];
-        for (int kq = 0; kq < NK; ++kq) {
-            if (kq + 1 < NK) {
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int nb = 0; nb < NCB; ++nb) bn[nb] = B[((size_t)(nb0 + nb) * NK + kq + 1) * 64 + l];
-            }
-            __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
+        for (int nb = 0; nb < NCB; ++nb) rb[t][nb] = B[((size_t)(nb0 + nb) * NK + t) * 64 + l];
+    for (int k0 = 0; k0 < NK; k0 += RS) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 16 * kq + 4 * j + (l >> 4);
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    const float a = ((const float*)act)[(16 * mb + (l & 15)) * ld + k];
-#pragma unroll
-                    for (int nb = 0; nb < NCB; ++nb) {
-                        const float bv = j == 0 ? b[nb].x : j == 1 ? b[nb].y : j == 2 ? b[nb].z : b[nb].w;
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[mb][nb], 0, 0, 0);
-                    }
-                }
-            }
-#pragma unroll
-            for (int nb = 0; nb < NCB; ++nb) b[nb] = bn[nb];
-        }
-    } else {
-        constexpr int NK = K / 32;
-        const gu16x8* B = (const gu16x8*)Bpack;
-        u16x8 b[NCB], bn[NCB];
-#pragma unroll
-        for (int nb = 0; nb < NCB; ++nb) b[nb] = B[((size_t)(nb0 + nb) * NK + 0) * 64 + l];
-        for (int ks = 0; ks < NK; ++ks) {
-            if (ks + 1 < NK) {
-#pragma unroll
-                for (int nb = 0; nb < NCB; ++nb) bn[nb] = B[((size_t)(nb0 + nb) * NK + ks + 1) * 64 + l];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            const int k = 32 * ks + 8 * (l >> 4);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const bf16x8 a = *(const bf16x8*)((const uint16_t*)act + (16 * mb + (l & 15)) * ld + k);
+        for (int u = 0; u < RS; ++u) {
+            const int kq = k0 + u;
+            if (kq + 2 < NK) {
 #pragma unroll
                 for (int nb = 0; nb < NCB; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b[nb]),
-                                                                          acc[mb][nb], 0, 0, 0);
+                    rb[(u + 2) % RS][nb] = B[((size_t)(nb0 + nb) * NK + kq + 2) * 64 + l];
             }
-#pragma unroll
-            for (int nb = 0; nb < NCB; ++nb) b[nb] = bn[nb];
+            __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
+            mfma_kstep<BF, MB, NCB>(act, ld, kq, rb[u], acc);
         }
     }
 }
@@ -201,7 +226,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     typedef typename Cfg<BF>::act_t act_t;
     constexpr int MB = TM / 16;
     constexpr int LD = Cfg<BF>::kLd;
-    constexpr int CH = Cfg<BF>::kChunk, CLD = Cfg<BF>::kChunkLd;
+    // layer-1 chunk: FP32 tiles above 16 rows take 32 k (the 64-k chunk makes them spill)
+    constexpr int CH = (!BF && TM > 16) ? 32 : Cfg<BF>::kChunk, CLD = CH + Cfg<BF>::kPad;
     constexpr int kActBytes = TM * LD * (int)sizeof(act_t);
     constexpr int kStageBytes = 2 * TM * CLD * (int)sizeof(act_t);
     constexpr int kLdsBytes = kActBytes > kStageBytes ? kActBytes : kStageBytes;
@@ -263,70 +289,46 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 }
             }
         };
-        const gfloat4* Bf = (const gfloat4*)pBf1;
-        const gu16x8* Bb = (const gu16x8*)pBf1;
+        typedef typename Frag<BF>::reg_t reg_t;
+        typedef typename Frag<BF>::mem_t mem_t;
+        const mem_t* B1 = (const mem_t*)pBf1;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) h1[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-        // B fragments of global k-step t (FP32: 16 k per step; BF16: 32), prefetched one step ahead
-        constexpr int KS = BF ? 32 : 16;
-        constexpr int NT = K0 / KS, TPC = CH / KS;
-        f32x4 bf[4], bfn[4];
-        u16x8 bb[4], bbn[4];
-        auto loadB = [&](int t, f32x4 (&df)[4], u16x8 (&db)[4]) {
+        // B fragments of global k-step t in ring slot t % 4, loaded two k-steps
+        // ahead; a ring turn spans CPR chunks, so every slot index is known at
+        // compile time
+        constexpr int KS = Frag<BF>::kK;
+        constexpr int NT = K0 / KS, TPC = CH / KS, NCH = K0 / CH;
+        constexpr int RS = 4, PD = 2, CPR = TPC >= RS ? 1 : RS / TPC;
+        static_assert((TPC >= RS ? TPC % RS : RS % TPC) == 0 && NCH % CPR == 0, "chunks hold whole ring turns");
+        reg_t rb[RS][4];
+        auto loadB = [&](int t, reg_t (&d)[4]) {
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                if (!BF) df[nb] = Bf[((size_t)(4 * w + nb) * NT + t) * 64 + l];
-                else db[nb] = Bb[((size_t)(4 * w + nb) * NT + t) * 64 + l];
-            }
+            for (int nb = 0; nb < 4; ++nb) d[nb] = B1[((size_t)(4 * w + nb) * NT + t) * 64 + l];
         };
-        loadB(0, bf, bb);
+#pragma unroll
+        for (int t0 = 0; t0 < PD; ++t0) loadB(t0, rb[t0]);
         gload(0);
         sstore(0);
         __syncthreads();
-        constexpr int NCH = K0 / CH;
-        for (int c = 0; c < NCH; ++c) {
-            if (c + 1 < NCH) gload(c + 1);
-            const act_t* cur = stage + (c & 1) * TM * CLD;
+        for (int c0 = 0; c0 < NCH; c0 += CPR) {
 #pragma unroll
-            for (int kq = 0; kq < TPC; ++kq) {
-                const int t = c * TPC + kq;
-                if (t + 1 < NT) loadB(t + 1, bfn, bbn);
-                __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
-                if (!BF) {
+            for (int cc = 0; cc < CPR; ++cc) {
+                const int c = c0 + cc;
+                if (c + 1 < NCH) gload(c + 1);
+                const act_t* cur = stage + (c & 1) * TM * CLD;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int k = 16 * kq + 4 * j + (l >> 4);
-#pragma unroll
-                        for (int mb = 0; mb < MB; ++mb) {
-                            const float a = ((const float*)cur)[(16 * mb + (l & 15)) * CLD + k];
-#pragma unroll
-                            for (int nb = 0; nb < 4; ++nb) {
-                                const float bv = j == 0 ? bf[nb].x : j == 1 ? bf[nb].y : j == 2 ? bf[nb].z : bf[nb].w;
-                                h1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, h1[mb][nb], 0, 0, 0);
-                            }
-                        }
-                    }
-                } else {
-                    const int k = 32 * kq + 8 * (l >> 4);
-#pragma unroll
-                    for (int mb = 0; mb < MB; ++mb) {
-                        const bf16x8 a = *(const bf16x8*)((const uint16_t*)cur + (16 * mb + (l & 15)) * CLD + k);
-#pragma unroll
-                        for (int nb = 0; nb < 4; ++nb)
-                            h1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                a, __builtin_bit_cast(bf16x8, bb[nb]), h1[mb][nb], 0, 0, 0);
-                    }
+                for (int kq = 0; kq < TPC; ++kq) {
+                    const int t = c * TPC + kq, slot = (cc * TPC + kq) % RS;
+                    if (t + PD < NT) loadB(t + PD, rb[(slot + PD) % RS]);
+                    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
+                    mfma_kstep<BF, MB, 4>(cur, CLD, kq, rb[slot], h1);
                 }
-#pragma unroll
-                for (int nb = 0; nb < 4; ++nb) {
-                    bf[nb] = bfn[nb];
-                    bb[nb] = bbn[nb];
-                }
+                if (c + 1 < NCH) sstore((c + 1) & 1);
+                __syncthreads();
             }
-            if (c + 1 < NCH) sstore((c + 1) & 1);
-            __syncthreads();
         }
     }
     // epilogue 1: h1 = CELU(z1 + b1) (kept), act = h1
