@@ -18,7 +18,8 @@
 //   forward:  radial sums with lanes as (shell k, quarter q) over each species
 //             segment; angular sums per species-pair bin, one neighbour pair
 //             per lane (8 angle factors, 4 radial factors) into a 64-pair LDS
-//             tile, reduced by lanes as (a, z) columns in two halves.
+//             tile, reduced by lanes as (shell, 4 angle sections, eighth of
+//             the pairs).
 //   adjoint:  radial gradient by the lane that holds the slot; angular pair
 //             gradients one pair per lane into an LDS tile of up to 192
 //             pairs, then summed per angular neighbour in a fixed order (one
@@ -196,7 +197,7 @@ struct FwdLds {
     float rfc[kMaxR];
     float4 au[kMaxA];          // angular list: unit vector, r
     float afc[kMaxA];
-    float f1[kWave][kNz];      // pair tile: 8 angle factors
+    alignas(16) float f1[kWave][kNz];   // pair tile: 8 angle factors
     float f2[kWave][kNa];      // pair tile: 4 radial factors times 2 fc fc
     int seg_r[kMaxSpecies + 1];
     int seg_a[kMaxSpecies + 1];
@@ -274,9 +275,12 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
             if (q == 0) store_out(orow + 16 * s + k, P.pr * acc);
         }
     }
-    // ---- angular: one species-pair bin at a time
+    // ---- angular: one species-pair bin at a time, one pair per lane into an
+    // LDS tile; then lane (ra, rz, rq) sums f1[z] f2[ra] for the four angle
+    // sections z = 4 rz .. 4 rz + 3 over the tile's pairs rq, rq + 8, ...,
+    // and a three-stage butterfly over rq completes each bin
     const int az = l & 31, half = l >> 5;
-    const int ca = az >> 3, cz = az & 7;
+    const int ra = l & 3, rz = (l >> 2) & 1, rq = l >> 3;
     int p = 0;
     for (int s = 0; s < ns; ++s) {
         const int bs = S.seg_a[s], cs_ = S.seg_a[s + 1] - bs;
@@ -287,7 +291,8 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
             }
             const int bt = S.seg_a[t], ct = S.seg_a[t + 1] - bt;
             const int np_ = (s == t) ? cs_ * (cs_ - 1) / 2 : cs_ * ct;
-            float acc = 0.f;
+            const float inv_ct = hw_rcp((float)ct);
+            float acc[4] = {0.f, 0.f, 0.f, 0.f};
             for (int u0 = 0; u0 < np_; u0 += kWave) {
                 const int u = u0 + l;
                 if (u < np_) {
@@ -297,8 +302,12 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
                         ja += bs;
                         ka += bs;
                     } else {
-                        ja = bs + u / ct;
-                        ka = bt + u % ct;
+                        // u = j' ct + k': the float quotient, corrected to the exact one
+                        int qd = (int)((float)u * inv_ct);
+                        qd -= qd * ct > u;
+                        qd += (qd + 1) * ct <= u;
+                        ja = bs + qd;
+                        ka = bt + (u - qd * ct);
                     }
                     const float4 A = S.au[ja], B = S.au[ka];
                     float c = A.x * B.x + A.y * B.y + A.z * B.z;
@@ -318,13 +327,26 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
                 }
                 wave_sync();
                 const int nv = min(kWave, np_ - u0);
-                const int h0 = (nv + 1) >> 1;
-                const int lo = half ? h0 : 0, hi = half ? nv : h0;
-                for (int m = lo; m < hi; ++m) acc += S.f1[m][cz] * S.f2[m][ca];
+                for (int m = rq; m < nv; m += 8) {
+                    const float4 f1v = *(const float4*)&S.f1[m][4 * rz];
+                    const float f2v = S.f2[m][ra];
+                    acc[0] += f1v.x * f2v;
+                    acc[1] += f1v.y * f2v;
+                    acc[2] += f1v.z * f2v;
+                    acc[3] += f1v.w * f2v;
+                }
                 wave_sync();
             }
-            const float tot = acc + shfl_xor(acc, 32);
-            if (half == 0) store_out(orow + P.radial_dim + 32 * p + az, tot);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                acc[i] += shfl_xor(acc[i], 8);
+                acc[i] += shfl_xor(acc[i], 16);
+                acc[i] += shfl_xor(acc[i], 32);
+            }
+            if (rq == 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) store_out(orow + P.radial_dim + 32 * p + 8 * ra + 4 * rz + i, acc[i]);
+            }
         }
     }
     for (int c = P.dim + l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
