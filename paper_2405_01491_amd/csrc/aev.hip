@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     const RowsView rows, const int32_t* __restrict__ out_row, OutT* __restrict__ out, unsigned* flags,
     int32_t* __restrict__ rev_out, const int32_t* __restrict__ gate) {
     __shared__ FwdLds lds[kWaves];
-    const int w = threadIdx.x / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: the atom is a scalar
     const int l = lane_id();
     const int i = blockIdx.x * kWaves + w;
     if (i >= n) return;
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
     const RowsView rows, const int32_t* __restrict__ g_row, const float* __restrict__ g, float4* __restrict__ G,
     float* __restrict__ Wat, unsigned* flags) {
     __shared__ BwdLds lds[kWaves];
-    const int w = threadIdx.x / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: the atom is a scalar
     const int l = lane_id();
     const int i = blockIdx.x * kWaves + w;
     if (i >= n) return;

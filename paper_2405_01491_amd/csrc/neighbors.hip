@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     __shared__ int s_beg[kRowsPerBlock][28];
     __shared__ int s_col[kRowsPerBlock][kRowLds];
     __shared__ int s_sh[kRowsPerBlock][kRowLds];
-    const int w = threadIdx.x / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: the row is a scalar
     const int l = lane_id();
     const int i = blockIdx.x * kRowsPerBlock + w;
     if (i >= n) return;
@@ -214,13 +214,21 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
         n_src = g.ns[0] * g.ns[1] * g.ns[2];
         int beg = 0, cnt = 0;
         if (l < n_src) {
-            const int a = l / (g.ns[1] * g.ns[2]);
-            const int b = (l / g.ns[2]) % g.ns[1];
-            const int c = l % g.ns[2];
-            // stencil: offsets -1..1 when nc >= 3, else every cell of the dimension
-            const int ox = g.nc[0] >= 3 ? (cx + a - 1 + g.nc[0]) % g.nc[0] : a;
-            const int oy = g.nc[1] >= 3 ? (cy + b - 1 + g.nc[1]) % g.nc[1] : b;
-            const int oz = g.nc[2] >= 3 ? (cz + c - 1 + g.nc[2]) % g.nc[2] : c;
+            int a, b, c;
+            if (n_src == 27) {   // 3 x 3 x 3 stencil: constant divisors
+                a = l / 9;
+                b = (l / 3) % 3;
+                c = l % 3;
+            } else {
+                a = l / (g.ns[1] * g.ns[2]);
+                b = (l / g.ns[2]) % g.ns[1];
+                c = l % g.ns[2];
+            }
+            // stencil: offsets -1..1 when nc >= 3 (wrapped periodically), else every cell of the dimension
+            auto wrap = [](int x, int nc) { return x < 0 ? x + nc : (x >= nc ? x - nc : x); };
+            const int ox = g.nc[0] >= 3 ? wrap(cx + a - 1, g.nc[0]) : a;
+            const int oy = g.nc[1] >= 3 ? wrap(cy + b - 1, g.nc[1]) : b;
+            const int oz = g.nc[2] >= 3 ? wrap(cz + c - 1, g.nc[2]) : c;
             const int cell = (ox * g.nc[1] + oy) * g.nc[2] + oz;
             beg = cell_start[cell];
             cnt = cell_start[cell + 1] - beg;
