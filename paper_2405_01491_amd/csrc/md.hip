@@ -58,6 +58,8 @@ __global__ __launch_bounds__(kFirstThreads) void k_md_first(int n, float* __rest
 __global__ __launch_bounds__(256) void k_md_decide(MdState* st, const float* __restrict__ d2_part, int n_parts,
                                                    int rebuild_every, float trigger2) {
     __shared__ float s_max[256 / kWave];
+    MdState cur{};
+    if (threadIdx.x == 0) cur = *st;
     float mx = 0.f;
     for (int q = threadIdx.x; q < n_parts; q += 256) mx = fmaxf(mx, d2_part[q]);
 #pragma unroll
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_md_decide(MdState* st, const float* __r
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int q = 1; q < 256 / kWave; ++q) mx = fmaxf(mx, s_max[q]);
-        md_decide(st, mx, rebuild_every, trigger2);
+        md_decide(st, cur, mx, rebuild_every, trigger2);
     }
 }
 

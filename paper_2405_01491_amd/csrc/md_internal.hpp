@@ -105,22 +105,23 @@ __device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, f
 }
 
 // Rebuild decision (one thread): every rebuild_every steps, or earlier once an
-// atom has moved more than trigger * skin / 2 since the last build.
-__device__ __forceinline__ int md_decide(MdState* st, float max_d2, int rebuild_every, float trigger2) {
-    const int since = st->since + 1;
+// atom has moved more than trigger * skin / 2 since the last build.  cur is
+// the state as read at the start of the kernel (loaded early, off the
+// critical path); the new state is written to st.
+__device__ __forceinline__ int md_decide(MdState* st, const MdState& cur, float max_d2, int rebuild_every,
+                                         float trigger2) {
+    const int since = cur.since + 1;
     const bool due = since >= rebuild_every;
     const bool moved = trigger2 >= 0.f && max_d2 > trigger2;
-    if (due || moved) {
-        st->gate = 1;
-        st->since = 0;
-        st->rebuilds += 1;
-        if (!due) st->early_rebuilds += 1;
-    } else {
-        st->gate = 0;
-        st->since = since;
-    }
+    const int gate = due || moved ? 1 : 0;
+    st->gate = gate;
+    st->since = gate ? 0 : since;
     st->max_d2 = 0.f;
-    return st->gate;
+    if (gate) {
+        st->rebuilds = cur.rebuilds + 1;
+        if (!due) st->early_rebuilds = cur.early_rebuilds + 1;
+    }
+    return gate;
 }
 
 // Energy fused into the last kernel of a step (small systems): what it needs.

@@ -391,6 +391,8 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     __shared__ int s_wsum[kFrontThreads / kWave];
     __shared__ int s_gate;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
+    MdState cur{};
+    if (t == 0) cur = *st;   // read now, used by the decision below
     float d2 = 0.f;
     float xs[kFrontPer][3];   // this thread's atoms after the half step (kept for the wrap and binning)
 #pragma unroll
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     if (t == 0) {
         float mx = 0.f;
         for (int q = 0; q < kFrontThreads / kWave; ++q) mx = fmaxf(mx, s_max[q]);
-        s_gate = md_decide(st, mx, rebuild_every, trigger2);
+        s_gate = md_decide(st, cur, mx, rebuild_every, trigger2);
     }
     __syncthreads();
     if (!s_gate) return;
