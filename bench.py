@@ -37,6 +37,57 @@ def mlp_flops_per_atom(widths):
     return fwd, adj
 
 
+def fused_tile_rows(n_atoms, precision):
+    """Rows per tile of the fused network kernel (as the library chooses them)."""
+    tm = 64 if n_atoms >= 48 * 1024 else (32 if n_atoms >= 12 * 1024 else 16)
+    return min(tm, 32) if precision != "bf16" else tm
+
+
+def mlp_useful_flops(w, spec, precision, nets=1):
+    """FLOP of one launch of the fused networks counting only the first
+    layer's products (forward and adjoint) over the feature blocks that some
+    atom of each species tile can have non-zero, as the kernel runs them: a
+    species' 16 radial features when it occurs within Rc_R of an atom of the
+    tile, a species pair's 32 angular features when both occur within Rc_A.
+    Returns (useful FLOP, dense FLOP, mean active features per atom)."""
+    from scipy.spatial import cKDTree
+    N, ns = w.n_atoms, spec.n_species
+    x = w.pos.astype(np.float64)
+    kw = {}
+    if w.box is not None:
+        L = np.asarray(w.box, dtype=np.float64)
+        x = np.mod(x, L)
+        x[x >= L] = 0.0
+        kw["boxsize"] = L
+    tree = cKDTree(x, **kw)
+    sp = w.species.astype(np.int64)
+    mask = np.zeros(N, dtype=np.int64)
+    for r, shift in ((spec.rc_r, 0), (spec.rc_a, 8)):
+        pr = tree.query_pairs(r, output_type="ndarray")
+        if len(pr):
+            np.bitwise_or.at(mask, pr[:, 0], 1 << (shift + sp[pr[:, 1]]))
+            np.bitwise_or.at(mask, pr[:, 1], 1 << (shift + sp[pr[:, 0]]))
+    widths = spec.widths
+    n1, D = widths[1], spec.aev_dim
+    fwd, adj = mlp_flops_per_atom(widths)
+    dense = (fwd + adj) * nets * N
+    tm = fused_tile_rows(N, precision)
+    useful, feats = 0.0, 0.0
+    for s in range(ns):
+        idx = np.nonzero(w.species == s)[0]
+        for t0 in range(0, len(idx), tm):
+            m = int(np.bitwise_or.reduce(mask[idx[t0:t0 + tm]]))
+            blocks = sum(1 for q in range(ns) if (m >> q) & 1)
+            blocks += sum(2 for q in range(ns) for u in range(q, ns) if (m >> (8 + q)) & (m >> (8 + u)) & 1)
+            F = 16 * blocks
+            rows = len(idx[t0:t0 + tm])
+            feats += F * rows
+            f_fwd = fwd - 2 * D * n1 + 2 * F * n1
+            f_adj = adj - 2 * n1 * D + 2 * n1 * F if nets == 1 else adj   # ensembles: dense first-layer adjoint
+            useful += nets * (f_fwd + f_adj) * rows
+    return useful, dense, feats / max(N, 1)
+
+
 # one kernel per timed stage where the roofline is reported
 STAGE_KERNEL = {("mlp", True): "k_mlp_fused", ("mlp", False): "k_gemm_* chain", ("aev", True): "k_aev_fwd",
                 ("aev", False): "k_aev_fwd", ("aev_adjoint", True): "k_aev_bwd",
@@ -361,12 +412,17 @@ def main():
     ms_dom, cnt_dom = stages[dom]
     avg_ms = ms_dom / max(cnt_dom, 1)
     if dom == "mlp":
-        flop = (fwd + adj) * N
+        flop, dense_flop, feats = (fwd + adj) * N, (fwd + adj) * N, float(spec.aev_dim)
+        if model.fused_mlp:
+            flop, dense_flop, feats = mlp_useful_flops(w, spec, precision, args.nets)
         peak = MI355X_PEAK["bf16_TFLOPs" if precision == "bf16" else "fp32_TFLOPs"]
         achieved = flop / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None, "stage": "mlp (per-species GEMM chain, forward + adjoint)",
-                "algorithmic_per_launch": "%.4g FLOP" % flop}
+                "algorithmic_per_launch": "%.4g FLOP" % flop,
+                "dense_equivalent_per_launch": "%.4g FLOP (every feature; the kernel skips feature blocks that "
+                                               "are zero for a whole tile)" % dense_flop,
+                "active_features_per_atom": round(feats, 1)}
     else:
         byt = stage_bytes(dom, N, n_pairs, precision, spec.aev_dim)
         achieved = byt / (avg_ms * 1e-3) / 1e9

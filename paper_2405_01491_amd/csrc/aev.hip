@@ -207,7 +207,7 @@ template <typename OutT>
 __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
     const RowsView rows, const int32_t* __restrict__ out_row, OutT* __restrict__ out, unsigned* flags,
-    int32_t* __restrict__ rev_out, const int32_t* __restrict__ gate) {
+    int32_t* __restrict__ rev_out, const int32_t* __restrict__ gate, uint32_t* __restrict__ amask) {
     __shared__ FwdLds lds[kWaves];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: the atom is a scalar
     const int l = lane_id();
@@ -239,8 +239,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     if (!load_row(R, P, i, pos, species, bx, rows, flags) ||
         !group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, &present, flags)) {
         for (int c = l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
+        if (amask && l == 0) amask[i] = 0xffffu;
         return;
     }
+    if (amask && l == 0) amask[i] = present;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         if (pr_[q] >= 0) {
@@ -600,15 +602,15 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
 
 hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
                           const RowsView& rows, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
-                          hipStream_t s, int32_t* rev_out, const int32_t* gate) {
+                          hipStream_t s, int32_t* rev_out, const int32_t* gate, uint32_t* amask_out) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
     if (bf16)
         k_aev_fwd<uint16_t><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, out_row, (uint16_t*)out,
-                                                            flags, rev_out, gate);
+                                                            flags, rev_out, gate, amask_out);
     else
         k_aev_fwd<float><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, out_row, (float*)out, flags,
-                                                         rev_out, gate);
+                                                         rev_out, gate, amask_out);
     return hipGetLastError();
 }
 

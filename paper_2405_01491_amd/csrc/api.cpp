@@ -130,6 +130,7 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.mw.meta = (int32_t*)take(sizeof(int32_t) * 32);
     W.mw.prow = (int32_t*)take(sizeof(int32_t) * nn);
     W.mw.row_atom = (int32_t*)take(sizeof(int32_t) * rows_max);
+    W.mw.amask = (uint32_t*)take(sizeof(uint32_t) * nn);
     W.mstart = (int32_t*)take(sizeof(int32_t) * (nn + 1));
     W.mend = (int32_t*)take(sizeof(int32_t) * (nn + 1));
     W.aev = take(sizeof(float) * (size_t)rows_max * m->aev.stride);
@@ -231,7 +232,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     if (n > 0) {
         prof_begin(m, NNP_STAGE_AEV, s);
         if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.aev, bf, flags, s,
-                               opts ? opts->rev_out : nullptr, opts ? opts->gate : nullptr);
+                               opts ? opts->rev_out : nullptr, opts ? opts->gate : nullptr, W.mw.amask);
         prof_end(m, NNP_STAGE_AEV, s);
         prof_begin(m, NNP_STAGE_MLP, s);
         if (e == hipSuccess) {
@@ -624,6 +625,8 @@ nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float*
     if (n == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
     const EfWs W = ef_layout(m, n, 0, (char*)ws);
+    MlpWs dense = W.mw;
+    dense.amask = nullptr;   // dE/dAEV of every feature is returned
     const bool fused = m->fused && (!m->force_unfused || m->n_nets > 1);
     const bool bfa = fused && m->precision == NNP_BF16_MLP;   // the fused BF16 kernels read bf16 rows
     void* rows = W.aev;
@@ -635,9 +638,9 @@ nnp_status nnp_mlp(nnp_model* m, int32_t n, const int32_t* species, const float*
     }
     if (e == hipSuccess) {
         if (fused && mlp_split(m, n))
-            e = launch_mlp_ensemble(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, W.d1, W.E_net,
+            e = launch_mlp_ensemble(m, dense, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, W.d1, W.E_net,
                                     nullptr, s);
-        else if (fused) e = launch_mlp_fused(m, W.mw, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, s);
+        else if (fused) e = launch_mlp_fused(m, dense, rows, daev_out ? W.g : nullptr, W.E_row, nullptr, n, s);
         else e = launch_mlp(m, W.mw, W.aev, false, W.h, daev_out ? W.g : nullptr, W.E_row, nullptr, s);
     }
     if (e == hipSuccess) e = launch_gather_e(W.mw.prow, n, species, self_e(m), W.E_row, e_atom, s);

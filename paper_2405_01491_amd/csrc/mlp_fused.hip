@@ -140,9 +140,10 @@ constexpr int ring_slots() { return NK % 3 == 0 ? 3 : 4; }
 
 // C[TM x (NCB*16 columns of this wave)] = A[TM x K] (LDS, stride ld) * B (packed, global)
 // FP32 pack: [nb][K/16][64 lanes][4]   BF16 pack: [nb][K/32][64 lanes][8]
+// nbl (optional): the NCB output column blocks, in place of nb0 .. nb0 + NCB - 1
 template <bool BF, int MB, int NCB, int K, bool kZero = true>
 __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int ld, const void* Bpack, int nb0,
-                                         f32x4 (&acc)[MB][NCB]) {
+                                         f32x4 (&acc)[MB][NCB], const int* nbl = nullptr) {
     typedef typename Frag<BF>::reg_t reg_t;
     typedef typename Frag<BF>::mem_t mem_t;
     constexpr int NK = K / Frag<BF>::kK;
@@ -156,11 +157,14 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
             for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
     const mem_t* B = (const mem_t*)Bpack;
+    int blk[NCB];
+#pragma unroll
+    for (int nb = 0; nb < NCB; ++nb) blk[nb] = nbl ? nbl[nb] : nb0 + nb;
     reg_t rb[RS][NCB];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int nb = 0; nb < NCB; ++nb) rb[t][nb] = B[((size_t)(nb0 + nb) * NK + t) * 64 + l];
+        for (int nb = 0; nb < NCB; ++nb) rb[t][nb] = B[((size_t)blk[nb] * NK + t) * 64 + l];
     for (int k0 = 0; k0 < NK; k0 += RS) {
 #pragma unroll
         for (int u = 0; u < RS; ++u) {
@@ -168,7 +172,7 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
             if (kq + 2 < NK) {
 #pragma unroll
                 for (int nb = 0; nb < NCB; ++nb)
-                    rb[(u + 2) % RS][nb] = B[((size_t)(nb0 + nb) * NK + kq + 2) * 64 + l];
+                    rb[(u + 2) % RS][nb] = B[((size_t)blk[nb] * NK + kq + 2) * 64 + l];
             }
             __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
             mfma_kstep<BF, MB, NCB>(act, ld, kq, rb[u], acc);
@@ -216,6 +220,9 @@ struct FusedArgs {
     void* d1_out;
     float* E_net;
     int rows;
+    // per atom, the species present in its environment (bits 0-7 radial,
+    // 8-15 angular); null: every feature block may be non-zero
+    const uint32_t* amask;
 };
 
 // kEns: network blockIdx.y of an ensemble; stops after d1 (the adjoint of the
@@ -259,15 +266,72 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     const float* const pw4 = tab->w4[s];
     const float hb4 = tab->b4[s];
 
-    // ---------------- layer 1: K0 -> N1, A streamed from HBM through LDS
+    // ---------------- active feature blocks of the tile
+    // A 16-feature block of the AEV (a species' radial shells, or half of a
+    // species pair's angular bin) is zero for an atom whose environment lacks
+    // that species.  The first layer runs only over the k-steps that hold a
+    // block some atom of the tile can have non-zero, and its adjoint only
+    // over those output blocks: the skipped products are exact zeros, and
+    // dE/dAEV is consumed only where the features are non-zero.  Without a
+    // mask every block is active.
+    constexpr int KS = Frag<BF>::kK;                          // features per k-step
+    constexpr int NT = K0 / KS, TPC = CH / KS;
+    constexpr int RS = 4, PD = 2, CPR = TPC >= RS ? 1 : RS / TPC;
+    static_assert((TPC >= RS ? TPC % RS : RS % TPC) == 0 && (K0 / CH) % CPR == 0, "chunks hold whole ring turns");
+    constexpr int kGran = TPC * CPR;                          // k-step list granularity
+    __shared__ int s_kq[NT];                                  // active k-steps, then -1 (zero) padding
+    __shared__ int s_ob[64];                                  // active adjoint output blocks, then -1
+    __shared__ int s_n[2];
+    if (t < kWave) {
+        unsigned m = 0xffffffffu;
+        if (A.amask) {
+            m = 0;
+            for (int r = l; r < TM; r += kWave) {
+                const int a = A.row_atom[row0 + r];
+                if (a >= 0) m |= A.amask[a];
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) m |= (unsigned)shfl_xor((int)m, d);
+        }
+        unsigned long long bm = ~0ull;
+        if (m != 0xffffffffu) {
+            bm = 0;
+            const int ns = A.ns;
+            for (int q = 0; q < ns; ++q)
+                if ((m >> q) & 1u) bm |= 1ull << q;
+            int p = 0;
+            for (int q = 0; q < ns; ++q)
+                for (int u = q; u < ns; ++u, ++p)
+                    if ((m >> (8 + q)) & (m >> (8 + u)) & 1u) bm |= 3ull << (ns + 2 * p);
+        }
+        // compact lists by ballot: lane b stands for block b (and for k-step b)
+        const bool kon = KS == 16 ? ((bm >> l) & 1ull) : (l < NT && ((bm >> (2 * l)) & 3ull));
+        const unsigned long long kb = ballot(kon);
+        const int nk = __popcll(kb), nk_pad = (nk + kGran - 1) / kGran * kGran;
+        if (kon) s_kq[rank_below(kb)] = l;
+        if (l < NT && l >= nk && l < nk_pad) s_kq[l] = -1;
+        const bool oon = (bm >> l) & 1ull;
+        const unsigned long long ob = ballot(oon);
+        const int no = __popcll(ob), no_pad = (no + 15) / 16 * 16;
+        if (oon) s_ob[rank_below(ob)] = l;
+        if (l >= no && l < no_pad) s_ob[l] = -1;
+        if (l == 0) {
+            s_n[0] = nk_pad;
+            s_n[1] = no_pad;
+        }
+    }
+    __syncthreads();
+    // ---------------- layer 1: K0 -> N1 over the active k-steps, A streamed
+    // from HBM through LDS (gathered by k-step)
     f32x4 h1[MB][4];
     {
         act_t* stage = act;
         const act_t* src = (const act_t*)A.aev + (size_t)row0 * K0;
         constexpr int kElems = TM * CH;                       // per chunk
-        constexpr int kVec = 16 / sizeof(act_t);              // elements per 16-byte load
+        constexpr int kVec = 16 / sizeof(act_t);              // elements per 16-byte load (within one k-step)
         constexpr int kPer = kElems / kVec / kThreads > 0 ? kElems / kVec / kThreads : 1;
         typedef typename std::conditional<BF, u16x8, float4>::type vec_t;
+        const int nk = s_n[0], nch = nk / TPC;
         vec_t pre[kPer];
         auto gload = [&](int c) {
 #pragma unroll
@@ -275,7 +339,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 const int idx = (t + kThreads * q) * kVec;
                 if (idx < kElems) {
                     const int r = idx / CH, cc = idx % CH;
-                    pre[q] = *(const vec_t*)(src + (size_t)r * K0 + c * CH + cc);
+                    const int kq = s_kq[c * TPC + cc / KS];
+                    if (kq >= 0) pre[q] = *(const vec_t*)(src + (size_t)r * K0 + kq * KS + cc % KS);
+                    else pre[q] = vec_t{};
                 }
             }
         };
@@ -296,37 +362,38 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) h1[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-        // B fragments of global k-step t in ring slot t % 4, loaded two k-steps
-        // ahead; a ring turn spans CPR chunks, so every slot index is known at
-        // compile time
-        constexpr int KS = Frag<BF>::kK;
-        constexpr int NT = K0 / KS, TPC = CH / KS, NCH = K0 / CH;
-        constexpr int RS = 4, PD = 2, CPR = TPC >= RS ? 1 : RS / TPC;
-        static_assert((TPC >= RS ? TPC % RS : RS % TPC) == 0 && NCH % CPR == 0, "chunks hold whole ring turns");
+        // B fragments of list entry e (k-step s_kq[e]; a zero-padding entry
+        // reads k-step 0 against zero features) in ring slot e % 4, loaded two
+        // entries ahead; a ring turn spans CPR chunks, so every slot index is
+        // known at compile time
         reg_t rb[RS][4];
-        auto loadB = [&](int t, reg_t (&d)[4]) {
+        auto loadB = [&](int e, reg_t (&d)[4]) {
+            const int kq = max(s_kq[e], 0);
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) d[nb] = B1[((size_t)(4 * w + nb) * NT + t) * 64 + l];
+            for (int nb = 0; nb < 4; ++nb) d[nb] = B1[((size_t)(4 * w + nb) * NT + kq) * 64 + l];
         };
 #pragma unroll
-        for (int t0 = 0; t0 < PD; ++t0) loadB(t0, rb[t0]);
-        gload(0);
-        sstore(0);
+        for (int t0 = 0; t0 < PD; ++t0)
+            if (t0 < nk) loadB(t0, rb[t0]);
+        if (nch > 0) {   // a tile of atoms without neighbours has no active k-step (h1 = CELU(b1))
+            gload(0);
+            sstore(0);
+        }
         __syncthreads();
-        for (int c0 = 0; c0 < NCH; c0 += CPR) {
+        for (int c0 = 0; c0 < nch; c0 += CPR) {
 #pragma unroll
             for (int cc = 0; cc < CPR; ++cc) {
                 const int c = c0 + cc;
-                if (c + 1 < NCH) gload(c + 1);
+                if (c + 1 < nch) gload(c + 1);
                 const act_t* cur = stage + (c & 1) * TM * CLD;
 #pragma unroll
                 for (int kq = 0; kq < TPC; ++kq) {
-                    const int t = c * TPC + kq, slot = (cc * TPC + kq) % RS;
-                    if (t + PD < NT) loadB(t + PD, rb[(slot + PD) % RS]);
+                    const int e = c * TPC + kq, slot = (cc * TPC + kq) % RS;
+                    if (e + PD < nk) loadB(e + PD, rb[(slot + PD) % RS]);
                     __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
                     mfma_kstep<BF, MB, 4>(cur, CLD, kq, rb[slot], h1);
                 }
-                if (c + 1 < NCH) sstore((c + 1) & 1);
+                if (c + 1 < nch) sstore((c + 1) & 1);
                 __syncthreads();
             }
         }
@@ -457,16 +524,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         for (int q = t; q < TM * N1; q += kThreads) dst[q] = act[(q / N1) * LD + (q % N1)];
         return;
     }
-    // ---------------- adjoint 1: g = W1^T d1, 1024 columns, 4 passes of 64 per wave
-    for (int pass = 0; pass < 4; ++pass) {
+    // ---------------- adjoint 1: g = W1^T d1 over the active output blocks
+    // (16 columns each), four blocks per wave and pass
+    const int no = s_n[1];
+    for (int pass = 0; pass < no / 16; ++pass) {
+        int blk[4], use[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            const int b = s_ob[16 * pass + 4 * w + nb];
+            use[nb] = b >= 0;
+            blk[nb] = max(b, 0);
+        }
         f32x4 gacc[MB][4];
-        const int nb0 = 16 * w + 4 * pass;
-        gemm_act<BF, MB, 4, N1>(act, LD, pBa1, nb0, gacc);
+        gemm_act<BF, MB, 4, N1>(act, LD, pBa1, 0, gacc, blk);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) {
-                const int col = 16 * (nb0 + nb) + (l & 15);
+                if (!use[nb]) continue;
+                const int col = 16 * blk[nb] + (l & 15);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     A.g_out[(size_t)(row0 + 16 * mb + 4 * (l >> 4) + r) * K0 + col] = gacc[mb][nb][r];
@@ -661,6 +737,7 @@ FusedArgs fused_args(const nnp_model* m, const MlpWs& W, const void* aev, float*
     A.alpha = m->celu_alpha;
     A.ns = m->aev.ns;
     A.rows = W.rows_max;
+    A.amask = W.amask;
     return A;
 }
 

@@ -133,6 +133,10 @@ struct MlpWs {
     int32_t* meta;       // [32]: counts[8], padded offsets[9]
     int32_t* prow;       // [n] atom -> grouped row
     int32_t* row_atom;   // [rows_max] grouped row -> atom (-1: padding)
+    // [n] species present in each atom's environment (bits 0-7 within the
+    // radial cutoff, 8-15 within the angular cutoff), from the AEV kernel;
+    // null: treat every feature as possibly non-zero
+    uint32_t* amask;
     int rows_max;
 };
 
@@ -228,9 +232,11 @@ inline RowsView rows_csr(const nnp_nlist* nl) {
 
 // rev_out (fixed-stride rows only, may be null): the reverse index of each
 // row, written while gate is null or *gate != 0 (the rows were rebuilt)
+// amask_out (may be null): each atom's species-presence mask (MlpWs::amask)
 hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
                           const RowsView& rows, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
-                          hipStream_t s, int32_t* rev_out = nullptr, const int32_t* gate = nullptr);
+                          hipStream_t s, int32_t* rev_out = nullptr, const int32_t* gate = nullptr,
+                          uint32_t* amask_out = nullptr);
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
                           const RowsView& rows, const int32_t* g_row, const float* g, float4* G,
                           float* atom_virial, unsigned* flags, hipStream_t s);

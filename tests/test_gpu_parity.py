@@ -307,3 +307,32 @@ def test_ensemble_bf16_matches_emulation():
     fe = np.abs(F.cpu().numpy() - emu["F"]).max()
     print("ensemble bf16 vs emulation (median, max): E/rms %.3g %.3g, F max %.3g" % (emed, emax, fe))
     assert emed < 1e-5 and emax < 1e-2 and fe < 2e-2
+
+
+def test_isolated_atoms_and_sparse_features(model, spec_bias):
+    """Atoms without neighbours (every feature zero) beside molecules of
+    several species: the networks see only the feature blocks some atom of a
+    tile can have non-zero, and the result equals the oracle's dense one."""
+    mols = synthetic.workload(4, n_mol=6)
+    pos = [mols.pos]
+    sp = [mols.species]
+    far = np.array([60.0, 60.0, 60.0], dtype=np.float32)
+    for k in range(20):   # lone atoms 12 A apart, one of each species in turn
+        pos.append((far + np.float32(12.0) * np.array([k % 4, (k // 4) % 4, k // 16], np.float32))[None, :])
+        sp.append(np.array([k % spec_bias.n_species], np.int32))
+    P = np.concatenate(pos).astype(np.float32)
+    S = np.concatenate(sp).astype(np.int32)
+    # the molecules keep their own ids; each lone atom is a structure of its own
+    M = np.concatenate([mols.mol, mols.n_mol + np.arange(20)]).astype(np.int32)
+    w = synthetic.geometry.Workload("molecules_and_lone_atoms", P, S, M, mols.n_mol + 20, None)
+    x, s_, m_ = to_dev(w)
+    nl = nnp.nnp_neighbors(model, x, m_, w.n_mol, None, 5.1)
+    e_mol, e_atom, F = nnp.nnp_energy_forces(model, x, s_, m_, w.n_mol, None, nl, e_atom=True)
+    torch.cuda.synchronize()
+    nnp.nnp_check(model)
+    ref = oracle_ef(w, spec_bias, r_list=5.1)
+    ee = energy_error(e_atom.cpu().numpy(), ref["E_atom"])
+    fe = np.max(np.abs(F.cpu().numpy() - ref["F"]))
+    em = np.max(np.abs(e_mol.cpu().numpy() - ref["E_mol"]) / np.maximum(1.0, np.abs(ref["E_mol"])))
+    print("isolated + molecules: E_atom err %.3g, E_mol err %.3g, F max err %.3g" % (ee, em, fe))
+    assert ee < E_ATOM_REL and em < 1e-5 and fe < F_MAX_ABS
