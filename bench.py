@@ -83,7 +83,7 @@ def mlp_useful_flops(w, spec, precision, nets=1):
             rows = len(idx[t0:t0 + tm])
             feats += F * rows
             f_fwd = fwd - 2 * D * n1 + 2 * F * n1
-            f_adj = adj - 2 * n1 * D + 2 * n1 * F if nets == 1 else adj   # ensembles: dense first-layer adjoint
+            f_adj = adj - 2 * n1 * D + 2 * n1 * F
             useful += nets * (f_fwd + f_adj) * rows
     return useful, dense, feats / max(N, 1)
 

@@ -225,6 +225,45 @@ struct FusedArgs {
     const uint32_t* amask;
 };
 
+// The 16-feature blocks (bit b: features 16 b .. 16 b + 15) that some atom of
+// the tile rows row0 .. row0 + TM - 1 can have non-zero: a species' radial
+// block when the species occurs within Rc_R of the atom, the two blocks of a
+// species pair's angular bin when both occur within Rc_A.  Every block
+// without a mask.  Wave-level: every lane of the calling wave returns it.
+template <int TM>
+__device__ __forceinline__ unsigned long long tile_blocks(const FusedArgs& A, int row0) {
+    if (!A.amask) return ~0ull;
+    const int l = lane_id();
+    unsigned m = 0;
+    for (int r = l; r < TM; r += kWave) {
+        const int a = A.row_atom[row0 + r];
+        if (a >= 0) m |= A.amask[a];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m |= (unsigned)shfl_xor((int)m, d);
+    unsigned long long bm = 0;
+    const int ns = A.ns;
+    for (int q = 0; q < ns; ++q)
+        if ((m >> q) & 1u) bm |= 1ull << q;
+    int p = 0;
+    for (int q = 0; q < ns; ++q)
+        for (int u = q; u < ns; ++u, ++p)
+            if ((m >> (8 + q)) & (m >> (8 + u)) & 1u) bm |= 3ull << (ns + 2 * p);
+    return bm;
+}
+
+// The set blocks of bm in ascending order into list[0 .. n), then -1 up to
+// the next multiple of gran (<= 64); returns that padded count.  Wave-level.
+__device__ __forceinline__ int block_list(unsigned long long bm, int* list, int gran) {
+    const int l = lane_id();
+    const bool on = (bm >> l) & 1ull;
+    const unsigned long long b = ballot(on);
+    const int n = __popcll(b), n_pad = (n + gran - 1) / gran * gran;
+    if (on) list[rank_below(b)] = l;
+    if (l >= n && l < n_pad) list[l] = -1;
+    return n_pad;
+}
+
 // kEns: network blockIdx.y of an ensemble; stops after d1 (the adjoint of the
 // first layer sums over networks, k_ens_adj1) and writes this network's
 // energies to E_net.
@@ -283,38 +322,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     __shared__ int s_ob[64];                                  // active adjoint output blocks, then -1
     __shared__ int s_n[2];
     if (t < kWave) {
-        unsigned m = 0xffffffffu;
-        if (A.amask) {
-            m = 0;
-            for (int r = l; r < TM; r += kWave) {
-                const int a = A.row_atom[row0 + r];
-                if (a >= 0) m |= A.amask[a];
-            }
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) m |= (unsigned)shfl_xor((int)m, d);
+        const unsigned long long bm = tile_blocks<TM>(A, row0);
+        // k-steps: a 16-feature step is a block, a 32-feature step a block pair
+        unsigned long long km = bm;
+        if (KS == 32) {
+            km = 0;
+            for (int j = 0; j < NT; ++j)
+                if ((bm >> (2 * j)) & 3ull) km |= 1ull << j;
         }
-        unsigned long long bm = ~0ull;
-        if (m != 0xffffffffu) {
-            bm = 0;
-            const int ns = A.ns;
-            for (int q = 0; q < ns; ++q)
-                if ((m >> q) & 1u) bm |= 1ull << q;
-            int p = 0;
-            for (int q = 0; q < ns; ++q)
-                for (int u = q; u < ns; ++u, ++p)
-                    if ((m >> (8 + q)) & (m >> (8 + u)) & 1u) bm |= 3ull << (ns + 2 * p);
-        }
-        // compact lists by ballot: lane b stands for block b (and for k-step b)
-        const bool kon = KS == 16 ? ((bm >> l) & 1ull) : (l < NT && ((bm >> (2 * l)) & 3ull));
-        const unsigned long long kb = ballot(kon);
-        const int nk = __popcll(kb), nk_pad = (nk + kGran - 1) / kGran * kGran;
-        if (kon) s_kq[rank_below(kb)] = l;
-        if (l < NT && l >= nk && l < nk_pad) s_kq[l] = -1;
-        const bool oon = (bm >> l) & 1ull;
-        const unsigned long long ob = ballot(oon);
-        const int no = __popcll(ob), no_pad = (no + 15) / 16 * 16;
-        if (oon) s_ob[rank_below(ob)] = l;
-        if (l >= no && l < no_pad) s_ob[l] = -1;
+        const int nk_pad = block_list(km, s_kq, kGran);
+        const int no_pad = block_list(bm, s_ob, 16);
         if (l == 0) {
             s_n[0] = nk_pad;
             s_n[1] = no_pad;
@@ -552,8 +569,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
 
 // Ensemble, first layer's adjoint summed over networks:
 //   g = (1 / n_nets) sum_net W1_net^T d1_net    (one GEMM with K = 256 n_nets)
-// and the ensemble-mean energies.  Block (tile, pass): 16-column blocks
-// 16 w + 4 pass .. + 3 of each wave, as in the single-network kernel.
+// and the ensemble-mean energies.  Block (tile, pass): the tile's active
+// output blocks 16 pass + 4 w .. + 3 (as in the single-network kernel).
 template <bool BF, int TM>
 __global__ __launch_bounds__(kThreads, 2) void k_ens_adj1(const FusedArgs A, int n_nets, float inv_nets,
                                                          float* E_atom_net, int n_atoms) {
@@ -571,26 +588,41 @@ __global__ __launch_bounds__(kThreads, 2) void k_ens_adj1(const FusedArgs A, int
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     constexpr int kVec = 16 / (int)sizeof(act_t);
     typedef typename std::conditional<BF, u16x8, float4>::type vec_t;
+    __shared__ int s_ob[64];
+    __shared__ int s_no;
+    if (t < kWave) {
+        const int no = block_list(tile_blocks<TM>(A, row0), s_ob, 16);
+        if (l == 0) s_no = no;
+    }
+    __syncthreads();
+    const bool work = A.g_out && 16 * pass < s_no;   // block-uniform
+    int blk[4], use[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int b = work ? s_ob[16 * pass + 4 * w + nb] : -1;
+        use[nb] = b >= 0;
+        blk[nb] = max(b, 0);
+    }
     f32x4 acc[MB][4];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const int nb0 = 16 * w + 4 * pass;
-    for (int net = 0; A.g_out && net < n_nets; ++net) {
+    for (int net = 0; work && net < n_nets; ++net) {
         const act_t* src = (const act_t*)A.d1_out + ((size_t)net * A.rows + row0) * N1;
         for (int q = t * kVec; q < TM * N1; q += kThreads * kVec)
             *(vec_t*)(act + (q / N1) * LD + (q % N1)) = *(const vec_t*)(src + q);
         __syncthreads();
-        gemm_act<BF, MB, 4, N1, false>(act, LD, A.nets[net].Ba1[s], nb0, acc);
+        gemm_act<BF, MB, 4, N1, false>(act, LD, A.nets[net].Ba1[s], 0, acc, blk);
         __syncthreads();
     }
-    if (A.g_out) {
+    if (work) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) {
-                const int col = 16 * (nb0 + nb) + (l & 15);
+                if (!use[nb]) continue;
+                const int col = 16 * blk[nb] + (l & 15);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     A.g_out[(size_t)(row0 + 16 * mb + 4 * (l >> 4) + r) * K0 + col] = acc[mb][nb][r] * inv_nets;
