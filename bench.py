@@ -43,15 +43,16 @@ def fused_tile_rows(n_atoms, precision):
     return min(tm, 32) if precision != "bf16" else tm
 
 
-def mlp_useful_flops(w, spec, precision, nets=1):
-    """FLOP of one launch of the fused networks counting only the first
-    layer's products (forward and adjoint) over the feature blocks that some
-    atom of each species tile can have non-zero, as the kernel runs them: a
-    species' 16 radial features when it occurs within Rc_R of an atom of the
-    tile, a species pair's 32 angular features when both occur within Rc_A.
-    Returns (useful FLOP, dense FLOP, mean active features per atom)."""
+_MASKS = {}
+
+
+def species_masks(w, spec):
+    """Per atom: bits 0-7 the species within Rc_R, 8-15 those within Rc_A."""
+    key = (w.name, w.n_atoms)
+    if key in _MASKS:
+        return _MASKS[key]
     from scipy.spatial import cKDTree
-    N, ns = w.n_atoms, spec.n_species
+    N = w.n_atoms
     x = w.pos.astype(np.float64)
     kw = {}
     if w.box is not None:
@@ -67,6 +68,26 @@ def mlp_useful_flops(w, spec, precision, nets=1):
         if len(pr):
             np.bitwise_or.at(mask, pr[:, 0], 1 << (shift + sp[pr[:, 1]]))
             np.bitwise_or.at(mask, pr[:, 1], 1 << (shift + sp[pr[:, 0]]))
+    _MASKS[key] = mask
+    return mask
+
+
+def active_features(m, ns):
+    """Features of the blocks a species mask can make non-zero."""
+    blocks = sum(1 for q in range(ns) if (m >> q) & 1)
+    blocks += sum(2 for q in range(ns) for u in range(q, ns) if (m >> (8 + q)) & (m >> (8 + u)) & 1)
+    return 16 * blocks
+
+
+def mlp_useful_flops(w, spec, precision, nets=1):
+    """FLOP of one launch of the fused networks counting only the first
+    layer's products (forward and adjoint) over the feature blocks that some
+    atom of each species tile can have non-zero, as the kernel runs them: a
+    species' 16 radial features when it occurs within Rc_R of an atom of the
+    tile, a species pair's 32 angular features when both occur within Rc_A.
+    Returns (useful FLOP, dense FLOP, mean active features per atom)."""
+    N, ns = w.n_atoms, spec.n_species
+    mask = species_masks(w, spec)
     widths = spec.widths
     n1, D = widths[1], spec.aev_dim
     fwd, adj = mlp_flops_per_atom(widths)
@@ -76,10 +97,7 @@ def mlp_useful_flops(w, spec, precision, nets=1):
     for s in range(ns):
         idx = np.nonzero(w.species == s)[0]
         for t0 in range(0, len(idx), tm):
-            m = int(np.bitwise_or.reduce(mask[idx[t0:t0 + tm]]))
-            blocks = sum(1 for q in range(ns) if (m >> q) & 1)
-            blocks += sum(2 for q in range(ns) for u in range(q, ns) if (m >> (8 + q)) & (m >> (8 + u)) & 1)
-            F = 16 * blocks
+            F = active_features(int(np.bitwise_or.reduce(mask[idx[t0:t0 + tm]])), ns)
             rows = len(idx[t0:t0 + tm])
             feats += F * rows
             f_fwd = fwd - 2 * D * n1 + 2 * F * n1
@@ -97,14 +115,17 @@ STAGE_SOURCE = {"mlp": "mlp_fused.hip", "aev": "aev.hip", "aev_adjoint": "aev.hi
                 "neighbors": "neighbors.hip"}
 
 
-def stage_bytes(stage, N, P, precision, D):
+def stage_bytes(stage, N, P, precision, D, Fg=None):
     """Algorithmic HBM bytes of one launch: every input read once, every
-    output written once (N atoms, P list pairs, D features)."""
+    output written once (N atoms, P list pairs, D features; the adjoint reads
+    dE/dAEV only for the Fg features per atom its environment can make
+    non-zero, D when not given)."""
+    Fg = D if Fg is None else Fg
     feat = 2 if precision == "bf16" else 4       # feature rows handed to the networks
     nl = 4 * (N + 1) + 7 * P                     # row_ptr, col (int32), shift (3 x int8)
     atoms = 20 * N                               # position, species, species-grouped row
     return {"aev": atoms + nl + feat * D * N,
-            "aev_adjoint": atoms + nl + 4 * D * N + 12 * P,
+            "aev_adjoint": atoms + nl + 4 * Fg * N + 12 * P,
             "forces": 4 * (N + 1) + 16 * P + 12 * N,
             "neighbors": 12 * N + nl + 4 * P}.get(stage, 0)
 
@@ -424,7 +445,10 @@ def main():
                                                "are zero for a whole tile)" % dense_flop,
                 "active_features_per_atom": round(feats, 1)}
     else:
-        byt = stage_bytes(dom, N, n_pairs, precision, spec.aev_dim)
+        Fg = None
+        if dom == "aev_adjoint":
+            Fg = float(np.mean([active_features(int(m), spec.n_species) for m in species_masks(w, spec)]))
+        byt = stage_bytes(dom, N, n_pairs, precision, spec.aev_dim, Fg)
         achieved = byt / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": MI355X_PEAK["hbm_GBs"], "unit": "GB/s",
                 "frac": achieved / MI355X_PEAK["hbm_GBs"], "traffic": None, "stage": dom,

@@ -398,8 +398,21 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
         if (kVir && l < 9) Wat[9 * (size_t)i + l] = 0.f;
         return;
     }
+    // dE/dAEV of the feature blocks this atom's environment can make non-zero
+    // (16 radial features per species present within Rc_R, 32 angular per
+    // species pair present within Rc_A); the kernel reads no others
+    unsigned long long bm = 0;
+#pragma unroll 1
+    for (int q = 0; q < ns; ++q)
+        if ((present >> q) & 1u) bm |= 1ull << q;
+    int pp0 = 0;
+#pragma unroll 1
+    for (int q = 0; q < ns; ++q)
+        for (int u = q; u < ns; ++u, ++pp0)
+            if ((present >> (8 + q)) & (present >> (8 + u)) & 1u) bm |= 3ull << (P.radial_dim / 16 + 2 * pp0);
     const float* grow = g + (size_t)row * P.stride;
-    for (int c = l; c < P.dim; c += kWave) S.g[c] = grow[c];
+    for (int c = l; c < P.dim; c += kWave)
+        if ((bm >> (c >> 4)) & 1ull) S.g[c] = grow[c];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         const int slot = l + kWave * q;
