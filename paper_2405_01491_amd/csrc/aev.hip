@@ -359,7 +359,6 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
 constexpr int kPairTile = 3 * kWave;     // angular pairs held at once by the adjoint
 
 struct BwdLds {
-    float g[1280];              // dE/dAEV row of the atom
     float4 au[kMaxA];           // angular list: unit vector, r
     float afc[kMaxA], adfc[kMaxA];
     int azs[kMaxA];             // species | slot << 8
@@ -398,21 +397,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
         if (kVir && l < 9) Wat[9 * (size_t)i + l] = 0.f;
         return;
     }
-    // dE/dAEV of the feature blocks this atom's environment can make non-zero
-    // (16 radial features per species present within Rc_R, 32 angular per
-    // species pair present within Rc_A); the kernel reads no others
-    unsigned long long bm = 0;
-#pragma unroll 1
-    for (int q = 0; q < ns; ++q)
-        if ((present >> q) & 1u) bm |= 1ull << q;
-    int pp0 = 0;
-#pragma unroll 1
-    for (int q = 0; q < ns; ++q)
-        for (int u = q; u < ns; ++u, ++pp0)
-            if ((present >> (8 + q)) & (present >> (8 + u)) & 1u) bm |= 3ull << (P.radial_dim / 16 + 2 * pp0);
-    const float* grow = g + (size_t)row * P.stride;
-    for (int c = l; c < P.dim; c += kWave)
-        if ((bm >> (c >> 4)) & 1ull) S.g[c] = grow[c];
+    // dE/dAEV of this atom, read where used (a species' 16 radial or a species
+    // pair's 32 angular coefficients: one or two cache lines shared by the
+    // lanes that need them)
+    const float* __restrict__ grow = g + (size_t)row * P.stride;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         const int slot = l + kWave * q;
@@ -442,7 +430,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
             const float r = r_[q];
             const float fc = cutoff_fc(r, P.pi_rc_r);
             const float dfc = -0.5f * P.pi_rc_r * __sinf(P.pi_rc_r * r);
-            const float* gs = &S.g[16 * R.z[q]];
+            const float* gs = grow + 16 * R.z[q];
             float dEdr = 0.f;
 #pragma unroll
             for (int k = 0; k < kNr; ++k) {
@@ -482,7 +470,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
                 const float dfj = S.adfc[ja], dfk = S.adfc[ka];
                 const int pp = species_pair(S.azs[ja] & 0xff, S.azs[ka] & 0xff, ns);
                 // this bin's 32 coefficients, [a][z] (radial_dim is a multiple of 16)
-            const float4* gp4 = (const float4*)&S.g[P.radial_dim + 32 * pp];
+            const float4* gp4 = (const float4*)(grow + P.radial_dim + 32 * pp);
             float gp[kNa * kNz];
 #pragma unroll
             for (int v = 0; v < kNa * kNz / 4; ++v) {
@@ -501,15 +489,17 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
                 }
                 float Rz[kNa] = {0.f, 0.f, 0.f, 0.f};
                 float sum_c = 0.f, Ssum = 0.f;
-                const float inv_sq = hw_rcp(sq);
+                const float us = uu * hw_rcp(sq);                 // u / sqrt(1 - u^2)
+                const float zm1 = P.zeta - 1.f, l2hz = __log2f(0.5f * P.zeta);
 #pragma unroll
                 for (int z = 0; z < kNz; ++z) {
-                    // base^zeta and its derivative; base = 0 gives log2 = -inf and both 0
+                    // base^zeta and its derivative (zeta/2) base^(zeta-1), the factor
+                    // folded into the exponent; base = 0 gives log2 = -inf and both 0
                     const float base = fmaxf(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), 0.f);
                     const float lg = hw_log2(base);
                     const float F1 = hw_exp2(P.zeta * lg);
-                    const float dF1 = 0.5f * P.zeta * hw_exp2((P.zeta - 1.f) * lg);
-                    const float dwdu = P.cos_z[z] - uu * P.sin_z[z] * inv_sq;
+                    const float dF1 = hw_exp2(fmaf(zm1, lg, l2hz));
+                    const float dwdu = P.cos_z[z] - us * P.sin_z[z];
                     float Q = 0.f;
 #pragma unroll
                     for (int a = 0; a < kNa; ++a) {
