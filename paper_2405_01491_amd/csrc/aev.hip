@@ -374,7 +374,7 @@ struct BwdLds {
 // kVir: also the per-centre virial W_i = -sum_j v_ij (outer) G_ij, row-major
 // [n][9] (the strain derivative of E_i is -W_i transposed).
 template <bool kVir>
-__global__ __launch_bounds__(kWaves* kWave) void k_aev_bwd(
+__global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
     const RowsView rows, const int32_t* __restrict__ g_row, const float* __restrict__ g, float4* __restrict__ G,
     float* __restrict__ Wat, unsigned* flags) {
