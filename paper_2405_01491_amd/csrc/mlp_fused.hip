@@ -138,17 +138,41 @@ __device__ __forceinline__ void mfma_kstep(const typename Cfg<BF>::act_t* act, i
 template <int NK>
 constexpr int ring_slots() { return NK % 3 == 0 ? 3 : 4; }
 
-// C[TM x (NCB*16 columns of this wave)] = A[TM x K] (LDS, stride ld) * B (packed, global)
+// The B-fragment ring of one product C[TM x (NCB*16 columns of this wave)] =
+// A[TM x K] (LDS, stride ld) * B (packed, global); start() issues the loads
+// of the first two k-steps, so that a caller can put them ahead of the
+// epilogue and barrier that precede the product (the barrier waits only for
+// LDS operations, not for these loads).
 // FP32 pack: [nb][K/16][64 lanes][4]   BF16 pack: [nb][K/32][64 lanes][8]
 // nbl (optional): the NCB output column blocks, in place of nb0 .. nb0 + NCB - 1
-template <bool BF, int MB, int NCB, int K, bool kZero = true>
-__device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int ld, const void* Bpack, int nb0,
-                                         f32x4 (&acc)[MB][NCB], const int* nbl = nullptr) {
+// (a negative entry reads block 0; its columns are discarded by the caller)
+template <bool BF, int NCB, int K>
+struct BPipe {
     typedef typename Frag<BF>::reg_t reg_t;
     typedef typename Frag<BF>::mem_t mem_t;
-    constexpr int NK = K / Frag<BF>::kK;
-    constexpr int RS = ring_slots<NK>();
+    static constexpr int NK = K / Frag<BF>::kK;
+    static constexpr int RS = ring_slots<NK>();
     static_assert(NK % RS == 0 && NK >= 2, "k-steps must fill whole rings");
+    reg_t rb[RS][NCB];
+    int blk[NCB];
+    const mem_t* B;
+    __device__ __forceinline__ void start(const void* Bpack, int nb0, const int* nbl = nullptr) {
+        const int l = lane_id();
+        B = (const mem_t*)Bpack;
+#pragma unroll
+        for (int nb = 0; nb < NCB; ++nb) blk[nb] = nbl ? max(nbl[nb], 0) : nb0 + nb;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NCB; ++nb) rb[t][nb] = B[((size_t)blk[nb] * NK + t) * 64 + l];
+    }
+};
+
+// The product of a started ring: acc (+)= A * B over the K rows.
+template <bool BF, int MB, int NCB, int K, bool kZero = true>
+__device__ __forceinline__ void gemm_run(const typename Cfg<BF>::act_t* act, int ld, BPipe<BF, NCB, K>& p,
+                                         f32x4 (&acc)[MB][NCB]) {
+    constexpr int NK = BPipe<BF, NCB, K>::NK, RS = BPipe<BF, NCB, K>::RS;
     const int l = lane_id();
     if (kZero) {
 #pragma unroll
@@ -156,15 +180,6 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
 #pragma unroll
             for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
-    const mem_t* B = (const mem_t*)Bpack;
-    int blk[NCB];
-#pragma unroll
-    for (int nb = 0; nb < NCB; ++nb) blk[nb] = nbl ? nbl[nb] : nb0 + nb;
-    reg_t rb[RS][NCB];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int nb = 0; nb < NCB; ++nb) rb[t][nb] = B[((size_t)blk[nb] * NK + t) * 64 + l];
     for (int k0 = 0; k0 < NK; k0 += RS) {
 #pragma unroll
         for (int u = 0; u < RS; ++u) {
@@ -172,12 +187,20 @@ __device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int
             if (kq + 2 < NK) {
 #pragma unroll
                 for (int nb = 0; nb < NCB; ++nb)
-                    rb[(u + 2) % RS][nb] = B[((size_t)blk[nb] * NK + kq + 2) * 64 + l];
+                    p.rb[(u + 2) % RS][nb] = p.B[((size_t)p.blk[nb] * NK + kq + 2) * 64 + l];
             }
             __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
-            mfma_kstep<BF, MB, NCB>(act, ld, kq, rb[u], acc);
+            mfma_kstep<BF, MB, NCB>(act, ld, kq, p.rb[u], acc);
         }
     }
+}
+
+template <bool BF, int MB, int NCB, int K, bool kZero = true>
+__device__ __forceinline__ void gemm_act(const typename Cfg<BF>::act_t* act, int ld, const void* Bpack, int nb0,
+                                         f32x4 (&acc)[MB][NCB], const int* nbl = nullptr) {
+    BPipe<BF, NCB, K> p;
+    p.start(Bpack, nb0, nbl);
+    gemm_run<BF, MB, NCB, K, kZero>(act, ld, p, acc);
 }
 
 template <bool BF>
@@ -264,6 +287,22 @@ __device__ __forceinline__ int block_list(unsigned long long bm, int* list, int 
     return n_pad;
 }
 
+// dE/dAEV of the tile rows row0 .. for the output blocks b (16 columns
+// each; a negative block is padding and is not stored)
+template <int MB, int NCB>
+__device__ __forceinline__ void store_g(float* g, int row0, const f32x4 (&acc)[MB][NCB], const int (&b)[NCB]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NCB; ++nb) {
+            if (b[nb] < 0) continue;
+            const int col = 16 * b[nb] + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g[(size_t)(row0 + 16 * mb + 4 * (l >> 4) + r) * K0 + col] = acc[mb][nb][r];
+        }
+}
+
 // kEns: network blockIdx.y of an ensemble; stops after d1 (the adjoint of the
 // first layer sums over networks, k_ens_adj1) and writes this network's
 // energies to E_net.
@@ -331,7 +370,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 if ((bm >> (2 * j)) & 3ull) km |= 1ull << j;
         }
         const int nk_pad = block_list(km, s_kq, kGran);
-        const int no_pad = block_list(bm, s_ob, 16);
+        const int no_pad = block_list(bm, s_ob, 8);
         if (l == 0) {
             s_n[0] = nk_pad;
             s_n[1] = no_pad;
@@ -415,6 +454,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
             }
         }
     }
+    // layer 2's first weight fragments, loaded while the epilogue runs
+    BPipe<BF, 3, N1> p2;
+    p2.start(pBf2, 3 * w);
     // epilogue 1: h1 = CELU(z1 + b1) (kept), act = h1
     {
         const float* b1 = pb1;
@@ -434,7 +476,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     __syncthreads();
     // ---------------- layer 2: N1 -> N2
     f32x4 h2[MB][3];
-    gemm_act<BF, MB, 3, N1>(act, LD, pBf2, 3 * w, h2);
+    gemm_run<BF, MB, 3, N1>(act, LD, p2, h2);
+    BPipe<BF, 3, N2> p3;
+    p3.start(pBf3, 3 * w);
     __syncthreads();
     {
         const float* b2 = pb2;
@@ -453,9 +497,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     }
     __syncthreads();
     // ---------------- layer 3: N2 -> N3 (160 padded to 192), head, d3
+    BPipe<BF, 3, N3> pa3;
     {
         f32x4 z3[MB][3];
-        gemm_act<BF, MB, 3, N2>(act, LD, pBf3, 3 * w, z3);
+        gemm_run<BF, MB, 3, N2>(act, LD, p3, z3);
+        if (A.g_out) pa3.start(pBa3, 3 * w);
         __syncthreads();
         const float* b3 = pb3;
         const float* w4 = pw4;
@@ -502,9 +548,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     }
     if (!A.g_out) return;
     // ---------------- adjoint 3: d2 = (W3^T d3) * CELU'(h2)
+    BPipe<BF, 4, N2> pa2;
     {
         f32x4 d[MB][3];
-        gemm_act<BF, MB, 3, N3>(act, LD, pBa3, 3 * w, d);
+        gemm_run<BF, MB, 3, N3>(act, LD, pa3, d);
+        pa2.start(pBa2, 4 * w);
         __syncthreads();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -519,9 +567,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     }
     __syncthreads();
     // ---------------- adjoint 2: d1 = (W2^T d2) * CELU'(h1)
+    // adjoint 1 runs over the active output blocks (16 columns each, listed
+    // in s_ob and padded with -1 to a multiple of eight): passes of four
+    // blocks per wave, then one pass of two for a remainder of eight
+    const int no = s_n[1], n16 = no / 16;
+    BPipe<BF, 4, N1> pg4;
+    BPipe<BF, 2, N1> pg2;
     {
         f32x4 d[MB][4];
-        gemm_act<BF, MB, 4, N2>(act, LD, pBa2, 4 * w, d);
+        gemm_run<BF, MB, 4, N2>(act, LD, pa2, d);
+        if (!kEns) {
+            if (n16 > 0) pg4.start(pBa1, 0, s_ob + 4 * w);
+            else if (no > 0) pg2.start(pBa1, 0, s_ob + 2 * w);
+        }
         __syncthreads();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -542,28 +600,23 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         return;
     }
     // ---------------- adjoint 1: g = W1^T d1 over the active output blocks
-    // (16 columns each), four blocks per wave and pass
-    const int no = s_n[1];
-    for (int pass = 0; pass < no / 16; ++pass) {
-        int blk[4], use[4];
+    for (int pass = 0; pass < n16; ++pass) {
+        const int* ob = s_ob + 16 * pass + 4 * w;
+        int b[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int b = s_ob[16 * pass + 4 * w + nb];
-            use[nb] = b >= 0;
-            blk[nb] = max(b, 0);
-        }
+        for (int nb = 0; nb < 4; ++nb) b[nb] = ob[nb];
         f32x4 gacc[MB][4];
-        gemm_act<BF, MB, 4, N1>(act, LD, pBa1, 0, gacc, blk);
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                if (!use[nb]) continue;
-                const int col = 16 * blk[nb] + (l & 15);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    A.g_out[(size_t)(row0 + 16 * mb + 4 * (l >> 4) + r) * K0 + col] = gacc[mb][nb][r];
-            }
+        gemm_run<BF, MB, 4, N1>(act, LD, pg4, gacc);
+        if (pass + 1 < n16) pg4.start(pBa1, 0, ob + 16);
+        else if (no > 16 * n16) pg2.start(pBa1, 0, s_ob + 16 * n16 + 2 * w);
+        store_g<MB, 4>(A.g_out, row0, gacc, b);
+    }
+    if (no > 16 * n16) {
+        const int* ob = s_ob + 16 * n16 + 2 * w;
+        const int b[2] = {ob[0], ob[1]};
+        f32x4 gacc[MB][2];
+        gemm_run<BF, MB, 2, N1>(act, LD, pg2, gacc);
+        store_g<MB, 2>(A.g_out, row0, gacc, b);
     }
 }
 
