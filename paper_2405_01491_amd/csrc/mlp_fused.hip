@@ -35,6 +35,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // loads would also count against the LDS wait counter, so every wait for an
 // LDS read would wait for the prefetched weights as well.
 typedef __attribute__((address_space(1))) const f32x4 gfloat4;
+typedef __attribute__((address_space(1))) const float gfloat;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(1))) const u16x8 gu16x8;
@@ -62,8 +63,14 @@ struct Cfg<true> {                  // BF16
     static constexpr int kPad = 8;
 };
 
-__device__ __forceinline__ float celu(float v, float alpha) { return v > 0.f ? v : alpha * (__expf(v / alpha) - 1.f); }
-__device__ __forceinline__ float celu_grad_from_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
+// CELU and its derivative from the output, h > 0 ? 1 : 1 + h / alpha (ia =
+// 1 / alpha); both sides are evaluated and one selected, so the epilogues
+// run without divergent branches
+__device__ __forceinline__ float celu(float v, float alpha, float ia) {
+    const float neg = alpha * (__expf(fminf(v, 0.f) * ia) - 1.f);
+    return v > 0.f ? v : neg;
+}
+__device__ __forceinline__ float celu_grad_from_h(float h, float ia) { return h > 0.f ? 1.f : fmaf(h, ia, 1.f); }
 
 // one MFMA k-step: A fragment from LDS activations (row stride ld), B fragment given
 template <bool BF>
@@ -328,7 +335,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     // skip tiles that hold only segment padding
     if (row0 >= meta[8 + s] + meta[s]) return;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
-    const float alpha = A.alpha;
+    const float alpha = A.alpha, ia = 1.f / alpha;
     const int net = kEns ? blockIdx.y : 0;
     // this network's and species' pointers, loaded once (the table is read-only)
     const FusedNet* __restrict__ tab = A.nets + net;
@@ -377,6 +384,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         }
     }
     __syncthreads();
+    // This wave's bias and head-weight columns are read once, through
+    // global-address-space pointers (as the weight packs), each ahead of the
+    // product before its epilogue: the epilogues then hold no memory reads,
+    // and their waits leave the next product's prefetched weights in flight.
+    float cb1[4], cb2[3], cb3[3], cw4[3];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) cb1[nb] = ((const gfloat*)pb1)[64 * w + 16 * nb + (l & 15)];
     // ---------------- layer 1: K0 -> N1 over the active k-steps, A streamed
     // from HBM through LDS (gathered by k-step)
     f32x4 h1[MB][4];
@@ -457,9 +471,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     // layer 2's first weight fragments, loaded while the epilogue runs
     BPipe<BF, 3, N1> p2;
     p2.start(pBf2, 3 * w);
+#pragma unroll
+    for (int nb = 0; nb < 3; ++nb) cb2[nb] = ((const gfloat*)pb2)[48 * w + 16 * nb + (l & 15)];
     // epilogue 1: h1 = CELU(z1 + b1) (kept), act = h1
     {
-        const float* b1 = pb1;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -467,7 +482,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 const int col = 64 * w + 16 * nb + (l & 15);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float h = celu(h1[mb][nb][r] + b1[col], alpha);
+                    const float h = celu(h1[mb][nb][r] + cb1[nb], alpha, ia);
                     h1[mb][nb][r] = h;
                     put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col, h);
                 }
@@ -479,9 +494,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     gemm_run<BF, MB, 3, N1>(act, LD, p2, h2);
     BPipe<BF, 3, N2> p3;
     p3.start(pBf3, 3 * w);
+#pragma unroll
+    for (int nb = 0; nb < 3; ++nb) {
+        cb3[nb] = ((const gfloat*)pb3)[48 * w + 16 * nb + (l & 15)];
+        cw4[nb] = ((const gfloat*)pw4)[48 * w + 16 * nb + (l & 15)];
+    }
     __syncthreads();
     {
-        const float* b2 = pb2;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -489,7 +508,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 const int col = 48 * w + 16 * nb + (l & 15);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float h = celu(h2[mb][nb][r] + b2[col], alpha);
+                    const float h = celu(h2[mb][nb][r] + cb2[nb], alpha, ia);
                     h2[mb][nb][r] = h;
                     put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col, h);
                 }
@@ -503,8 +522,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
         gemm_run<BF, MB, 3, N2>(act, LD, p3, z3);
         if (A.g_out) pa3.start(pBa3, 3 * w);
         __syncthreads();
-        const float* b3 = pb3;
-        const float* w4 = pw4;
         float part[MB][4];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -515,12 +532,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
 #pragma unroll
             for (int nb = 0; nb < 3; ++nb) {
                 const int col = 48 * w + 16 * nb + (l & 15);
-                const float wc = w4[col];
+                const float wc = cw4[nb];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float h = celu(z3[mb][nb][r] + b3[col], alpha);
+                    const float h = celu(z3[mb][nb][r] + cb3[nb], alpha, ia);
                     part[mb][r] += h * wc;
-                    put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col, wc * celu_grad_from_h(h, alpha));
+                    put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col, wc * celu_grad_from_h(h, ia));
                 }
             }
         // reduce the 16 lanes sharing a row (columns), fixed butterfly
@@ -562,7 +579,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col,
-                                d[mb][nb][r] * celu_grad_from_h(h2[mb][nb][r], alpha));
+                                d[mb][nb][r] * celu_grad_from_h(h2[mb][nb][r], ia));
             }
     }
     __syncthreads();
@@ -589,7 +606,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     put_act<BF>(act, (16 * mb + 4 * (l >> 4) + r) * LD + col,
-                                d[mb][nb][r] * celu_grad_from_h(h1[mb][nb][r], alpha));
+                                d[mb][nb][r] * celu_grad_from_h(h1[mb][nb][r], ia));
             }
     }
     __syncthreads();
