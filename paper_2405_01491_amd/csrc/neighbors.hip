@@ -125,8 +125,10 @@ __device__ __forceinline__ bool finite3(float3 p) {
 }
 
 __device__ __forceinline__ int cell_coord(float x, double L, double inv_cs, int nc) {
-    double xd = (double)x;
-    double w = xd - L * floor(xd / L);
+    // a coordinate already in [0, L) is its own image (floor(x / L) is 0
+    // there), so only coordinates outside the box take the division
+    double w = (double)x;
+    if (w < 0.0 || w >= L) w -= L * floor(w / L);
     int c = (int)(w * inv_cs);
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
@@ -429,9 +431,11 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
             fin = fin && isfinite(v);
             if (g.periodic && isfinite(v)) {
                 const float L = g.Lf[d];
-                v -= L * floorf(v / L);
-                if (v >= L) v -= L;
-                if (v < 0.f) v = 0.f;
+                if (v < 0.f || v >= L) {   // inside the box floor(v / L) is 0: v stays
+                    v -= L * floorf(v / L);
+                    if (v >= L) v -= L;
+                    if (v < 0.f) v = 0.f;
+                }
                 pos[3 * a + d] = v;
             }
             ref[3 * a + d] = v;
