@@ -182,11 +182,138 @@ __global__ void k_finite(const float* pos, int n, unsigned* flags, const int32_t
     if (!finite3(load_pos(pos, i))) set_flag(flags, NNP_FLAG_NONFINITE);
 }
 
+// The stencil's source cells around cell ci (3 x 3 x 3, or every cell of a
+// dimension with fewer than three), one per lane below the returned count
+// n_src: beg[k] is source k's first slot in cell_atoms and off[k] the
+// exclusive prefix of the sources' atom counts, off[n_src] their total.
+// Wave-level.
+__device__ __forceinline__ int stencil_sources(const Grid& g, int ci, const int32_t* cell_start, int* off,
+                                               int* beg) {
+    const int l = lane_id();
+    const int cz = ci % g.nc[2];
+    const int cy = (ci / g.nc[2]) % g.nc[1];
+    const int cx = ci / (g.nc[2] * g.nc[1]);
+    const int n_src = g.ns[0] * g.ns[1] * g.ns[2];
+    int b0 = 0, cnt = 0;
+    if (l < n_src) {
+        int a, b, c;
+        if (n_src == 27) {   // 3 x 3 x 3 stencil: constant divisors
+            a = l / 9;
+            b = (l / 3) % 3;
+            c = l % 3;
+        } else {
+            a = l / (g.ns[1] * g.ns[2]);
+            b = (l / g.ns[2]) % g.ns[1];
+            c = l % g.ns[2];
+        }
+        // stencil: offsets -1..1 when nc >= 3 (wrapped periodically), else every cell of the dimension
+        auto wrap = [](int x, int nc) { return x < 0 ? x + nc : (x >= nc ? x - nc : x); };
+        const int ox = g.nc[0] >= 3 ? wrap(cx + a - 1, g.nc[0]) : a;
+        const int oy = g.nc[1] >= 3 ? wrap(cy + b - 1, g.nc[1]) : b;
+        const int oz = g.nc[2] >= 3 ? wrap(cz + c - 1, g.nc[2]) : c;
+        const int cell = (ox * g.nc[1] + oy) * g.nc[2] + oz;
+        b0 = cell_start[cell];
+        cnt = cell_start[cell + 1] - b0;
+    }
+    // inclusive scan of counts over the first n_src lanes
+    int inc = cnt;
+    for (int d = 1; d < 32; d <<= 1) {
+        int u = __shfl_up(inc, d, kWave);
+        if (l >= d) inc += u;
+    }
+    if (l < n_src) {
+        off[l] = inc - cnt;
+        beg[l] = b0;
+    }
+    if (l == n_src - 1) off[n_src] = inc;
+    return n_src;
+}
+
+// Slot in cell_atoms (or atom index without cells) of candidate t: source k
+// is the last one with off[k] <= t (off[n_src] = total > t)
+__device__ __forceinline__ int cand_slot(const int* off, const int* beg, int n_src, int t) {
+    int lo = 0, hi = n_src;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= t) lo = mid; else hi = mid;
+    }
+    return beg[lo] + (t - off[lo]);
+}
+
+// The row of atom i (position xi) over candidates t = 0 .. total - 1:
+// fetch(t, j, xj) gives candidate t's index j and returns whether it may be
+// a neighbour, then with its position xj.  The kept pairs are compacted into
+// the wave's LDS row (s_col, s_sh), rank-sorted by neighbour index and
+// written to the staging row i * kRowLds with the count; a row longer than
+// kRowLds raises NNP_FLAG_ROW and is left empty.  Wave-level.
+template <class Fetch>
+__device__ __forceinline__ void build_row(int i, float3 xi, int total, Fetch fetch, const Grid& g, double r2,
+                                          float rf, int* s_col, int* s_sh, int32_t* row_count, int32_t* stage_col,
+                                          int32_t* stage_sh, unsigned* flags) {
+    const int l = lane_id();
+    int count = 0;
+    bool overflow = false;
+    for (int base = 0; base < total; base += kWave) {
+        const int t = base + l;
+        bool keep = false;
+        int j = -1, sh = 0;
+        float3 xj;
+        if (t < total && fetch(t, j, xj)) {
+            PairOut o = pair_predicate(xi, xj, g, r2, rf);
+            keep = o.keep;
+            sh = o.packed_shift;
+            if (keep && sh == -1) {
+                set_flag(flags, NNP_FLAG_SHIFT);
+                sh = 0;
+            }
+        }
+        const unsigned long long m = ballot(keep);
+        if (keep) {
+            const int pos_in_row = count + rank_below(m);
+            if (pos_in_row < kRowLds) {
+                s_col[pos_in_row] = j;
+                s_sh[pos_in_row] = sh;
+            } else {
+                overflow = true;
+            }
+        }
+        count += __popcll(m);
+    }
+    if (overflow || count > kRowLds) {
+        if (l == 0) {
+            set_flag(flags, NNP_FLAG_ROW);
+            row_count[i] = 0;
+        }
+        wave_sync();
+        return;
+    }
+    wave_sync();
+    // rank sort by neighbour index (indices in a row are distinct); the row
+    // is read four entries per 16-byte LDS load, several loads in flight
+    int32_t* oc = stage_col + (size_t)i * kRowLds;
+    int32_t* os = stage_sh + (size_t)i * kRowLds;
+    for (int e = l; e < count; e += kWave) {
+        const int je = s_col[e];
+        int rank = 0, f = 0;
+#pragma unroll 4
+        for (; f + 4 <= count; f += 4) {
+            const int4 q = *(const int4*)(s_col + f);
+            rank += (q.x < je) + (q.y < je) + (q.z < je) + (q.w < je);
+        }
+        for (; f < count; ++f) rank += s_col[f] < je;
+        oc[rank] = je;
+        os[rank] = s_sh[e];
+    }
+    if (l == 0) row_count[i] = count;
+    wave_sync();   // the LDS row is free for the wave's next row
+}
+
 // One wave per row: the row's pairs are found once, rank-sorted by
 // neighbour index in LDS and written to a fixed-stride staging row
 // (stage_col / stage_sh at i * kRowLds) with their count; k_compact then
 // copies the rows to their CSR offsets.  A row longer than kRowLds raises
-// NNP_FLAG_ROW and is left empty.
+// NNP_FLAG_ROW and is left empty.  Candidates come from the atom's stencil
+// cells (periodic) or its structure (free), each read from global memory.
 __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     const float* pos, int n, const int32_t* mol, int n_mol, const Grid g, double r2, const int32_t* cell_of,
     const int32_t* cell_start, const int32_t* cell_atoms, const int32_t* mol_start, const int32_t* mol_end,
@@ -194,7 +321,7 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     if (gate && *gate == 0) return;
     __shared__ int s_off[kRowsPerBlock][28];
     __shared__ int s_beg[kRowsPerBlock][28];
-    __shared__ int s_col[kRowsPerBlock][kRowLds];
+    __shared__ __attribute__((aligned(16))) int s_col[kRowsPerBlock][kRowLds];
     __shared__ int s_sh[kRowsPerBlock][kRowLds];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: the row is a scalar
     const int l = lane_id();
@@ -210,42 +337,7 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
             if (l == 0) row_count[i] = 0;
             return;
         }
-        const int cz = ci % g.nc[2];
-        const int cy = (ci / g.nc[2]) % g.nc[1];
-        const int cx = ci / (g.nc[2] * g.nc[1]);
-        n_src = g.ns[0] * g.ns[1] * g.ns[2];
-        int beg = 0, cnt = 0;
-        if (l < n_src) {
-            int a, b, c;
-            if (n_src == 27) {   // 3 x 3 x 3 stencil: constant divisors
-                a = l / 9;
-                b = (l / 3) % 3;
-                c = l % 3;
-            } else {
-                a = l / (g.ns[1] * g.ns[2]);
-                b = (l / g.ns[2]) % g.ns[1];
-                c = l % g.ns[2];
-            }
-            // stencil: offsets -1..1 when nc >= 3 (wrapped periodically), else every cell of the dimension
-            auto wrap = [](int x, int nc) { return x < 0 ? x + nc : (x >= nc ? x - nc : x); };
-            const int ox = g.nc[0] >= 3 ? wrap(cx + a - 1, g.nc[0]) : a;
-            const int oy = g.nc[1] >= 3 ? wrap(cy + b - 1, g.nc[1]) : b;
-            const int oz = g.nc[2] >= 3 ? wrap(cz + c - 1, g.nc[2]) : c;
-            const int cell = (ox * g.nc[1] + oy) * g.nc[2] + oz;
-            beg = cell_start[cell];
-            cnt = cell_start[cell + 1] - beg;
-        }
-        // inclusive scan of counts over the first n_src lanes
-        int inc = cnt;
-        for (int d = 1; d < 32; d <<= 1) {
-            int u = __shfl_up(inc, d, kWave);
-            if (l >= d) inc += u;
-        }
-        if (l < n_src) {
-            s_off[w][l] = inc - cnt;
-            s_beg[w][l] = beg;
-        }
-        if (l == n_src - 1) s_off[w][n_src] = inc;
+        n_src = stencil_sources(g, ci, cell_start, s_off[w], s_beg[w]);
     } else {
         n_src = 1;
         if (l == 0) {
@@ -265,64 +357,84 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     }
     wave_sync();
     const int total = s_off[w][n_src];
-    int count = 0;
-    bool overflow = false;
-    for (int base = 0; base < total; base += kWave) {
-        const int t = base + l;
-        bool keep = false;
-        int j = -1, sh = 0;
-        if (t < total) {
-            // last source k with s_off[k] <= t (s_off[n_src] = total > t)
-            int lo = 0, hi = n_src;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_off[w][mid] <= t) lo = mid; else hi = mid;
-            }
-            const int k = lo;
-            const int idx = s_beg[w][k] + (t - s_off[w][k]);
-            j = g.periodic ? cell_atoms[idx] : idx;
-            if (j != i && (!mol || mol[j] == mi)) {
-                const float3 xj = load_pos(pos, j);
-                PairOut o = pair_predicate(xi, xj, g, r2, rf);
-                keep = o.keep;
-                sh = o.packed_shift;
-                if (keep && sh == -1) {
-                    set_flag(flags, NNP_FLAG_SHIFT);
-                    sh = 0;
-                }
-            }
-        }
-        const unsigned long long m = ballot(keep);
-        if (keep) {
-            const int pos_in_row = count + rank_below(m);
-            if (pos_in_row < kRowLds) {
-                s_col[w][pos_in_row] = j;
-                s_sh[w][pos_in_row] = sh;
-            } else {
-                overflow = true;
-            }
-        }
-        count += __popcll(m);
+    const int* off = s_off[w];
+    const int* beg = s_beg[w];
+    auto fetch = [&](int t, int& j, float3& xj) {
+        const int idx = cand_slot(off, beg, n_src, t);
+        j = g.periodic ? cell_atoms[idx] : idx;
+        if (j == i || (mol && mol[j] != mi)) return false;
+        xj = load_pos(pos, j);
+        return true;
+    };
+    build_row(i, xi, total, fetch, g, r2, rf, s_col[w], s_sh[w], row_count, stage_col, stage_sh, flags);
+}
+
+// The same rows for a periodic system without structure ids, one block per
+// cell: the block stages the positions of its stencil's atoms in LDS once,
+// and its waves build the rows of the cell's atoms from there (each atom's
+// position is read once per stencil it belongs to, not once per neighbour
+// search that visits it).  A stencil of more than kCellCand atoms is read
+// from global memory per row instead.  Every block also empties the rows of
+// its share of the atoms outside every cell (non-finite coordinates).
+constexpr int kCellWaves = 16;
+constexpr int kCellCand = 1536;
+__global__ __launch_bounds__(kCellWaves* kWave) void k_rows_cells(
+    const float* pos, int n, int n_cells, const Grid g, double r2, const int32_t* cell_of, const int32_t* cell_start,
+    const int32_t* cell_atoms, int32_t* row_count, int32_t* stage_col, int32_t* stage_sh, unsigned* flags,
+    const int32_t* gate) {
+    if (gate && *gate == 0) return;
+    __shared__ int s_off[28];
+    __shared__ int s_beg[28];
+    __shared__ float4 s_x[kCellCand];
+    __shared__ __attribute__((aligned(16))) int s_col[kCellWaves][kRowLds];
+    __shared__ int s_sh[kCellWaves][kRowLds];
+    const int c = blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    {
+        const int per = (n + n_cells - 1) / n_cells;
+        const int a1 = min(n, (c + 1) * per);
+        for (int a = c * per + (int)threadIdx.x; a < a1; a += kCellWaves * kWave)
+            if (cell_of[a] < 0) row_count[a] = 0;
     }
-    if (overflow || count > kRowLds) {
-        if (l == 0) {
-            set_flag(flags, NNP_FLAG_ROW);
-            row_count[i] = 0;
+    const int h0 = cell_start[c], h1 = cell_start[c + 1];
+    if (h1 <= h0) return;
+    int n_src = 0;
+    if (w == 0) n_src = stencil_sources(g, c, cell_start, s_off, s_beg);
+    __syncthreads();
+    n_src = g.ns[0] * g.ns[1] * g.ns[2];
+    const int total = s_off[n_src];
+    const float rf = (float)sqrt(r2);
+    if (total <= kCellCand) {
+        for (int t = threadIdx.x; t < total; t += kCellWaves * kWave) {
+            const int j = cell_atoms[cand_slot(s_off, s_beg, n_src, t)];
+            const float3 x = load_pos(pos, j);
+            s_x[t] = make_float4(x.x, x.y, x.z, __int_as_float(j));
         }
-        return;
+        __syncthreads();
+        for (int r = h0 + w; r < h1; r += kCellWaves) {
+            const int i = cell_atoms[r];
+            const float3 xi = load_pos(pos, i);
+            auto fetch = [&](int t, int& j, float3& xj) {
+                const float4 q = s_x[t];
+                j = __float_as_int(q.w);
+                xj = make_float3(q.x, q.y, q.z);
+                return j != i;
+            };
+            build_row(i, xi, total, fetch, g, r2, rf, s_col[w], s_sh[w], row_count, stage_col, stage_sh, flags);
+        }
+    } else {
+        for (int r = h0 + w; r < h1; r += kCellWaves) {
+            const int i = cell_atoms[r];
+            const float3 xi = load_pos(pos, i);
+            auto fetch = [&](int t, int& j, float3& xj) {
+                j = cell_atoms[cand_slot(s_off, s_beg, n_src, t)];
+                if (j == i) return false;
+                xj = load_pos(pos, j);
+                return true;
+            };
+            build_row(i, xi, total, fetch, g, r2, rf, s_col[w], s_sh[w], row_count, stage_col, stage_sh, flags);
+        }
     }
-    wave_sync();
-    // rank sort by neighbour index (indices in a row are distinct)
-    int32_t* oc = stage_col + (size_t)i * kRowLds;
-    int32_t* os = stage_sh + (size_t)i * kRowLds;
-    for (int e = l; e < count; e += kWave) {
-        const int je = s_col[w][e];
-        int rank = 0;
-        for (int f = 0; f < count; ++f) rank += s_col[w][f] < je;
-        oc[rank] = je;
-        os[rank] = s_sh[w][e];
-    }
-    if (l == 0) row_count[i] = count;
 }
 
 // Staging rows -> CSR at row_ptr (only the first row_ptr[i+1] - row_ptr[i]
@@ -647,9 +759,15 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         } else {
             k_finite<<<nb, tb, 0, s>>>(pos, n, flags, gate);
         }
-        k_rows<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
-            pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count, stage_col,
-            stage_sh, flags, gate);
+        if (g.periodic && !mol) {
+            k_rows_cells<<<(int)n_cells, kCellWaves * kWave, 0, s>>>(pos, n, (int)n_cells, g, r2, cell_of,
+                                                                      cell_start, cell_atoms, row_count, stage_col,
+                                                                      stage_sh, flags, gate);
+        } else {
+            k_rows<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
+                pos, n, mol, n_mol, g, r2, cell_of, cell_start, cell_atoms, mol_start, mol_end, row_count,
+                stage_col, stage_sh, flags, gate);
+        }
     }
     if (rows_out) {
         RowsView r{};

@@ -1,6 +1,8 @@
 """Neighbour list on the GPU vs the oracle: the pair set (i, j, image shift)
 must be identical bit for bit; rows sorted; reverse index consistent; the
 capacity / box / non-finite / mol error protocol."""
+import types
+
 import numpy as np
 import pytest
 import torch
@@ -60,6 +62,24 @@ def test_workload_pair_sets(model, name, r_list):
     pos, sp, mol = to_dev(w)
     nl = nnp.nnp_neighbors(model, pos, mol, w.n_mol, w.box, r_list)
     _check_list(nl, w, r_list)
+
+
+def test_dense_stencil_reads_candidates_from_global(model):
+    """Periodic rows are built per cell from the stencil's atoms staged in
+    LDS; a stencil holding more atoms than that stage (here the whole box:
+    2,100 random atoms in a 19.9 A box, three cells of 1.3 r_list per side,
+    about 150 neighbours per row) is searched from global memory row by
+    row.  The list is exact either way."""
+    rng = np.random.default_rng(31)
+    L, n = 19.9, 2100
+    w = types.SimpleNamespace(name="dense_box", pos=(rng.random((n, 3)) * L).astype(np.float32),
+                              species=np.zeros(n, np.int32), mol=np.zeros(n, np.int32), n_mol=1,
+                              box=np.array([L, L, L], np.float32), n_atoms=n)
+    pos, sp, _ = to_dev(w)
+    nl = nnp.nnp_neighbors(model, pos, None, 1, w.box, 5.1)
+    torch.cuda.synchronize()
+    _check_list(nl, w, 5.1)
+    assert np.diff(nl.row_ptr.cpu().numpy()).max() < 256
 
 
 @pytest.mark.parametrize("cfg,r_list", [(3, 5.1), (5, 5.6)])
