@@ -52,15 +52,20 @@ __device__ __forceinline__ int species_pair(int s, int t, int ns) {
     return s * ns - (s * (s - 1)) / 2 + (t - s);
 }
 
-// (j, k) of the v-th unordered pair (j < k) of c items in row-major triangle order
+// (j, k) of the v-th unordered pair (j < k) of c <= NNP_MAX_ANGULAR items in
+// row-major triangle order.  j is the largest integer with j (2c - j - 1) / 2
+// <= v; the float root of that quadratic is exact up to the square root's
+// rounding, so its truncation is off by at most one and one correction step
+// each way gives j (checked exhaustively for every c and v, with the root
+// perturbed by up to 4 ulp).  The products are below 2^24: 24-bit multiplies.
 __device__ __forceinline__ void tri_decode(int v, int c, int& j, int& k) {
     const float tc = (float)(2 * c - 1);
     int jj = (int)((tc - hw_sqrt(fmaxf(tc * tc - 8.0f * (float)v, 0.f))) * 0.5f);
     jj = max(0, min(jj, c - 2));
-    while (jj > 0 && (jj * (2 * c - jj - 1)) / 2 > v) --jj;
-    while (jj + 1 <= c - 2 && ((jj + 1) * (2 * c - jj - 2)) / 2 <= v) ++jj;
+    jj -= jj > 0 && (__mul24(jj, 2 * c - jj - 1) >> 1) > v;
+    jj += jj + 1 <= c - 2 && (__mul24(jj + 1, 2 * c - jj - 2) >> 1) <= v;
     j = jj;
-    k = jj + 1 + (v - (jj * (2 * c - jj - 1)) / 2);
+    k = jj + 1 + (v - (__mul24(jj, 2 * c - jj - 1) >> 1));
 }
 
 // base^zeta for base in [0, 1] (log2 0 = -inf gives 0; a base rounded below
@@ -306,10 +311,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
                     } else {
                         // u = j' ct + k': the float quotient, corrected to the exact one
                         int qd = (int)((float)u * inv_ct);
-                        qd -= qd * ct > u;
-                        qd += (qd + 1) * ct <= u;
+                        qd -= __mul24(qd, ct) > u;
+                        qd += __mul24(qd + 1, ct) <= u;
                         ja = bs + qd;
-                        ka = bt + (u - qd * ct);
+                        ka = bt + (u - __mul24(qd, ct));
                     }
                     const float4 A = S.au[ja], B = S.au[ka];
                     float c = A.x * B.x + A.y * B.y + A.z * B.z;
