@@ -525,12 +525,14 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
                 const float sk = 0.5f * dEdrbar + 2.f * fj * Ssum * dfk;
                 const float ij = rj > 0.f ? hw_rcp(rj) : 0.f;
                 const float ik = rk > 0.f ? hw_rcp(rk) : 0.f;
-                S.pb[u - c0][0] = dEdc * (B.x - c * A.x) * ij + sj * A.x;
-                S.pb[u - c0][1] = dEdc * (B.y - c * A.y) * ij + sj * A.y;
-                S.pb[u - c0][2] = dEdc * (B.z - c * A.z) * ij + sj * A.z;
-                S.pb[u - c0][3] = dEdc * (A.x - c * B.x) * ik + sk * B.x;
-                S.pb[u - c0][4] = dEdc * (A.y - c * B.y) * ik + sk * B.y;
-                S.pb[u - c0][5] = dEdc * (A.z - c * B.z) * ik + sk * B.z;
+                // tile slot u - c0 < kPairTile: its offset by a 24-bit multiply
+                float* pb = &S.pb[0][0] + __mul24(u - c0, 6);
+                pb[0] = dEdc * (B.x - c * A.x) * ij + sj * A.x;
+                pb[1] = dEdc * (B.y - c * A.y) * ij + sj * A.y;
+                pb[2] = dEdc * (B.z - c * A.z) * ij + sj * A.z;
+                pb[3] = dEdc * (A.x - c * B.x) * ik + sk * B.x;
+                pb[4] = dEdc * (A.y - c * B.y) * ik + sk * B.y;
+                pb[5] = dEdc * (A.z - c * B.z) * ik + sk * B.z;
             }
         }
         wave_sync();
@@ -538,13 +540,13 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
         for (int q = 0; q < 2; ++q) {
             if (q * kWave >= n_a) break;   // wave-uniform
             const int m = l + q * kWave;
-            const int Tm = m * (2 * n_a - m - 1) / 2;   // first pair (m, m + 1)
+            const int Tm = __mul24(m, 2 * n_a - m - 1) >> 1;   // first pair (m, m + 1)
             int Tj = 0;                                 // first pair (j, j + 1)
             for (int j = 0; j + 1 < n_a; ++j) {
                 const bool before = j < m;              // pair (j, m), else pair (m, j + 1)
                 const int t = before ? Tj + (m - j - 1) : Tm + (j - m);
                 if (m < n_a && t >= c0 && t < c1) {
-                    const float* e = &S.pb[t - c0][before ? 3 : 0];
+                    const float* e = &S.pb[0][0] + __mul24(t - c0, 6) + (before ? 3 : 0);
                     ax_[q] += e[0];
                     ay_[q] += e[1];
                     az_[q] += e[2];
