@@ -190,21 +190,23 @@ def test_engine_nve_energy_log(spec):
 def test_engine_langevin_thermalises(spec):
     """A cold start heats to the bath temperature (equipartition, 3N/2 kT).
 
-    The kinetic temperature of BAOAB, read after the closing half kick, is
-    biased by O(dt^2) in proportion to the stiffness of the forces; with the
-    random-weight network's forces a 0.5 fs step runs about 15 % hot, so the
-    test takes 0.25 fs (the same 300 fs of simulated time), where that bias
-    is small against the tolerance."""
+    The water box is far from a minimum of the random-weight network's
+    potential, which keeps releasing potential energy as the box relaxes
+    (the hydrogens are not bonded): with a 10 fs coupling time (100/ps) the
+    atoms run about 10 % above the bath at every step from 0.125 to 0.5 fs.
+    That excess falls with the coupling time, so the test couples at 1 fs
+    (1000/ps) and averages the last 150 fs of 300."""
     w = synthetic.geometry.small_water_box(64)
     model = nnp.Model(spec, "fp32")
     v0 = np.zeros((w.n_atoms, 3), np.float32)
-    eng = _engine(model, w, v0, dt=0.25, integrator="langevin", temperature=300.0, friction=100.0, seed=12,
+    eng = _engine(model, w, v0, dt=0.25, integrator="langevin", temperature=300.0, friction=1000.0, seed=12,
                   skin=0.5, rebuild_every=20, log_every=20, log_capacity=100)
     eng.run(1200)
     ke = eng.log()[-30:, 1].mean()
     want = 1.5 * w.n_atoms * nmd.KB_EV * 300.0
     print("Langevin cold start: <KE> %.4f eV, 3N kT/2 %.4f eV, info %s" % (ke, want, eng.info()))
-    assert abs(ke / want - 1.0) < 0.15
+    # about 1 % sampling noise (30 samples 5 fs apart, one per coupling time or more)
+    assert abs(ke / want - 1.0) < 0.05
 
 
 def test_engine_general_path_tracks_oracle(spec_bias):
