@@ -220,18 +220,34 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     if (i >= n) return;
     FwdLds& S = lds[w];
     // fixed-stride rows just rebuilt: the reverse index of this row (the rows
-    // are sorted by neighbour, so j's slot of i is found by bisection)
+    // are sorted by neighbour, so j's slot of i is found by bisection).  A lane
+    // searches the rows of its pairs p and p + 64 side by side, so that the
+    // dependent loads of the two searches are in flight together; a finished
+    // search issues no load.
     if (rev_out && (!gate || *gate)) {
         const int b = rows.begin(i), e = rows.end(i);
-        for (int p = b + l; p < e; p += kWave) {
-            const int j = rows.col[p];
-            const int bj = rows.begin(j);
-            int lo = bj, hi = rows.end(j);
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (rows.col[mid] < i) lo = mid + 1; else hi = mid;
+        for (int p0 = b + l; p0 < e; p0 += 2 * kWave) {
+            const int p1 = p0 + kWave;
+            const bool two = p1 < e;
+            const int j0 = rows.col[p0];
+            const int j1 = two ? rows.col[p1] : j0;
+            const int e0 = rows.end(j0), e1 = two ? rows.end(j1) : e0;
+            int lo0 = rows.begin(j0), hi0 = e0;
+            int lo1 = rows.begin(j1), hi1 = two ? e1 : lo1;
+            while (lo0 < hi0 || lo1 < hi1) {
+                const int m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
+                int c0 = 0, c1 = 0;
+                if (lo0 < hi0) c0 = rows.col[m0];
+                if (lo1 < hi1) c1 = rows.col[m1];
+                if (lo0 < hi0) {
+                    if (c0 < i) lo0 = m0 + 1; else hi0 = m0;
+                }
+                if (lo1 < hi1) {
+                    if (c1 < i) lo1 = m1 + 1; else hi1 = m1;
+                }
             }
-            rev_out[p] = (lo < rows.end(j) && rows.col[lo] == i) ? lo : p;
+            rev_out[p0] = (lo0 < e0 && rows.col[lo0] == i) ? lo0 : p0;
+            if (two) rev_out[p1] = (lo1 < e1 && rows.col[lo1] == i) ? lo1 : p1;
         }
     }
     const int row = out_row ? out_row[i] : i;
