@@ -3,11 +3,14 @@
 // orthorhombic box, rows sorted by neighbour index, plus the reverse index.
 //
 // Periodic systems use an integer cell list (cells at least r_list wide, a
-// 27-cell stencil, or every cell along a dimension with fewer than 3 cells);
-// open systems scan all atoms of the same structure.  Candidates of one row
-// are streamed across the 64 lanes of a wave and compacted with ballots; the
-// row is rank-sorted in LDS before it is written, so the output does not
-// depend on the (atomic) order in which atoms were binned.
+// 27-cell stencil, or every cell along a dimension with fewer than 3 cells):
+// without structure ids one block per cell stages the stencil's positions in
+// LDS and builds the rows of the cell's atoms from there.  Systems with
+// structure ids, and open systems (all atoms of the same structure), search
+// per row from global memory.  Candidates of one row are streamed across the
+// 64 lanes of a wave and compacted with ballots; the row is rank-sorted in
+// LDS before it is written, so the output does not depend on the (atomic)
+// order in which atoms were binned.
 //
 // The pair predicate is evaluated in float64 with every operation rounded
 // (floating-point contraction is disabled in that function), so the pair set
