@@ -37,10 +37,11 @@ def mlp_flops_per_atom(widths):
     return fwd, adj
 
 
-def fused_tile_rows(n_atoms, precision):
-    """Rows per tile of the fused network kernel (as the library chooses them)."""
+def fused_tile_rows(n_atoms, precision, nets=1):
+    """Rows per tile of the fused network kernel (as the library chooses them):
+    64 only for the BF16 ensemble from 48 Ki atoms, else at most 32."""
     tm = 64 if n_atoms >= 48 * 1024 else (32 if n_atoms >= 12 * 1024 else 16)
-    return min(tm, 32) if precision != "bf16" else tm
+    return tm if (precision == "bf16" and nets > 1) else min(tm, 32)
 
 
 _MASKS = {}
@@ -92,7 +93,7 @@ def mlp_useful_flops(w, spec, precision, nets=1):
     n1, D = widths[1], spec.aev_dim
     fwd, adj = mlp_flops_per_atom(widths)
     dense = (fwd + adj) * nets * N
-    tm = fused_tile_rows(N, precision)
+    tm = fused_tile_rows(N, precision, nets)
     useful, feats = 0.0, 0.0
     for s in range(ns):
         idx = np.nonzero(w.species == s)[0]

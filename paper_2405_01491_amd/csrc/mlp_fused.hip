@@ -817,11 +817,14 @@ void fused_net_entry(void* out, int ns, const char* const* packs, const float* c
 
 namespace {
 
-// tile height: enough tiles to fill the chip twice over (the FP32 form stops at
-// 32 rows: its 64-row tile does not fit the register file)
-int fused_tile_rows(int n_atoms, bool bf) {
+// tile height: enough tiles to fill the chip twice over.  One network stops
+// at 32 rows (the FP32 form's 64-row tile does not fit the register file, and
+// the BF16 form's runs slower than two 32-row tiles); the BF16 ensemble takes
+// 64 rows from 48 Ki atoms, where its first-layer adjoint over all networks
+// gains from the taller tile.
+int fused_tile_rows(int n_atoms, bool bf, bool ens) {
     int tm = n_atoms >= 48 * 1024 ? 64 : (n_atoms >= 12 * 1024 ? 32 : 16);
-    if (!bf && tm > 32) tm = 32;
+    if ((!bf || !ens) && tm > 32) tm = 32;
     return tm;
 }
 
@@ -849,11 +852,10 @@ hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev,
                             float* E_atomo, int n_atoms, hipStream_t s) {
     const bool bf = m->precision == NNP_BF16_MLP;
     const FusedArgs A = fused_args(m, W, aev, g_out, E_row, E_atomo);
-    const int tm = fused_tile_rows(n_atoms, bf);
+    const int tm = fused_tile_rows(n_atoms, bf, false);
     const int grid = ceil_div(W.rows_max, tm);
     if (bf) {
-        if (tm == 64) k_mlp_fused<true, 64, false><<<grid, kThreads, 0, s>>>(A);
-        else if (tm == 32) k_mlp_fused<true, 32, false><<<grid, kThreads, 0, s>>>(A);
+        if (tm == 32) k_mlp_fused<true, 32, false><<<grid, kThreads, 0, s>>>(A);
         else k_mlp_fused<true, 16, false><<<grid, kThreads, 0, s>>>(A);
     } else {
         if (tm == 32) k_mlp_fused<false, 32, false><<<grid, kThreads, 0, s>>>(A);
@@ -874,7 +876,7 @@ hipError_t launch_mlp_ensemble(const nnp_model* m, const MlpWs& W, const void* a
     FusedArgs A = fused_args(m, W, aev, g_out, E_row, E_atomo);
     A.d1_out = d1_scratch;
     A.E_net = E_net;
-    const int tm = fused_tile_rows(n_atoms, bf);
+    const int tm = fused_tile_rows(n_atoms, bf, true);
     const dim3 g1(ceil_div(W.rows_max, tm), m->n_nets), g2(ceil_div(W.rows_max, tm), g_out ? 4 : 1);
     const float inv = 1.f / (float)m->n_nets;
     if (bf) {
