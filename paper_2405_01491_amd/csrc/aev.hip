@@ -198,12 +198,21 @@ __device__ __forceinline__ bool group_species(const Row& R, int ns, int* pos_r, 
 // ---------------------------------------------------------------- forward
 
 struct FwdLds {
-    float rr[kMaxR];           // radial list: r, fc (species-grouped)
-    float rfc[kMaxR];
     float4 au[kMaxA];          // angular list: unit vector, r
     float afc[kMaxA];
-    alignas(16) float f1[kWave][kNz];   // pair tile: 8 angle factors
-    float f2[kWave][kNa];      // pair tile: 4 radial factors times 2 fc fc
+    // the radial list is read only before the angular pair tile is first
+    // written, so the two share their space (5 KB per wave, not 7: eight
+    // waves per SIMD instead of five)
+    union {
+        struct {
+            float rr[kMaxR];   // radial list: r, fc (species-grouped)
+            float rfc[kMaxR];
+        } rad;
+        struct {
+            alignas(16) float f1[kWave][kNz];   // pair tile: 8 angle factors
+            float f2[kWave][kNa];               // 4 radial factors times 2 fc fc
+        } tile;
+    };
     int seg_r[kMaxSpecies + 1];
     int seg_a[kMaxSpecies + 1];
 };
@@ -268,8 +277,8 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     for (int q = 0; q < kQ; ++q) {
         if (pr_[q] >= 0) {
             const float r = hw_sqrt(R.r2[q]);
-            S.rr[pr_[q]] = r;
-            S.rfc[pr_[q]] = cutoff_fc(r, P.pi_rc_r);
+            S.rad.rr[pr_[q]] = r;
+            S.rad.rfc[pr_[q]] = cutoff_fc(r, P.pi_rc_r);
             if (pa_[q] >= 0) {
                 const float inv = r > 0.f ? hw_rcp(r) : 0.f;
                 S.au[pa_[q]] = make_float4(R.vx[q] * inv, R.vy[q] * inv, R.vz[q] * inv, r);
@@ -290,14 +299,15 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
             const int sb = S.seg_r[s], se = S.seg_r[s + 1];
             float acc = 0.f;
             for (int m = sb + q; m < se; m += 4) {
-                const float d = S.rr[m] - rk;
-                acc += __expf(-P.eta_r * d * d) * S.rfc[m];
+                const float d = S.rad.rr[m] - rk;
+                acc += __expf(-P.eta_r * d * d) * S.rad.rfc[m];
             }
             acc += shfl_xor(acc, 16);
             acc += shfl_xor(acc, 32);
             if (q == 0) store_out(orow + 16 * s + k, P.pr * acc);
         }
     }
+    wave_sync();   // the radial list is read; its space becomes the pair tile
     // ---- angular: one species-pair bin at a time, one pair per lane into an
     // LDS tile; then lane (ra, rz, rq) sums f1[z] f2[ra] for the four angle
     // sections z = 4 rz .. 4 rz + 3 over the tile's pairs rq, rq + 8, ...,
@@ -342,17 +352,17 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
 #pragma unroll
                     for (int a = 0; a < kNa; ++a) {
                         const float d = rbar - P.shf_a[a];
-                        S.f2[l][a] = w2 * __expf(-P.eta_a * d * d);
+                        S.tile.f2[l][a] = w2 * __expf(-P.eta_a * d * d);
                     }
 #pragma unroll
                     for (int z = 0; z < kNz; ++z)
-                        S.f1[l][z] = pow_zeta(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), P.zeta);
+                        S.tile.f1[l][z] = pow_zeta(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), P.zeta);
                 }
                 wave_sync();
                 const int nv = min(kWave, np_ - u0);
                 for (int m = rq; m < nv; m += 8) {
-                    const float4 f1v = *(const float4*)&S.f1[m][4 * rz];
-                    const float f2v = S.f2[m][ra];
+                    const float4 f1v = *(const float4*)&S.tile.f1[m][4 * rz];
+                    const float f2v = S.tile.f2[m][ra];
                     acc[0] += f1v.x * f2v;
                     acc[1] += f1v.y * f2v;
                     acc[2] += f1v.z * f2v;
