@@ -336,3 +336,32 @@ def test_isolated_atoms_and_sparse_features(model, spec_bias):
     em = np.max(np.abs(e_mol.cpu().numpy() - ref["E_mol"]) / np.maximum(1.0, np.abs(ref["E_mol"])))
     print("isolated + molecules: E_atom err %.3g, E_mol err %.3g, F max err %.3g" % (ee, em, fe))
     assert ee < E_ATOM_REL and em < 1e-5 and fe < F_MAX_ABS
+
+
+def test_angular_neighbour_limit(model, spec_bias):
+    """A compact cluster, every atom within 3.4 A of a central one: 25 to 92
+    angular neighbours per atom (the limit is NNP_MAX_ANGULAR = 96), 4,186
+    angular pairs for the centre, bins of one species and of two, so the
+    kernels' pair enumeration runs over pair counts up to the limit."""
+    rng = np.random.default_rng(41)
+    n = 93
+    pts = [np.zeros(3)]
+    while len(pts) < n:   # uniform in the ball, at least 0.7 A apart
+        p = rng.uniform(-3.4, 3.4, 3)
+        if np.linalg.norm(p) <= 3.4 and min(np.linalg.norm(p - q) for q in pts) >= 0.7:
+            pts.append(p)
+    P = (np.array(pts) + 20.0).astype(np.float32)
+    S = rng.integers(0, 4, size=n).astype(np.int32)
+    d = np.linalg.norm(P[:, None] - P[None], axis=2)
+    assert ((d < 3.5) & (d > 0)).sum(axis=1).max() == 92
+    w = synthetic.geometry.Workload("angular_limit_cluster", P, S, np.zeros(n, np.int32), 1, None)
+    x, s_, _ = to_dev(w)
+    nl = nnp.nnp_neighbors(model, x, None, 1, None, 5.1)
+    e_mol, e_atom, F = nnp.nnp_energy_forces(model, x, s_, None, 1, None, nl, e_atom=True)
+    torch.cuda.synchronize()
+    nnp.nnp_check(model)
+    ref = oracle_ef(w, spec_bias, r_list=5.1)
+    ee = energy_error(e_atom.cpu().numpy(), ref["E_atom"])
+    fe = np.max(np.abs(F.cpu().numpy() - ref["F"]))
+    print("angular limit cluster: E_atom err %.3g, F max err %.3g eV/A (max |F| %.3g)" % (ee, fe, np.abs(ref["F"]).max()))
+    assert ee < E_ATOM_REL and fe < F_MAX_ABS
