@@ -95,7 +95,7 @@ __global__ void k_md_wrap_ref(int n, float* pos, float* ref, BoxConst bx, const 
 // energies (eV), in one kernel.  With kEnergy, one extra block (the last)
 // sums the structure energy in float64 (per-thread sums in ascending atom
 // order, then a fixed tree) while the others gather.
-constexpr int kBackThreads = 256, kBackLanes = 16, kBackAtoms = kBackThreads / kBackLanes;
+constexpr int kBackThreads = 256, kBackLanes = 32, kBackAtoms = kBackThreads / kBackLanes;
 
 template <bool kEnergy>
 __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const RowsView rows,
