@@ -3,15 +3,20 @@
 A step is one pass of the whole hot path on GPU-resident state, run by the
 native MD engine (nnp_md_run: the steps are enqueued in one go and the host
 waits once, at the end): integrator half steps, the on-device rebuild
-decision, neighbour list build (cell list), AEV, species networks, float64
-structure energy, AEV adjoint and force gather.
+decision, neighbour list build (cell list) when due, AEV, species networks,
+AEV adjoint, force gather and the float64 structure energy (summed on every
+step).
 
-Default workload: periodic box of 1500 rigid-geometry waters (4,500 atoms,
-1.0 g/cm^3, L = 35.54 A), FP32, velocity Verlet at dt = 0.5 fs from 300 K
-Maxwell-Boltzmann velocities, neighbour list rebuilt every step (no skin).
-``--config 5`` runs the 99,999-atom box (BF16 MLP, 0.5 A skin, rebuild
-every 20 steps) and ``--config 3`` the 23,000-atom organic box (energy and
-forces only, no dynamics).
+Default workload: the large periodic water box, 33,333 rigid-geometry waters
+(99,999 atoms, 1.0 g/cm^3, L = 99.905 A), velocity Verlet at dt = 0.5 fs
+from 300 K Maxwell-Boltzmann velocities, neighbour list with a 0.5 A skin
+rebuilt every 20 steps and earlier when the Verlet-list bound requires it.
+The headline value is the FP32 form (the paper's precision); the BF16-MLP
+form runs beside it.  ``--config 2`` runs the 4,500-atom box (no skin, list
+rebuilt every step) and ``--config 3`` the 23,000-atom organic box (energy
+and forces only, no dynamics, with both forms' errors against the FP64
+oracle).  ``--config 4`` is the serving form (``--serving-sweep`` sweeps the
+request rate).
 
 Prints one JSON line.  Inputs are synthetic and seeded; weights are random
 (Glorot-uniform, seed 123456).
@@ -28,7 +33,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_PEAK = {"hbm_GBs": 8000.0, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0}
-MLP_FLOP_PER_ATOM = None   # filled from the model widths
 
 
 def mlp_flops_per_atom(widths):
@@ -155,79 +159,101 @@ def load_traffic(path, stage, config, precision, nets=1):
     return e
 
 
-def cpu_baseline(w, spec, budget_s=12.0):
-    """The FP64 oracle on the same workload, on the host's cores."""
-    import oracle
+def host_cpu():
+    """(model name, logical CPUs available to this process)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        return max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
-        cores = 1
-    times = []
-    t_start = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s and len(times) >= 2:
-            break
-    t = float(np.median(times))
-    ref = oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec)
-    return {"value": w.n_atoms / t, "unit": "atom-steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": "%d full energy+forces evaluation(s) of the same %d-atom system (neighbour list, AEV, "
-                      "MLP, adjoint), median %.2f s each; numpy float64, BLAS threads = %d"
-                      % (len(times), w.n_atoms, t, cores)}, ref
+        return 1
 
 
-def precision_errors(models, w, ref):
-    """Errors of each precision form against the FP64 oracle on the
-    workload's starting configuration: per-atom energy (relative to
-    max(|E_i|, rms E), and absolute), structure energy (relative and
-    absolute), max and rms force (eV/A).  The benchmark model carries no
-    self energies, so its atomic energies are small (about 0.1 eV) and the
-    absolute errors are the ones to read."""
+def oracle_eval(w, spec):
+    import oracle
+    return oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec)
+
+
+def cpu_baseline(w, spec, single_thread=True):
+    """The FP64 oracle (never tuned for speed) on the same workload: one full
+    energy + forces evaluation (neighbour search, AEV, networks, adjoint) with
+    the host's BLAS threads, and one with a single thread.  Returns the
+    record and the oracle's result (the reference for the error table)."""
+    cpu_model, ncpu = host_cpu()
+    cores = blas_threads()
+    t0 = time.perf_counter()
+    ref = oracle_eval(w, spec)
+    t_all = time.perf_counter() - t0
+    rec = {"value": w.n_atoms / t_all, "unit": "atom-steps/s", "cores": int(cores), "kind": "oracle",
+           "sample": "one full energy+forces evaluation of the same %d-atom system (cell-binned neighbour search, "
+                     "AEV, MLP, adjoint) in %.1f s; numpy float64, BLAS threads = %d (only the network products "
+                     "are threaded)" % (w.n_atoms, t_all, cores),
+           "cpu_model": cpu_model, "nproc": ncpu}
+    if single_thread:
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                oracle_eval(w, spec)
+                t_one = time.perf_counter() - t0
+            rec["single_thread"] = {"value": w.n_atoms / t_one, "unit": "atom-steps/s", "cores": 1,
+                                    "seconds": t_one}
+        except ImportError:
+            pass
+    return rec, ref
+
+
+def error_row(e_mol, ea, F, ref, spec):
+    """Errors of one evaluation against the FP64 oracle: per-atom energy
+    relative to max(|E_i|, rms E) and absolute; structure energy relative to
+    its magnitude, to the self-energy-free scale sum_i |E_i - e_s| and
+    absolute; max and rms force (eV/A)."""
+    Er = ref["E_atom"]
+    rms = float(np.sqrt(np.mean(Er ** 2)))
+    se = np.asarray(spec.self_energy, dtype=np.float64)
+    dF = F - ref["F"]
+    dE = abs(float(e_mol) - ref["E_mol"][0])
+    return {"E_atom_rel": float(np.max(np.abs(ea - Er) / np.maximum(np.abs(Er), rms))),
+            "E_atom_max_abs_eV": float(np.max(np.abs(ea - Er))),
+            "E_mol_rel": dE / max(abs(ref["E_mol"][0]), 1e-30),
+            "E_mol_rel_net_scale": dE / max(float(np.sum(np.abs(Er - se[ref["species"]]))), 1e-30),
+            "E_mol_abs_eV": dE,
+            "F_max_abs": float(np.abs(dF).max()), "F_rms": float(np.sqrt(np.mean(dF ** 2))),
+            "F_ref_rms": float(np.sqrt(np.mean(ref["F"] ** 2)))}
+
+
+def precision_errors(models, w, ref, spec):
+    """Both forms against the FP64 oracle on the workload's starting
+    configuration, every atom."""
     import torch
     import paper_2405_01491_amd as nnp
     dev = torch.device("cuda", 0)
     pos = torch.from_numpy(w.pos).to(dev)
     sp = torch.from_numpy(w.species).to(dev)
+    ref = dict(ref, species=w.species.astype(np.int64))
     out = {}
-    Er = ref["E_atom"]
-    rms = float(np.sqrt(np.mean(Er ** 2)))
     for name, model in models.items():
         nl = nnp.nnp_neighbors(model, pos, None, 1, w.box, model.spec.rc_r)
         e, ea, F = nnp.nnp_energy_forces(model, pos, sp, None, 1, w.box, nl, e_atom=True)
-        ea = ea.cpu().numpy().astype(np.float64)
-        dF = F.cpu().numpy().astype(np.float64) - ref["F"]
-        dE = abs(float(e[0]) - ref["E_mol"][0])
-        out[name] = {"E_atom_rel": float(np.max(np.abs(ea - Er) / np.maximum(np.abs(Er), rms))),
-                     "E_atom_max_abs_eV": float(np.max(np.abs(ea - Er))),
-                     "E_mol_rel": dE / max(abs(ref["E_mol"][0]), 1e-30), "E_mol_abs_eV": dE,
-                     "F_max_abs": float(np.abs(dF).max()), "F_rms": float(np.sqrt(np.mean(dF ** 2)))}
+        out[name] = error_row(float(e[0]), ea.cpu().numpy().astype(np.float64),
+                              F.cpu().numpy().astype(np.float64), ref, spec)
     return out
-
-
-def md_form(spec, w, precision, integ, temperature, friction, skin, every, steps, warmup):
-    """Atom-steps/s of the same MD workload with another precision form."""
-    import torch
-    import paper_2405_01491_amd as nnp
-    from paper_2405_01491_amd import md as nmd
-    dev = torch.device("cuda", 0)
-    model = nnp.Model(spec, precision)
-    masses = synthetic_masses(w)
-    vel = torch.from_numpy(nmd.maxwell_boltzmann(masses, 300.0, seed=2024)).to(dev)
-    sim = nmd.MDEngine(model, torch.from_numpy(w.pos).to(dev), vel, torch.from_numpy(w.species).to(dev), masses,
-                       w.box, dt=0.5, integrator=integ, temperature=temperature, friction=friction, seed=2024,
-                       skin=skin, rebuild_every=every)
-    sim.run(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.run(steps)
-    torch.cuda.synchronize()
-    dt_s = time.perf_counter() - t0
-    info = sim.info()
-    return model, {"value": w.n_atoms * steps / dt_s, "ms_per_step": 1e3 * dt_s / steps,
-                   "rebuilds": info["rebuilds"], "dtype": "f32" if precision == "fp32" else "f32+bf16(mlp)"}
 
 
 def synthetic_masses(w):
@@ -235,20 +261,112 @@ def synthetic_masses(w):
     return synthetic.MASSES[w.species]
 
 
-def serving_bench(model, duration_s=5.0, warmup_s=1.0, rate=2000.0, pool=600, plain_sample=300, seed=1004):
-    """Open-loop Poisson stream of single-molecule requests through the
-    continuous-batching server; latency = time from the scheduled arrival to
-    the moment nnp_poll returns the result."""
+def make_engine(model, w, integ, temperature, friction, skin, every, log_every=0, log_capacity=0, dt=0.5,
+                seed=2024):
+    import torch
+    from paper_2405_01491_amd import md as nmd
+    dev = torch.device("cuda", 0)
+    masses = synthetic_masses(w)
+    vel = torch.from_numpy(nmd.maxwell_boltzmann(masses, 300.0, seed=seed)).to(dev)
+    return nmd.MDEngine(model, torch.from_numpy(w.pos).to(dev), vel, torch.from_numpy(w.species).to(dev), masses,
+                        w.box, dt=dt, integrator=integ, temperature=temperature, friction=friction, seed=seed,
+                        skin=skin, rebuild_every=every, log_every=log_every, log_capacity=log_capacity)
+
+
+def md_form(spec, w, precision, integ, temperature, friction, skin, every, steps, warmup):
+    """Atom-steps/s of the same MD workload with another precision form."""
+    import torch
+    import paper_2405_01491_amd as nnp
+    model = nnp.Model(spec, precision)
+    sim = make_engine(model, w, integ, temperature, friction, skin, every)
+    sim.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    info = sim.info()
+    sim.close()
+    return model, {"value": w.n_atoms * steps / dt_s, "ms_per_step": 1e3 * dt_s / steps,
+                   "rebuilds_total": info["rebuilds"], "early_rebuilds": info["early_rebuilds"],
+                   "dtype": "f32" if precision == "fp32" else "f32+bf16(mlp)"}
+
+
+def nve_drift(spec, n_mol=216, dt=0.1, steps=10000, log_every=100):
+    """The energy-conservation study of the paper's precision comparison, on a
+    short run: NVE velocity Verlet of a 216-water box (648 atoms, 1.0 g/cm^3)
+    at dt = 0.1 fs from 300 K, list rebuilt every step, for each precision
+    form.  Reports the total energy's largest excursion and its standard
+    deviation over the run, in eV and relative to |E_tot(0)| and to the mean
+    kinetic energy."""
     import torch
     import synthetic
     import paper_2405_01491_amd as nnp
+    w = synthetic.water_box(n_mol, seed=1216)
+    out = {"workload": "%d waters (%d atoms), L = %.3f A, NVE dt = %g fs, %d steps (%.1f ps), energy logged every "
+                       "%d steps" % (n_mol, w.n_atoms, float(w.box[0]), dt, steps, steps * dt * 1e-3, log_every)}
+    for precision in ("fp32", "bf16"):
+        model = nnp.Model(spec, precision)
+        eng = make_engine(model, w, "nve", 300.0, 0.0, 0.0, 1, log_every=log_every,
+                          log_capacity=steps // log_every + 1, dt=dt, seed=1216)
+        _, v0, _, ep0 = eng.state()
+        m = torch.from_numpy(synthetic_masses(w)).double().to(v0.device)
+        from paper_2405_01491_amd import md as nmd
+        e_start = float(ep0[0]) + float(0.5 * (m[:, None] * v0.double() ** 2).sum() / nmd.ACC_UNIT)
+        t0 = time.perf_counter()
+        eng.run(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rows = eng.log()
+        eng.close()
+        tot = np.concatenate([[e_start], rows.sum(1)])
+        e0 = e_start
+        ke = float(rows[:, 1].mean())
+        out[precision] = {"E_tot0_eV": float(e0), "max_abs_dev_eV": float(np.abs(tot - e0).max()),
+                          "std_eV": float(np.std(tot)), "max_abs_dev_rel_E_tot0": float(np.abs(tot - e0).max() / abs(e0)),
+                          "max_abs_dev_rel_KE": float(np.abs(tot - e0).max() / ke), "mean_KE_eV": ke,
+                          "drift_eV_per_ps": float(np.polyfit(np.arange(len(tot)) * log_every * dt * 1e-3, tot, 1)[0]),
+                          "last_minus_first_eV": float(tot[-1] - e0),
+                          "ms_per_step": 1e3 * wall / steps}
+    return out
+
+
+def cluster_latency(spec, reps=200):
+    """Latency of one plain-path call on the 72-atom water cluster (24
+    waters, open): neighbour list, energy and forces, results on the host."""
+    import torch
+    import synthetic
+    import paper_2405_01491_amd as nnp
+    dev = torch.device("cuda", 0)
+    w = synthetic.workload(1)
+    model = nnp.Model(spec, "fp32")
+    pos = torch.from_numpy(w.pos).to(dev)
+    sp = torch.from_numpy(w.species).to(dev)
+    ts = []
+    for k in range(reps + 20):
+        t0 = time.perf_counter()
+        nl = nnp.nnp_neighbors(model, pos, None, 1, None, spec.rc_r)
+        e, _, f = nnp.nnp_energy_forces(model, pos, sp, None, 1, None, nl)
+        e.cpu()
+        f.cpu()
+        if k >= 20:
+            ts.append(time.perf_counter() - t0)
+    ts = np.array(ts) * 1e3
+    return {"workload": "water_cluster_72: 24 waters, open, FP32; nnp_neighbors + nnp_energy_forces + copy to host",
+            "p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99)), "calls": reps}
+
+
+def serving_run(model, mols, rate, duration_s, warmup_s, seed, max_inflight=4):
+    """Open-loop Poisson stream of single-molecule requests through the
+    continuous-batching server; latency = time from the scheduled arrival to
+    the moment nnp_poll returns the result."""
     from paper_2405_01491_amd.server import Server, nnp_poll, nnp_submit
     rng = np.random.default_rng(seed)
-    mols = [synthetic.serving_molecule(rng) for _ in range(pool)]
+    pool = len(mols)
     n_req = int((duration_s + warmup_s) * rate)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     which = rng.integers(0, pool, size=n_req)
-    srv = Server(model, arena_bytes=256 << 20, max_slots=8192, max_inflight=4)
+    srv = Server(model, arena_bytes=256 << 20, max_slots=8192, max_inflight=max_inflight)
     lat = np.full(n_req, np.nan)
     pending = {}
     k = 0
@@ -275,12 +393,26 @@ def serving_bench(model, duration_s=5.0, warmup_s=1.0, rate=2000.0, pool=600, pl
     sel = arrivals >= warmup_s
     L = lat[sel] * 1e3
     atoms = np.array([len(mols[m][1]) for m in which])
-    meas_t = arrivals[-1] - warmup_s
-    # the same kind of requests one at a time on the plain path (closed loop)
+    # throughput over the measured window: requests done / time from the first
+    # measured arrival to the last completion
+    t_first = arrivals[sel][0] if sel.any() else 0.0
+    t_last = float(np.nanmax(arrivals[sel] + lat[sel])) if sel.any() else wall
+    span = max(t_last - t_first, 1e-9)
+    return {"rate_req_s": rate, "p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
+            "max_ms": float(np.max(L)), "requests": int(sel.sum()),
+            "throughput_req_s": float(sel.sum() / span), "atoms_per_s": float(atoms[sel].sum() / span),
+            "launches": st["launches"], "mean_requests_per_launch": st["batched_requests"] / max(1, st["launches"]),
+            "wall_s": wall}
+
+
+def plain_one_at_a_time(model, mols, which):
+    """The same requests one at a time on the plain path (closed loop)."""
+    import torch
+    import paper_2405_01491_amd as nnp
     dev = torch.device("cuda", 0)
     plain = []
-    for j in range(plain_sample):
-        p, s = mols[which[j]]
+    for j in which:
+        p, s = mols[j]
         t1 = time.perf_counter()
         pk = torch.from_numpy(p).to(dev)
         sk = torch.from_numpy(s).to(dev)
@@ -290,19 +422,67 @@ def serving_bench(model, duration_s=5.0, warmup_s=1.0, rate=2000.0, pool=600, pl
         f.cpu()
         plain.append(time.perf_counter() - t1)
     plain = np.array(plain[10:]) * 1e3
-    return {
-        "p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
-        "max_ms": float(np.max(L)), "requests": int(sel.sum()), "rate_req_s": rate,
-        "throughput_req_s": float(sel.sum() / meas_t), "atoms_per_s": float(atoms[sel].sum() / meas_t),
-        "mean_atoms_per_request": float(atoms.mean()),
-        "launches": st["launches"], "mean_requests_per_launch": st["batched_requests"] / max(1, st["launches"]),
-        "wall_s": wall,
-        "plain_one_at_a_time": {"p50_ms": float(np.percentile(plain, 50)), "p99_ms": float(np.percentile(plain, 99)),
-                                "max_throughput_req_s": float(1e3 / np.mean(plain))},
-        "workload": "Poisson %.0f req/s, %.0f s after %.0f s warm-up; molecules of 8-150 atoms (log-uniform), "
-                    "chain-grown bonded-like geometries (bonds 0.95-1.6 A), H/C/O/N/S/F/Cl mix, open boundaries; "
-                    "each request drawn from a pool of %d generated molecules" % (rate, duration_s, warmup_s, pool),
-    }
+    return {"p50_ms": float(np.percentile(plain, 50)), "p99_ms": float(np.percentile(plain, 99)),
+            "max_throughput_req_s": float(1e3 / np.mean(plain))}
+
+
+def serving_bench(model, duration_s=5.0, warmup_s=1.0, rate=2000.0, pool=600, plain_sample=300, seed=1004,
+                  sweep=None):
+    import synthetic
+    rng = np.random.default_rng(seed)
+    mols = [synthetic.serving_molecule(rng) for _ in range(pool)]
+    main = serving_run(model, mols, rate, duration_s, warmup_s, seed)
+    which = np.random.default_rng(seed + 1).integers(0, pool, size=plain_sample)
+    main["mean_atoms_per_request"] = float(np.mean([len(mols[j][1]) for j in range(pool)]))
+    main["plain_one_at_a_time"] = plain_one_at_a_time(model, mols, which)
+    main["workload"] = ("Poisson %.0f req/s, %.0f s after %.0f s warm-up; molecules of 8-150 atoms (log-uniform), "
+                        "chain-grown bonded-like geometries (bonds 0.95-1.6 A), H/C/O/N/S/F/Cl mix, open "
+                        "boundaries; each request drawn from a pool of %d generated molecules"
+                        % (rate, duration_s, warmup_s, pool))
+    if sweep:
+        main["sweep"] = [serving_run(model, mols, r, duration_s, warmup_s, seed + 7 + k)
+                         for k, r in enumerate(sweep)]
+    return main
+
+
+METRIC = "energy+force atom-steps/s at 1 MI355X (FP32 vs BF16-MLP); p50/p99 request latency"
+
+
+def roofline_of(dom, stages, w, spec, precision, model, nets, n_pairs, traffic_path, config):
+    ms_dom, cnt_dom = stages[dom]
+    avg_ms = ms_dom / max(cnt_dom, 1)
+    N = w.n_atoms
+    fwd, adj = mlp_flops_per_atom(spec.widths)
+    if dom == "mlp":
+        flop, dense_flop, feats = (fwd + adj) * nets * N, (fwd + adj) * nets * N, float(spec.aev_dim)
+        if model.fused_mlp:
+            flop, dense_flop, feats = mlp_useful_flops(w, spec, precision, nets)
+        peak = MI355X_PEAK["bf16_TFLOPs" if precision == "bf16" else "fp32_TFLOPs"]
+        achieved = flop / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "stage": "mlp (per-species networks, forward + adjoint)",
+                "algorithmic_per_launch": "%.4g FLOP" % flop,
+                "dense_equivalent_per_launch": "%.4g FLOP (every feature; the kernel skips feature blocks that "
+                                               "are zero for a whole tile)" % dense_flop,
+                "active_features_per_atom": round(feats, 1)}
+    else:
+        Fg = None
+        if dom == "aev_adjoint":
+            Fg = float(np.mean([active_features(int(m), spec.n_species) for m in species_masks(w, spec)]))
+        byt = stage_bytes(dom, N, n_pairs, precision, spec.aev_dim, Fg)
+        achieved = byt / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": MI355X_PEAK["hbm_GBs"], "unit": "GB/s",
+                "frac": achieved / MI355X_PEAK["hbm_GBs"], "traffic": None, "stage": dom,
+                "algorithmic_per_launch": "%.4g B" % byt}
+    roof["avg_launch_ms"] = avg_ms
+    roof["kernel"] = STAGE_KERNEL.get((dom, model.fused_mlp), dom)
+    if dom == "mlp" and nets > 1:
+        roof["kernel"] = "k_mlp_fused (per network, to d1) + k_ens_adj1 (first-layer adjoint over networks)"
+    tr = load_traffic(traffic_path, dom, config, precision, nets)
+    if tr is not None:
+        roof["traffic"] = tr["bytes_per_launch"]
+        roof["traffic_source"] = tr["profile"]
+    return roof
 
 
 def main():
@@ -310,10 +490,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=5, choices=[2, 3, 4, 5])
     ap.add_argument("--serving-seconds", type=float, default=5.0)
-    ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
+    ap.add_argument("--serving-sweep", default=None,
+                    help="comma-separated request rates (req/s) to sweep in the serving form")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
+                    help="the headline form (the other one runs beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed MD forms (no serving, cluster latency or NVE drift study)")
     ap.add_argument("--integrator", default="nve", choices=["nve", "langevin"],
                     help="nve: velocity Verlet (the configured workloads); langevin: BAOAB as in the paper's "
                          "benchmarks")
@@ -350,23 +535,25 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     spec = synthetic.ani2x_like_spec() if args.nets == 1 else synthetic.ani2x_like_ensemble(n_nets=args.nets)
+    sweep = [float(r) for r in args.serving_sweep.split(",")] if args.serving_sweep else None
     if args.config == 4:
-        model = nnp.Model(spec, args.precision or "fp32")
-        sv = serving_bench(model, duration_s=args.serving_seconds)
+        model = nnp.Model(spec, args.precision)
+        sv = serving_bench(model, duration_s=args.serving_seconds, sweep=sweep)
         print(json.dumps({
-            "metric": "energy+force atom-steps/s at 1 MI355X (FP32 vs BF16-MLP); p50/p99 request latency",
-            "value": sv["atoms_per_s"], "unit": "atom-steps/s", "n_gpus": 1, "steps": sv["requests"], "warmup": 0,
-            "ms_per_step": sv["p50_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32", "data": "synthetic", "config": {"workload": sv["workload"]}, "serving": sv}))
+            "metric": METRIC, "value": sv["atoms_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
+            "steps": sv["requests"], "warmup": 0, "ms_per_step": sv["p50_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f32+bf16(mlp)",
+            "data": "synthetic", "config": {"workload": sv["workload"]}, "serving": sv}))
         return
     w = synthetic.workload(args.config)
-    precision = args.precision or ("bf16" if args.config == 5 else "fp32")
+    precision = args.precision
+    other = "bf16" if precision == "fp32" else "fp32"
     model = nnp.Model(spec, precision)
     pos = torch.from_numpy(w.pos).to(dev)
     sp = torch.from_numpy(w.species).to(dev)
-    masses = synthetic.MASSES[w.species]
-    fwd, adj = mlp_flops_per_atom(spec.widths)
-    fwd, adj = fwd * args.nets, adj * args.nets
+    integ = args.integrator
+    dyn = ("velocity Verlet" if integ == "nve" else
+           "BAOAB Langevin %g K, friction %g/ps" % (args.temperature, args.friction))
 
     if args.config == 3:
         skin, every = 0.0, 1
@@ -378,10 +565,6 @@ def main():
         workload = ("organic_box_23000: 23,000 atoms H/C/O/N/S/F/Cl 50/25/12/8/3/1/1 %%, 0.1 atoms/A^3, "
                     "L = 61.27 A, periodic; energy + forces per step (list built once), %s MLP" % precision)
     else:
-        vel = torch.from_numpy(nmd.maxwell_boltzmann(masses, 300.0, seed=2024)).to(dev)
-        integ = args.integrator
-        dyn = ("velocity Verlet" if integ == "nve" else
-               "BAOAB Langevin %g K, friction %g/ps" % (args.temperature, args.friction))
         if args.config == 2:
             skin, every = 0.0, 1
             workload = ("water_box_4500: 1500 rigid waters, 1.0 g/cm^3, L = 35.54 A, periodic; %s "
@@ -389,10 +572,9 @@ def main():
         else:
             skin, every = 0.5, 20
             workload = ("water_box_99999: 33,333 rigid waters, 1.0 g/cm^3, L = 99.905 A, periodic; %s "
-                        "dt = 0.5 fs from 300 K, 0.5 A skin, rebuild every 20 steps; %s MLP" % (dyn, precision))
-        sim = nmd.MDEngine(model, pos, vel, sp, masses, w.box, dt=0.5, integrator=integ,
-                           temperature=args.temperature, friction=args.friction, seed=2024, skin=skin,
-                           rebuild_every=every)
+                        "dt = 0.5 fs from 300 K, 0.5 A skin, rebuild every 20 steps or when the two largest "
+                        "displacements exceed the skin; %s MLP" % (dyn, precision))
+        sim = make_engine(model, w, integ, args.temperature, args.friction, skin, every)
 
     # warm-up with every stage timed (the stage breakdown and the choice of the
     # dominant stage), then the timed run with events around that stage only
@@ -408,6 +590,8 @@ def main():
     ranked = {k: ms for k, (ms, cnt) in warm.items() if cnt > 0}
     dom = max(ranked, key=ranked.get) if ranked else "mlp"
     nmd.profile_enable(model, True, stages=[dom])
+    if args.config != 3:
+        info0 = sim.info()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if args.config == 3:
@@ -426,47 +610,15 @@ def main():
         info = sim.info()
         x_now = sim.state()[0]
         n_pairs = int(nnp.nnp_neighbors(model, x_now, None, 1, w.box, info["r_list"]).c.n_pairs)
+        sim.close()
     dt_s = t1 - t0
     N = w.n_atoms
     value = N * args.steps / dt_s
-
-    # roofline of the dominant stage (HIP events recorded on the stream the kernels run on)
-    ms_dom, cnt_dom = stages[dom]
-    avg_ms = ms_dom / max(cnt_dom, 1)
-    if dom == "mlp":
-        flop, dense_flop, feats = (fwd + adj) * N, (fwd + adj) * N, float(spec.aev_dim)
-        if model.fused_mlp:
-            flop, dense_flop, feats = mlp_useful_flops(w, spec, precision, args.nets)
-        peak = MI355X_PEAK["bf16_TFLOPs" if precision == "bf16" else "fp32_TFLOPs"]
-        achieved = flop / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "stage": "mlp (per-species GEMM chain, forward + adjoint)",
-                "algorithmic_per_launch": "%.4g FLOP" % flop,
-                "dense_equivalent_per_launch": "%.4g FLOP (every feature; the kernel skips feature blocks that "
-                                               "are zero for a whole tile)" % dense_flop,
-                "active_features_per_atom": round(feats, 1)}
-    else:
-        Fg = None
-        if dom == "aev_adjoint":
-            Fg = float(np.mean([active_features(int(m), spec.n_species) for m in species_masks(w, spec)]))
-        byt = stage_bytes(dom, N, n_pairs, precision, spec.aev_dim, Fg)
-        achieved = byt / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": MI355X_PEAK["hbm_GBs"], "unit": "GB/s",
-                "frac": achieved / MI355X_PEAK["hbm_GBs"], "traffic": None, "stage": dom,
-                "algorithmic_per_launch": "%.4g B" % byt}
-    roof["avg_launch_ms"] = avg_ms
-    roof["kernel"] = STAGE_KERNEL.get((dom, model.fused_mlp), dom)
-    if dom == "mlp" and args.nets > 1:
-        roof["kernel"] = "k_mlp_fused (per network, to d1) + k_ens_adj1 (first-layer adjoint over networks)"
-    tr = load_traffic(args.traffic, dom, args.config, precision, args.nets)
-    if tr is not None:
-        roof["traffic"] = tr["bytes_per_launch"]
-        roof["traffic_source"] = tr["profile"]
-
+    roof = roofline_of(dom, stages, w, spec, precision, model, args.nets, n_pairs, args.traffic, args.config)
     result = {
-        "metric": "energy+force atom-steps/s at 1 MI355X (FP32 vs BF16-MLP); p50/p99 request latency",
-        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt_s / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt_s / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if precision == "fp32" else "f32+bf16(mlp)", "data": "synthetic",
         "config": {"workload": workload + ("; ensemble of %d networks" % args.nets if args.nets > 1 else ""),
                    "n_atoms": N, "precision": precision, "skin_A": skin, "rebuild_every": every,
@@ -475,23 +627,37 @@ def main():
         "roofline": roof,
     }
     if args.config != 3:
-        result["config"]["integrator"] = args.integrator
-        result["config"]["rebuilds"] = info["rebuilds"]
-        result["config"]["early_rebuilds"] = info["early_rebuilds"]
+        result["config"]["integrator"] = integ
+        result["config"]["rebuilds_in_timed_steps"] = info["rebuilds"] - info0["rebuilds"]
+        result["config"]["early_rebuilds_in_timed_steps"] = info["early_rebuilds"] - info0["early_rebuilds"]
     models = {precision: model}
     if args.config != 3:
-        # the other precision form on the same workload, beside the primary one
-        other = "bf16" if precision == "fp32" else "fp32"
-        om, form = md_form(spec, w, other, args.integrator, args.temperature, args.friction, skin, every,
-                           args.steps, args.warmup)
-        result["forms"] = {precision: {"value": value, "ms_per_step": result["ms_per_step"],
-                                       "dtype": result["dtype"]}, other: form}
-        models[other] = om
-    if args.config == 2 and args.serving_seconds > 0:
-        result["serving"] = serving_bench(model, duration_s=args.serving_seconds)
+        om, form = md_form(spec, w, other, integ, args.temperature, args.friction, skin, every, args.steps,
+                           args.warmup)
+    else:
+        om = nnp.Model(spec, other)
+        nl2 = nnp.nnp_neighbors(om, pos, None, 1, w.box, spec.rc_r)
+        out2 = {}
+        for _ in range(args.warmup):
+            nnp.nnp_energy_forces(om, pos, sp, None, 1, w.box, nl2, out=out2)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            nnp.nnp_energy_forces(om, pos, sp, None, 1, w.box, nl2, out=out2)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - ta) / args.steps
+        form = {"value": N / tb, "ms_per_step": 1e3 * tb, "dtype": "f32" if other == "fp32" else "f32+bf16(mlp)"}
+    result["forms"] = {precision: {"value": value, "ms_per_step": result["ms_per_step"], "dtype": result["dtype"]},
+                       other: form}
+    models[other] = om
+    if not args.no_extras and args.config in (2, 5):
+        if args.serving_seconds > 0:
+            result["serving"] = serving_bench(nnp.Model(spec, "fp32"), duration_s=args.serving_seconds, sweep=sweep)
+        result["latency_cluster_72"] = cluster_latency(spec)
+        result["nve_drift"] = nve_drift(spec)
     if not args.no_cpu_baseline:
         result["cpu_baseline"], ref = cpu_baseline(w, spec)
-        result["precision_vs_fp64_oracle"] = precision_errors(models, w, ref)
+        result["precision_vs_fp64_oracle"] = precision_errors(models, w, ref, spec)
     print(json.dumps(result))
 
 

@@ -292,9 +292,14 @@ nnp_status nnp_md_wrap(int32_t n_atoms, float* pos, const float* box_host, void*
  * u_k = ((w_k >> 40) + 1/2) 2^-24, xi = (rho0 cos 2pi u1, rho0 sin 2pi u1,
  * rho2 cos 2pi u3), rho_k = sqrt(-2 ln u_k).
  * The list (cutoff = radial cutoff + skin) is rebuilt, positions wrapped into
- * the box, every rebuild_every steps, and earlier as soon as an atom has
- * moved more than trigger * skin / 2 since the last build (skin > 0,
- * trigger > 0); the decision is taken on the device. */
+ * the box, every rebuild_every steps, and earlier as soon as the two largest
+ * displacements since the last build sum to more than trigger * skin (the
+ * Verlet-list bound: a pair outside the list was at least cutoff + skin
+ * apart at the build and has since come closer by at most the sum of its
+ * two atoms' displacements); the decision is taken on the device.  With a
+ * skin, 0 < trigger <= 1 is required (1 is the exact bound); without one
+ * (skin = 0), rebuild_every must be 1.  Other settings could let a pair
+ * come within the cutoff unlisted and are rejected (NNP_E_ARG). */
 typedef enum { NNP_MD_NVE = 0, NNP_MD_LANGEVIN = 1 } nnp_md_integrator;
 
 typedef struct {
@@ -305,7 +310,7 @@ typedef struct {
     uint64_t seed;            /* key of the noise generator (Langevin)            */
     float skin;               /* A, added to the radial cutoff for the list       */
     int32_t rebuild_every;    /* >= 1                                             */
-    float trigger;            /* early rebuild threshold in units of skin / 2     */
+    float trigger;            /* early rebuild when d1 + d2 > trigger * skin      */
     int32_t log_every;        /* > 0: record (E_pot, E_kin) every log_every steps */
     int32_t log_capacity;     /* rows kept (later rows are dropped)               */
 } nnp_md_params;
@@ -340,8 +345,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n_atoms, const float* pos, co
 nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream);
 /* Copy the current state into caller device buffers (any may be NULL):
  * pos, vel, forces float32 [n][3], e_pot float64 [1] (the potential energy
- * of the current positions: a run sums it on its last step and on logged
- * steps only).  Asynchronous. */
+ * of the current positions: every step sums it).  Asynchronous. */
 nnp_status nnp_md_get(nnp_md* md, float* pos, float* vel, float* forces, double* e_pot,
                       void* stream);
 /* Copy up to max_rows logged rows {E_pot, E_kin} (eV, float64) to host

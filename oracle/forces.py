@@ -33,7 +33,7 @@ import numpy as np
 from .aev import AEVLayout, aev as aev_fn, angular_factors, angular_triplets, f64, pair_geometry, \
     switch, switch_deriv
 from .mlp import mlp_energies_per_net, mlp_energy_and_grad
-from .neighbors import neighbor_list
+from .neighbors import neighbor_list, neighbor_list_cells
 
 
 def edge_gradients(pos, species, box, nl, spec, g, centers=None, chunk=1 << 18, geometry=None,
@@ -152,7 +152,10 @@ def energy_forces(pos, species, mol, n_mol, box, spec, r_list=None, precision="f
         r_list = spec.rc_r
     N = pos.shape[0]
     if nl is None:
-        nl = neighbor_list(pos, mol, box, r_list)
+        # the O(N^2) scan of the definition for small systems, the cell-binned
+        # search (pinned to the same edge set) beyond
+        search = neighbor_list if N <= 4096 else neighbor_list_cells
+        nl = search(pos, mol, box, r_list)
     A = aev_fn(pos, species, box, nl, spec)
     E_atom, g = mlp_energy_and_grad(A, species, spec, precision, need_grad=need_forces)
     mol = np.zeros(N, dtype=np.int64) if mol is None else np.asarray(mol)

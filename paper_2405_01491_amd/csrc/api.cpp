@@ -272,6 +272,8 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
                 ein.E_at = W.E_at;
                 for (int k = 0; k < kMaxSpecies; ++k) ein.se[k] = m->self_energy[k];
                 ein.e_pot = e_mol;
+                ein.part = md->e_part;
+                ein.ticket = md->e_ticket;
                 e = md_launch_back(n, rows, W.G, forces, *md, &ein, s);
             } else {
                 e = launch_force_gather(n, rows, W.G, forces, s);

@@ -3,42 +3,23 @@
 // With G_ij = dE_i/dv_ij and v_ij = x_j + n L - x_i, the force on atom a is
 //   F_a = -dE/dx_a = sum_{j in N(a)} (G_aj - G_ja),
 // where G_ja sits at rev[p] of the pair a -> j (the list is symmetric).  Each
-// atom's sum runs over its own row in a fixed order (16 lanes per atom, then
-// a fixed butterfly), so no atomics are involved (Sec. 2.4: forces as the
-// gradient of the total energy).
+// atom's sum runs over its own row in a fixed order (gather_row_force), so no
+// atomics are involved (Sec. 2.4: forces as the gradient of the total energy).
 #include "nnp_internal.hpp"
 
 namespace nnp {
 namespace {
 
-constexpr int kLanesPerAtom = 16;
-
 __global__ __launch_bounds__(256) void k_force_gather(int n, const RowsView rows,
                                                      const int32_t* __restrict__ rev, const float4* __restrict__ G,
                                                      float* __restrict__ F) {
-    const int a = (blockIdx.x * blockDim.x + threadIdx.x) / kLanesPerAtom;
-    const int sub = threadIdx.x % kLanesPerAtom;
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    if (a < n) {
-        const int b = rows.begin(a), e = rows.end(a);
-        for (int p = b + sub; p < e; p += kLanesPerAtom) {
-            const int q = rev[p];
-            const float4 gp = G[p], gq = G[q];
-            fx += gp.x - gq.x;
-            fy += gp.y - gq.y;
-            fz += gp.z - gq.z;
-        }
-    }
-#pragma unroll
-    for (int m = kLanesPerAtom / 2; m >= 1; m >>= 1) {
-        fx += shfl_xor(fx, m);
-        fy += shfl_xor(fy, m);
-        fz += shfl_xor(fz, m);
-    }
+    const int a = (blockIdx.x * blockDim.x + threadIdx.x) / kGatherLanes;
+    const int sub = threadIdx.x % kGatherLanes;
+    const float3 f = gather_row_force(rows, rev, G, a, n, sub);
     if (a < n && sub == 0) {
-        F[3 * a] = fx;
-        F[3 * a + 1] = fy;
-        F[3 * a + 2] = fz;
+        F[3 * a] = f.x;
+        F[3 * a + 1] = f.y;
+        F[3 * a + 2] = f.z;
     }
 }
 
@@ -61,6 +42,7 @@ __global__ void k_kick_drift(int n, float* pos, float* vel, const float* F, cons
         }
     }
     if (ref) {
+        d2 = d2 <= INFINITY ? d2 : INFINITY;   // a non-finite displacement must trigger a rebuild
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
         if (lane_id() == 0 && d2 > 0.f) atomicMax((unsigned*)max_d2, __float_as_uint(d2));
@@ -156,7 +138,7 @@ hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t*
 hipError_t launch_force_gather(int n, const RowsView& rows, const float4* G, float* F,
                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_force_gather<<<ceil_div((long)n * kLanesPerAtom, 256), 256, 0, s>>>(n, rows, rows.rev, G, F);
+    k_force_gather<<<ceil_div((long)n * kGatherLanes, 256), 256, 0, s>>>(n, rows, rows.rev, G, F);
     return hipGetLastError();
 }
 

@@ -29,26 +29,29 @@ namespace {
 
 constexpr int kFirstThreads = 256;
 
-// First part of the step; the largest squared displacement of each block
-// goes to d2_part[block] (one write per block, no contended atomics).
+// First part of the step; the two largest squared displacements of each
+// block go to d2_part[2 block], d2_part[2 block + 1] (one write per block, no
+// contended atomics).
 template <bool kLangevin>
 __global__ __launch_bounds__(kFirstThreads) void k_md_first(int n, float* __restrict__ pos, float* __restrict__ vel,
                                                            const float* __restrict__ F,
                                                            const float* __restrict__ inv_mass, const MdStepConst c,
                                                            uint64_t step, const float* __restrict__ ref,
                                                            float* __restrict__ d2_part) {
-    __shared__ float s_max[kFirstThreads / kWave];
+    __shared__ float s_m[kFirstThreads / kWave][2];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    float d2 = 0.f;
-    if (a < n) d2 = md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref);
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
-    if (lane_id() == 0) s_max[threadIdx.x / kWave] = d2;
+    float m1 = 0.f, m2 = 0.f;
+    if (a < n) m1 = md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref);
+    top2_wave(m1, m2);
+    if (lane_id() == 0) {
+        s_m[threadIdx.x / kWave][0] = m1;
+        s_m[threadIdx.x / kWave][1] = m2;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        float mx = s_max[0];
-        for (int q = 1; q < kFirstThreads / kWave; ++q) mx = fmaxf(mx, s_max[q]);
-        d2_part[blockIdx.x] = mx;
+        for (int q = 1; q < kFirstThreads / kWave; ++q) top2_merge(m1, m2, s_m[q][0], s_m[q][1]);
+        d2_part[2 * blockIdx.x] = m1;
+        d2_part[2 * blockIdx.x + 1] = m2;
     }
 }
 
@@ -56,19 +59,21 @@ __global__ __launch_bounds__(kFirstThreads) void k_md_first(int n, float* __rest
 // systems; small ones decide in the fused front kernel of the neighbour
 // builder).  One block.
 __global__ __launch_bounds__(256) void k_md_decide(MdState* st, const float* __restrict__ d2_part, int n_parts,
-                                                   int rebuild_every, float trigger2) {
-    __shared__ float s_max[256 / kWave];
+                                                   int rebuild_every, float trig_len) {
+    __shared__ float s_m[256 / kWave][2];
     MdState cur{};
     if (threadIdx.x == 0) cur = *st;
-    float mx = 0.f;
-    for (int q = threadIdx.x; q < n_parts; q += 256) mx = fmaxf(mx, d2_part[q]);
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, shfl_xor(mx, m));
-    if (lane_id() == 0) s_max[threadIdx.x / kWave] = mx;
+    float m1 = 0.f, m2 = 0.f;
+    for (int q = threadIdx.x; q < n_parts; q += 256) top2_merge(m1, m2, d2_part[2 * q], d2_part[2 * q + 1]);
+    top2_wave(m1, m2);
+    if (lane_id() == 0) {
+        s_m[threadIdx.x / kWave][0] = m1;
+        s_m[threadIdx.x / kWave][1] = m2;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 1; q < 256 / kWave; ++q) mx = fmaxf(mx, s_max[q]);
-        md_decide(st, cur, mx, rebuild_every, trigger2);
+        for (int q = 1; q < 256 / kWave; ++q) top2_merge(m1, m2, s_m[q][0], s_m[q][1]);
+        md_decide(st, cur, m1, m2, rebuild_every, trig_len);
     }
 }
 
@@ -90,55 +95,74 @@ __global__ void k_md_wrap_ref(int n, float* pos, float* ref, BoxConst bx, const 
     }
 }
 
-// Force gather (16 lanes per atom over its row, F_a = sum_j G_aj - G_ja, as
-// in k_force_gather), the last half kick and per-block float64 kinetic
-// energies (eV), in one kernel.  With kEnergy, one extra block (the last)
-// sums the structure energy in float64 (per-thread sums in ascending atom
-// order, then a fixed tree) while the others gather.
-constexpr int kBackThreads = 256, kBackLanes = 32, kBackAtoms = kBackThreads / kBackLanes;
+// Force gather (gather_row_force: the same per-atom sum as the plain path's
+// k_force_gather), the last half kick and per-block float64 kinetic energies
+// (eV), in one kernel.  With kEnergy the structure energy is summed in
+// float64 by the first ne = ceil(n / kEChunk) blocks, which are dispatched
+// before the gather blocks: block k sums the atoms of chunk k (per-thread
+// sums in ascending atom order, then a fixed tree) into part[k]; the block
+// that finishes last (an integer ticket) adds the parts in ascending order.
+// The order of every addition is fixed, so the energy does not depend on
+// scheduling.
+constexpr int kBackThreads = 256, kBackAtoms = kBackThreads / kGatherLanes;
+constexpr int kEChunk = 4096;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = kBackThreads / 2; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    return red[0];
+}
 
 template <bool kEnergy>
-__global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const RowsView rows,
+__global__ __launch_bounds__(kBackThreads) void k_md_back(int n, int ne, const RowsView rows,
                                                          const int32_t* __restrict__ rev, const float4* __restrict__ G,
                                                          float* __restrict__ F, float* __restrict__ vel,
                                                          const float* __restrict__ inv_mass, float dt, double* ke_part,
                                                          const MdEnergyIn E) {
     __shared__ double red[kBackThreads];
-    if (kEnergy && (int)blockIdx.x == (int)gridDim.x - 1) {
-        double acc = 0.0;
-        for (int a = threadIdx.x; a < n; a += kBackThreads)
-            if (E.prow[a] >= 0) acc += (double)E.E_at[a] + E.se[E.species[a]];
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int st = kBackThreads / 2; st >= 1; st >>= 1) {
-            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __shared__ int last;
+    int blk = blockIdx.x;
+    if (kEnergy) {
+        if (blk < ne) {
+            const int base = blk * kEChunk;
+            const int stop = min(n, base + kEChunk);
+            double acc = 0.0;
+            for (int a = base + threadIdx.x; a < stop; a += kBackThreads)
+                if (E.prow[a] >= 0) acc += (double)E.E_at[a] + E.se[E.species[a]];
+            const double tot = block_sum(acc, red);
+            if (ne == 1) {
+                if (threadIdx.x == 0) *E.e_pot = tot;
+                return;
+            }
+            if (threadIdx.x == 0) {
+                E.part[blk] = tot;
+                __threadfence();                                   // the part before the ticket
+                last = atomicAdd(E.ticket, 1u) == (unsigned)(ne - 1);
+            }
             __syncthreads();
+            if (!last) return;
+            __threadfence();                                       // every part after the last ticket
+            if (threadIdx.x == 0) {
+                double e = 0.0;
+                for (int q = 0; q < ne; ++q) e += __hip_atomic_load(&E.part[q], __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_AGENT);
+                *E.e_pot = e;
+                *E.ticket = 0u;                                    // ready for the next step
+            }
+            return;
         }
-        if (threadIdx.x == 0) *E.e_pot = red[0];
-        return;
+        blk -= ne;
     }
-    const int a = blockIdx.x * kBackAtoms + threadIdx.x / kBackLanes;
-    const int sub = threadIdx.x % kBackLanes;
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    if (a < n) {
-        const int b = rows.begin(a), e = rows.end(a);
-        for (int p = b + sub; p < e; p += kBackLanes) {
-            const int q = rev[p];
-            const float4 gp = G[p], gq = G[q];
-            fx += gp.x - gq.x;
-            fy += gp.y - gq.y;
-            fz += gp.z - gq.z;
-        }
-    }
-#pragma unroll
-    for (int m = kBackLanes / 2; m >= 1; m >>= 1) {
-        fx += shfl_xor(fx, m);
-        fy += shfl_xor(fy, m);
-        fz += shfl_xor(fz, m);
-    }
+    const int a = blk * kBackAtoms + threadIdx.x / kGatherLanes;
+    const int sub = threadIdx.x % kGatherLanes;
+    const float3 fs = gather_row_force(rows, rev, G, a, n, sub);
     double ke = 0.0;
     if (a < n && sub == 0) {
-        const float f[3] = {fx, fy, fz};
+        const float f[3] = {fs.x, fs.y, fs.z};
         const float im = inv_mass[a];
         const float kick = 0.5f * dt * kAccUnit * im;
         double v2 = 0.0;
@@ -152,13 +176,8 @@ __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, const RowsView 
         ke = 0.5 * v2 / ((double)im * (double)kAccUnit);
     }
     if (!ke_part) return;
-    red[threadIdx.x] = ke;
-    __syncthreads();
-    for (int st = kBackThreads / 2; st >= 1; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) ke_part[blockIdx.x] = red[0];
+    const double tot = block_sum(ke, red);
+    if (threadIdx.x == 0) ke_part[blk] = tot;
 }
 
 // log row: {potential energy, kinetic energy}, both float64, fixed order
@@ -194,9 +213,9 @@ hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const 
     return hipGetLastError();
 }
 
-hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trigger2,
+hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trig_len,
                             hipStream_t s) {
-    k_md_decide<<<1, 256, 0, s>>>(st, d2_part, n_parts, rebuild_every, trigger2);
+    k_md_decide<<<1, 256, 0, s>>>(st, d2_part, n_parts, rebuild_every, trig_len);
     return hipGetLastError();
 }
 
@@ -208,16 +227,19 @@ hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx,
 
 int md_ke_parts(int n) { return ceil_div(n > 0 ? n : 1, kBackAtoms); }
 
+int md_energy_parts(int n) { return ceil_div(n > 0 ? n : 1, kEChunk); }
+
 hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s) {
-    MdEnergyIn E{};
-    if (e) E = *e;
-    if (b.fuse_energy && e)
-        k_md_back<true><<<md_ke_parts(n) + 1, kBackThreads, 0, s>>>(n, rows, rows.rev, G, F, b.vel,
-                                                                    b.inv_mass, b.dt, b.ke_part, E);
-    else
-        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, rows, rows.rev, G, F, b.vel,
-                                                                 b.inv_mass, b.dt, b.ke_part, E);
+    if (b.fuse_energy && e) {
+        const int ne = md_energy_parts(n);
+        if (ne > 1 && (!e->part || !e->ticket)) return hipErrorInvalidValue;
+        k_md_back<true><<<md_ke_parts(n) + ne, kBackThreads, 0, s>>>(n, ne, rows, rows.rev, G, F, b.vel,
+                                                                     b.inv_mass, b.dt, b.ke_part, *e);
+    } else {
+        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, 0, rows, rows.rev, G, F, b.vel,
+                                                                 b.inv_mass, b.dt, b.ke_part, MdEnergyIn{});
+    }
     return hipGetLastError();
 }
 

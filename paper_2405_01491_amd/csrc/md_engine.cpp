@@ -31,7 +31,7 @@ struct nnp_md {
     float box[3] = {0, 0, 0};
     float r_list = 0.f;
     MdStepConst c{};
-    float trigger2 = -1.f;
+    float trig_len = -1.f;     // trigger * skin, or -1 without a skin
     uint64_t step = 0;
     bool small = false;       // fused front / back kernels (md_front_fits)
     bool grouped = false;     // species grouping in ws_ef is current
@@ -42,7 +42,9 @@ struct nnp_md {
     MdState* st = nullptr;
     unsigned* flags = nullptr;
     double* ke_part = nullptr;
-    float* d2_part = nullptr;   // per-block displacements (general path)
+    float* d2_part = nullptr;   // per-block two largest displacements (general path)
+    double* e_part = nullptr;   // chunk sums of the structure energy
+    unsigned* e_ticket = nullptr;
     // energy log [log_cap][2]
     double* log = nullptr;
     int log_cap = 0;
@@ -83,12 +85,11 @@ nnp_status status_of_flags(unsigned fl) {
 // One step.  Small systems (md_front_fits): a fused front kernel (first half
 // step, displacement, rebuild decision, wrap and cell binning), the gated
 // row kernel, AEV (with the reverse index on rebuild steps), networks, AEV
-// adjoint, and a fused back kernel (force gather, last half kick and, when
-// wanted, the structure energy): six launches.  Larger systems use the
-// general multi-kernel path for the front, the cell binning and the energy
-// sum.  The potential energy is summed only on logged steps and on the last
-// step of a run (the one nnp_md_get reports).
-nnp_status enqueue_step(nnp_md* md, uint64_t step, bool last, hipStream_t s) {
+// adjoint, and a fused back kernel (force gather, last half kick and the
+// float64 structure energy): six launches.  Larger systems use the general
+// multi-kernel path for the front and the cell binning.  The potential
+// energy is summed on every step, in the back kernel.
+nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     nnp_model* m = md->model;
     const bool langevin = md->p.integrator == NNP_MD_LANGEVIN;
     const float* bptr = md->bx.periodic ? md->box : nullptr;
@@ -96,14 +97,14 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, bool last, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (md->small) {
         nnp_status st = launch_md_front(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->st,
-                                        md->p.rebuild_every, md->trigger2, langevin, bptr, md->r_list, md->ws_nb,
+                                        md->p.rebuild_every, md->trig_len, langevin, bptr, md->r_list, md->ws_nb,
                                         md->ws_nb_bytes, md->flags, s);
         if (st != NNP_OK) return st;
     } else {
         e = md_launch_first(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->d2_part,
                             langevin, s);
         if (e == hipSuccess)
-            e = md_launch_decide(md->st, md->d2_part, md_first_parts(md->n), md->p.rebuild_every, md->trigger2, s);
+            e = md_launch_decide(md->st, md->d2_part, md_first_parts(md->n), md->p.rebuild_every, md->trig_len, s);
         if (e == hipSuccess) e = md_launch_wrap_ref(md->n, md->pos, md->ref, md->bx, md->st, s);
     }
     prof_end(m, NNP_STAGE_INTEGRATE, s);
@@ -115,16 +116,16 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, bool last, hipStream_t s) {
     md->rows.rev = md->nl.rev;
     const bool log = md->p.log_every > 0 && ((step + 1) % (uint64_t)md->p.log_every) == 0 &&
                      md->log_rows < md->log_cap;
-    const bool energy = log || last;
     MdBack back{};
     back.vel = md->vel;
     back.inv_mass = md->inv_mass;
     back.dt = md->p.dt;
     back.ke_part = log ? md->ke_part : nullptr;
-    back.fuse_energy = md->small && energy;
+    back.fuse_energy = true;
+    back.e_part = md->e_part;
+    back.e_ticket = md->e_ticket;
     EfOpts opts;
     opts.skip_group = md->grouped;
-    opts.skip_energy = !energy;
     opts.md = &back;
     opts.rows = &md->rows;
     opts.rev_out = md->nl.rev;
@@ -166,6 +167,10 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
         p.log_capacity < 0)
         return NNP_E_ARG;
     if (p.integrator == NNP_MD_LANGEVIN && (!(p.temperature >= 0.f) || !(p.friction >= 0.f))) return NNP_E_ARG;
+    // every setting must keep the list complete between builds: with a skin
+    // the displacement check is on (0 < trigger <= 1); without one the list
+    // is rebuilt every step
+    if (p.skin > 0.f ? !(p.trigger > 0.f && p.trigger <= 1.f) : p.rebuild_every != 1) return NNP_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     nnp_md* md = new nnp_md();
     md->model = model;
@@ -184,7 +189,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
                 delete md;
                 return NNP_E_BOX;
             }
-    md->trigger2 = p.skin > 0.f && p.trigger > 0.f ? (0.5f * p.trigger * p.skin) * (0.5f * p.trigger * p.skin) : -1.f;
+    md->trig_len = p.skin > 0.f ? p.trigger * p.skin : -1.f;
     md->c.dt = p.dt;
     md->c.seed = p.seed;
     if (p.integrator == NNP_MD_LANGEVIN) {
@@ -204,7 +209,8 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
               dmalloc(&md->inv_mass, (size_t)n) == hipSuccess && dmalloc(&md->species, (size_t)n) == hipSuccess &&
               dmalloc(&md->e_pot, 1) == hipSuccess && dmalloc(&md->st, 1) == hipSuccess &&
               dmalloc(&md->flags, 1) == hipSuccess && dmalloc(&md->ke_part, (size_t)md_ke_parts(n)) == hipSuccess &&
-              dmalloc(&md->d2_part, (size_t)md_first_parts(n)) == hipSuccess &&
+              dmalloc(&md->d2_part, 2 * (size_t)md_first_parts(n)) == hipSuccess &&
+              dmalloc(&md->e_part, (size_t)md_energy_parts(n)) == hipSuccess && dmalloc(&md->e_ticket, 1) == hipSuccess &&
               dmalloc(&md->log, 2 * (size_t)(md->log_cap > 0 ? md->log_cap : 1)) == hipSuccess &&
               hipHostMalloc(&md->host, 64, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -221,6 +227,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     if (e == hipSuccess) e = hipMemcpyAsync(md->species, species, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(md->st, 0, sizeof(MdState), s);
     if (e == hipSuccess) e = hipMemsetAsync(md->flags, 0, sizeof(unsigned), s);
+    if (e == hipSuccess) e = hipMemsetAsync(md->e_ticket, 0, sizeof(unsigned), s);
     if (e == hipSuccess) e = md_launch_inv_mass(n, masses, md->inv_mass, md->flags, s);
     // the starting configuration: wrapped, reference for displacements, list, forces
     MdState st0{};
@@ -268,7 +275,7 @@ nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream) {
     if (n_steps == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
     for (int k = 0; k < n_steps; ++k) {
-        nnp_status st = enqueue_step(md, md->step + (uint64_t)k, k + 1 == n_steps, s);
+        nnp_status st = enqueue_step(md, md->step + (uint64_t)k, s);
         if (st != NNP_OK) return st;
     }
     unsigned fl = 0;
@@ -324,7 +331,7 @@ nnp_status nnp_md_info(nnp_md* md, nnp_md_stats* out, void* stream) {
 void nnp_md_destroy(nnp_md* md) {
     if (!md) return;
     void* bufs[] = {md->pos, md->vel, md->F, md->ref, md->inv_mass, md->species, md->e_pot, md->st, md->flags,
-                    md->ke_part, md->d2_part, md->log, md->nl.rev, md->ws_ef, md->ws_nb};
+                    md->ke_part, md->d2_part, md->e_part, md->e_ticket, md->log, md->nl.rev, md->ws_ef, md->ws_nb};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (md->host) (void)hipHostFree(md->host);

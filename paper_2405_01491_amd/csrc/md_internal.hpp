@@ -9,7 +9,7 @@ namespace nnp {
 struct MdState {
     int32_t gate;              // 1 on steps that rebuild the neighbour list
     int32_t since;             // steps since the last rebuild
-    float max_d2;              // largest squared displacement since the last rebuild (this step)
+    float max_d2;              // largest squared displacement since the last rebuild (at the last decision)
     int32_t pad;
     unsigned long long rebuilds;
     unsigned long long early_rebuilds;
@@ -104,19 +104,41 @@ __device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, f
     return d2 <= INFINITY ? d2 : INFINITY;
 }
 
-// Rebuild decision (one thread): every rebuild_every steps, or earlier once an
-// atom has moved more than trigger * skin / 2 since the last build.  cur is
+// The two largest squared displacements of a set of atoms (m1 >= m2):
+// adding one atom, merging two disjoint sets, and the whole wave.
+__device__ __forceinline__ void top2_add(float& m1, float& m2, float x) {
+    m2 = fmaxf(m2, fminf(m1, x));
+    m1 = fmaxf(m1, x);
+}
+__device__ __forceinline__ void top2_merge(float& m1, float& m2, float n1, float n2) {
+    m2 = fmaxf(fminf(m1, n1), fmaxf(m2, n2));
+    m1 = fmaxf(m1, n1);
+}
+__device__ __forceinline__ void top2_wave(float& m1, float& m2) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const float n1 = shfl_xor(m1, m), n2 = shfl_xor(m2, m);
+        top2_merge(m1, m2, n1, n2);
+    }
+}
+
+// Rebuild decision (one thread): every rebuild_every steps, or earlier once
+// the two largest displacements since the last build, d1 + d2, exceed
+// trig_len = trigger * skin (trig_len < 0: no displacement check).  A pair
+// outside the list was at least r_list = Rc + skin apart at the build and
+// its distance has since shrunk by at most d_i + d_j <= d1 + d2, so no pair
+// can come within Rc before the check fires (the Verlet-list bound).  cur is
 // the state as read at the start of the kernel (loaded early, off the
 // critical path); the new state is written to st.
-__device__ __forceinline__ int md_decide(MdState* st, const MdState& cur, float max_d2, int rebuild_every,
-                                         float trigger2) {
+__device__ __forceinline__ int md_decide(MdState* st, const MdState& cur, float m1, float m2, int rebuild_every,
+                                         float trig_len) {
     const int since = cur.since + 1;
     const bool due = since >= rebuild_every;
-    const bool moved = trigger2 >= 0.f && max_d2 > trigger2;
+    const bool moved = trig_len >= 0.f && !(sqrtf(m1) + sqrtf(m2) <= trig_len);   // NaN rebuilds
     const int gate = due || moved ? 1 : 0;
     st->gate = gate;
     st->since = gate ? 0 : since;
-    st->max_d2 = 0.f;
+    st->max_d2 = m1;
     if (gate) {
         st->rebuilds = cur.rebuilds + 1;
         if (!due) st->early_rebuilds = cur.early_rebuilds + 1;
@@ -124,13 +146,15 @@ __device__ __forceinline__ int md_decide(MdState* st, const MdState& cur, float 
     return gate;
 }
 
-// Energy fused into the last kernel of a step (small systems): what it needs.
+// Energy fused into the last kernel of a step: what it needs.
 struct MdEnergyIn {
     const int32_t* prow;      // grouped row of each atom (< 0: no network energy)
     const int32_t* species;
     const float* E_at;        // network energies in atom order
     double se[kMaxSpecies];   // self energies
     double* e_pot;            // [1]
+    double* part;             // [md_energy_parts(n)] chunk sums (unused for one chunk)
+    unsigned* ticket;         // zero between launches (the last block resets it)
 };
 
 // Second part of a step: force gather, B(dt/2), per-block kinetic energies.
@@ -140,22 +164,25 @@ struct MdBack {
     float dt;
     double* ke_part;          // [md_ke_parts(n)] or null
     bool fuse_energy;         // sum the structure energy in the same kernel
+    double* e_part;           // [md_energy_parts(n)] chunk sums of the structure energy
+    unsigned* e_ticket;       // one word, zero between launches
 };
 
-// d2_part: [md_first_parts(n)] per-block largest squared displacements
+// d2_part: [2 md_first_parts(n)] per-block two largest squared displacements
 int md_first_parts(int n);
 hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
                            uint64_t step, const float* ref, float* d2_part, bool langevin, hipStream_t s);
-hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trigger2,
+hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trig_len,
                             hipStream_t s);
 hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx, const MdState* st, hipStream_t s);
 int md_ke_parts(int n);
+int md_energy_parts(int n);
 hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s);
 // neighbors.hip: the fused front of a step for small systems
 bool md_front_fits(int n, const float* box_host, float r_list);
 nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
-                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trigger2, bool langevin,
+                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trig_len, bool langevin,
                            const float* box_host, float r_list, void* ws, size_t ws_bytes, unsigned* flags,
                            hipStream_t s);
 hipError_t md_launch_log(int n, const double* ke_part, const double* e_pot, double* row, hipStream_t s);

@@ -487,7 +487,7 @@ __global__ void k_fill_gated(int32_t* p, long n, int32_t v, const int32_t* gate)
 // ---------------------------------------------------------------- MD front (small systems)
 //
 // One workgroup does, for every atom: the first part of the MD step
-// (md_first_atom), the largest displacement since the last list build, the
+// (md_first_atom), the two largest displacements since the last list build, the
 // rebuild decision, and on rebuild steps the wrap into the box, the new
 // reference positions and the cell binning (counts in LDS, a block scan for
 // the cell starts, the scatter).  It replaces five to seven launches of the
@@ -501,30 +501,31 @@ template <bool kLangevin>
 __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     int n, float* __restrict__ pos, float* __restrict__ vel, const float* __restrict__ F,
     const float* __restrict__ inv_mass, const MdStepConst c, uint64_t step, float* __restrict__ ref, MdState* st,
-    int rebuild_every, float trigger2, const Grid g, int n_cells, int32_t* __restrict__ cell_of,
+    int rebuild_every, float trig_len, const Grid g, int n_cells, int32_t* __restrict__ cell_of,
     int32_t* __restrict__ cell_start, int32_t* __restrict__ cell_atoms, unsigned* flags) {
     __shared__ int s_cnt[kFrontCells + 1];
-    __shared__ float s_max[kFrontThreads / kWave];
+    __shared__ float s_max[kFrontThreads / kWave][2];
     __shared__ int s_wsum[kFrontThreads / kWave];
     __shared__ int s_gate;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     MdState cur{};
     if (t == 0) cur = *st;   // read now, used by the decision below
-    float d2 = 0.f;
+    float m1 = 0.f, m2 = 0.f;   // the two largest squared displacements
     float xs[kFrontPer][3];   // this thread's atoms after the half step (kept for the wrap and binning)
 #pragma unroll
     for (int k = 0; k < kFrontPer; ++k) {
         const int a = t + k * kFrontThreads;
-        if (a < n) d2 = fmaxf(d2, md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref, xs[k]));
+        if (a < n) top2_add(m1, m2, md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref, xs[k]));
     }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) d2 = fmaxf(d2, shfl_xor(d2, m));
-    if (l == 0) s_max[w] = d2;
+    top2_wave(m1, m2);
+    if (l == 0) {
+        s_max[w][0] = m1;
+        s_max[w][1] = m2;
+    }
     __syncthreads();
     if (t == 0) {
-        float mx = 0.f;
-        for (int q = 0; q < kFrontThreads / kWave; ++q) mx = fmaxf(mx, s_max[q]);
-        s_gate = md_decide(st, cur, mx, rebuild_every, trigger2);
+        for (int q = 1; q < kFrontThreads / kWave; ++q) top2_merge(m1, m2, s_max[q][0], s_max[q][1]);
+        s_gate = md_decide(st, cur, m1, m2, rebuild_every, trig_len);
     }
     __syncthreads();
     if (!s_gate) return;
@@ -677,7 +678,7 @@ bool md_front_fits(int n, const float* box_host, float r_list) {
 }
 
 nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
-                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trigger2, bool langevin,
+                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trig_len, bool langevin,
                            const float* box_host, float r_list, void* ws, size_t ws_bytes, unsigned* flags,
                            hipStream_t s) {
     Grid g;
@@ -693,10 +694,10 @@ nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const 
     int32_t* cell_atoms = (int32_t*)(base + L.cell_atoms);
     if (langevin)
         k_md_front<true><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st, rebuild_every,
-                                                     trigger2, g, (int)n_cells, cell_of, cell_start, cell_atoms, flags);
+                                                     trig_len, g, (int)n_cells, cell_of, cell_start, cell_atoms, flags);
     else
         k_md_front<false><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st, rebuild_every,
-                                                      trigger2, g, (int)n_cells, cell_of, cell_start, cell_atoms,
+                                                      trig_len, g, (int)n_cells, cell_of, cell_start, cell_atoms,
                                                       flags);
     return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
 }

@@ -221,6 +221,35 @@ struct RowsView {
     }
 };
 
+// Force on atom a from the edge gradients of its row (Sec. 2.4: forces as
+// the gradient of the total energy), F_a = sum_j G_aj - G_ja, G_ja at rev[p]:
+// kGatherLanes lanes per atom stride over the row, then a fixed butterfly.
+// The plain path's gather and the MD engine's last kernel both use it, so
+// the two give the same forces bit for bit at the same positions.
+constexpr int kGatherLanes = 32;
+
+__device__ __forceinline__ float3 gather_row_force(const RowsView& rows, const int32_t* __restrict__ rev,
+                                                   const float4* __restrict__ G, int a, int n, int sub) {
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    if (a < n) {
+        const int b = rows.begin(a), e = rows.end(a);
+        for (int p = b + sub; p < e; p += kGatherLanes) {
+            const int q = rev[p];
+            const float4 gp = G[p], gq = G[q];
+            fx += gp.x - gq.x;
+            fy += gp.y - gq.y;
+            fz += gp.z - gq.z;
+        }
+    }
+#pragma unroll
+    for (int m = kGatherLanes / 2; m >= 1; m >>= 1) {
+        fx += shfl_xor(fx, m);
+        fy += shfl_xor(fy, m);
+        fz += shfl_xor(fz, m);
+    }
+    return make_float3(fx, fy, fz);
+}
+
 inline RowsView rows_csr(const nnp_nlist* nl) {
     RowsView r{};
     r.row_ptr = nl->row_ptr;

@@ -5,9 +5,12 @@ Per step:  kick + drift (nnp_md_kick_drift) -> neighbour rebuild when due
 (wrap into the box, nnp_neighbors) -> energy and forces (nnp_energy_forces)
 -> kick (nnp_md_kick).  With a skin (Sec. 5.5: a buffer and a rebuild every
 few steps), the list is rebuilt every ``rebuild_every`` steps, and earlier if
-the largest displacement since the last build exceeds ``trigger * skin / 2``;
-that displacement is folded on the device each step and read back through
-pinned memory one step late, so the loop never waits for it.
+the largest displacement since the last build exceeds ``trigger * skin / 2``
+(two atoms that each moved less than half the skin cannot have closed the
+gap).  That displacement is folded on the device after the drift and read
+back before the step's forces are computed, so this driver waits once per
+step when it has a skin; the native engine (``MDEngine``) decides on the
+device and never waits.
 """
 import ctypes
 
@@ -37,7 +40,11 @@ def _s(device):
 
 class VelocityVerlet:
     def __init__(self, model, pos, vel, species, masses, box=None, mol=None, n_mol=1, dt=0.5, skin=0.0,
-                 rebuild_every=1, trigger=0.8):
+                 rebuild_every=1, trigger=1.0):
+        if skin > 0 and not (0 < trigger <= 1):
+            raise ValueError("with a skin the displacement trigger must be in (0, 1]")
+        if skin <= 0 and int(rebuild_every) != 1:
+            raise ValueError("without a skin the list must be rebuilt every step")
         self.model = model
         self.dev = pos.device
         self.pos = pos.contiguous()
@@ -56,7 +63,6 @@ class VelocityVerlet:
         self.ref = torch.empty_like(self.pos)
         self.max_d2 = torch.zeros(1, dtype=torch.float32, device=self.dev)
         self._host_d2 = torch.zeros(1, dtype=torch.float32).pin_memory()
-        self._d2_event = None
         self.out = {}
         self.nl = None
         self.steps = 0
@@ -75,7 +81,6 @@ class VelocityVerlet:
         self.nl = nnp_neighbors(self.model, self.pos, self.mol, self.n_mol, self.box, self.r_list, nl=self.nl)
         self.ref.copy_(self.pos)
         self.max_d2.zero_()
-        self._d2_event = None
         self.since_build = 0
         self.rebuilds += 1
 
@@ -91,16 +96,19 @@ class VelocityVerlet:
               "nnp_md_kick_drift")
         self.since_build += 1
         due = self.since_build >= self.rebuild_every
-        if not due and track and self._d2_event is not None and self._d2_event.query():
-            if float(self._host_d2[0]) > self.trigger2:
+        if not due and track:
+            # this step's displacement, before its forces (NaN rebuilds, and
+            # the rebuild then flags the coordinates)
+            self._host_d2.copy_(self.max_d2, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record()
+            ev.synchronize()
+            d2 = float(self._host_d2[0])
+            if not d2 <= self.trigger2:
                 due = True
                 self.early_rebuilds += 1
         if due:
             self._rebuild()
-        elif track:
-            self._host_d2.copy_(self.max_d2, non_blocking=True)
-            self._d2_event = torch.cuda.Event()
-            self._d2_event.record()
         self.e_mol, _, self.forces = nnp_energy_forces(self.model, self.pos, self.species, self.mol, self.n_mol,
                                                        self.box, self.nl, out=self.out)
         check(L.nnp_md_kick(n, ctypes.c_void_p(self.vel.data_ptr()), ctypes.c_void_p(self.forces.data_ptr()),
@@ -138,7 +146,7 @@ class MDEngine:
     synchronises once.  State lives in the engine; ``state()`` copies it out."""
 
     def __init__(self, model, pos, vel, species, masses, box=None, dt=0.5, integrator="nve", temperature=300.0,
-                 friction=1.0, seed=0, skin=0.0, rebuild_every=1, trigger=0.8, log_every=0, log_capacity=0):
+                 friction=1.0, seed=0, skin=0.0, rebuild_every=1, trigger=1.0, log_every=0, log_capacity=0):
         L = lib()
         self.model = model
         self.dev = pos.device

@@ -76,6 +76,29 @@ def test_md_entry_points_reject_bad_arguments():
     assert L.nnp_md_kick(0, None, None, None, 0.5, None) == _lib.NNP_OK
 
 
+@pytest.mark.parametrize("skin,every,trigger", [(0.5, 20, 1.5), (0.5, 20, 0.0), (0.5, 20, -1.0),
+                                                (0.0, 5, 1.0), (0.5, 0, 1.0)])
+def test_md_create_rejects_incomplete_list_settings(skin, every, trigger):
+    """Settings that could let a pair come within the cutoff while missing
+    from the list are refused before anything touches the device: a trigger
+    outside (0, 1] with a skin, or no skin and no rebuild every step."""
+    L = _lib.lib()
+    buf = (ctypes.c_float * 12)()
+    p = _lib.MdParams()
+    p.integrator, p.dt, p.skin, p.rebuild_every, p.trigger = 0, 0.5, skin, every, trigger
+    h = ctypes.c_void_p()
+    dummy = ctypes.cast(buf, ctypes.c_void_p)
+    st = L.nnp_md_create(dummy, 4, dummy, dummy, dummy, dummy, None, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == _lib.NNP_E_ARG and not h.value
+
+
+@pytest.mark.parametrize("skin,every,trigger", [(0.5, 20, 1.5), (0.5, 20, 0.0), (0.0, 5, 1.0)])
+def test_python_driver_rejects_incomplete_list_settings(skin, every, trigger):
+    from paper_2405_01491_amd import md as nmd
+    with pytest.raises(ValueError):
+        nmd.VelocityVerlet(None, None, None, None, None, skin=skin, rebuild_every=every, trigger=trigger)
+
+
 def test_product_path_has_no_fallback(monkeypatch, tmp_path):
     """Without the built library the binding raises instead of computing
     anything on the CPU."""

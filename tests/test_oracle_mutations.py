@@ -134,3 +134,16 @@ def test_mutant_ensemble_self_energy_per_network(monkeypatch):
         return orig(aev, species, spec, precision, need_grad, weights, with_self=True)
     monkeypatch.setattr(omlp, "_single_net", bad)
     assert _fails(pins.test_ensemble_is_the_mean_of_its_networks)
+
+
+def test_mutant_cells_smaller_than_cutoff(monkeypatch):
+    # cells cut finer than the cutoff: the 27-cell stencil misses partners
+    monkeypatch.setattr(onb, "_cells_per_axis", lambda L, side: max(2, int(np.ceil(1.6 * L / side))))
+    assert _fails(pins.test_cell_search_matches_all_pairs_scan, "cubic")
+
+
+def test_mutant_cell_index_rounded(monkeypatch):
+    # binning by rounding instead of flooring puts atoms one cell off
+    monkeypatch.setattr(onb, "_cell_index",
+                        lambda x, lo, cs, nc: np.clip(np.rint((x - lo) / cs).astype(np.int64), 0, nc - 1))
+    assert _fails(pins.test_cell_search_matches_all_pairs_scan, "cubic")

@@ -74,6 +74,67 @@ def test_neighbors_relabel_invariant():
     assert mapped == _pairset(nl)
 
 
+@pytest.mark.parametrize("case", synthetic.adversarial_cases(), ids=lambda c: c.name)
+def test_cell_search_matches_brute_force_adversarial(case):
+    """The cell-binned search finds the same edge set as the pure-Python
+    enumeration over periodic images on the adversarial cases (atoms on cell
+    faces, at L - ulp, pairs exactly at the cutoff, a 2-cell-thin box)."""
+    r_list = 5.1
+    if case.box is not None and np.any(case.box < 2 * np.float32(r_list)):
+        with pytest.raises(ValueError):
+            oracle.neighbor_list_cells(case.pos, case.mol, case.box, r_list)
+        return
+    nl = oracle.neighbor_list_cells(case.pos, case.mol, case.box, r_list)
+    bf = oracle.brute_force_pairs(case.pos, case.mol, case.box, r_list)
+    assert _pairset(nl) == [(i, j, tuple(n)) for i, j, n in bf]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cell_search_matches_brute_force_random_periodic(seed):
+    rng = np.random.default_rng(seed)
+    box = np.array([11.5, 11.5, 13.0], dtype=np.float32)      # 2 cells per axis: the stencil wraps onto itself
+    pos = (rng.uniform(-1, 2, size=(40, 3)) * box).astype(np.float32)
+    nl = oracle.neighbor_list_cells(pos, None, box, 5.6)
+    bf = oracle.brute_force_pairs(pos, None, box, 5.6, max_image=4)
+    assert _pairset(nl) == [(i, j, tuple(n)) for i, j, n in bf]
+
+
+@pytest.mark.parametrize("shape", ["cubic", "thin", "open_mols"])
+def test_cell_search_matches_all_pairs_scan(shape):
+    """Same (i, j, image) arrays, in the same order, as the O(N^2) scan of
+    the definition, on boxes of several cells per axis (3-cell and 2-cell
+    axes, coordinates far outside the box) and on an open system of several
+    structures."""
+    rng = np.random.default_rng({"cubic": 10, "thin": 11, "open_mols": 12}[shape])
+    mol = None
+    if shape == "cubic":
+        box = np.array([23.0, 26.0, 31.5], dtype=np.float32)
+        pos = (rng.uniform(-2, 3, size=(900, 3)) * box).astype(np.float32)
+    elif shape == "thin":
+        box = np.array([10.3, 16.9, 40.0], dtype=np.float32)
+        pos = (rng.uniform(0, 1, size=(700, 3)) * box).astype(np.float32)
+        pos[:50, 0] = np.float32(0.0)                         # on a cell face
+        pos[50:100, 1] = np.nextafter(box[1], np.float32(0))  # just below L
+    else:
+        box = None
+        pos = rng.uniform(-15, 15, size=(600, 3)).astype(np.float32)
+        mol = rng.integers(0, 4, size=600)
+    a = oracle.neighbor_list(pos, mol, box, 5.1)
+    b = oracle.neighbor_list_cells(pos, mol, box, 5.1)
+    assert len(a[0]) > 1000
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_cell_search_matches_all_pairs_scan_water():
+    w = synthetic.workload(2)
+    a = oracle.neighbor_rows(w.pos, None, w.box, 5.6, np.arange(0, w.n_atoms, 7))
+    b = oracle.neighbor_list_cells(w.pos, None, w.box, 5.6)
+    sel = np.isin(b[0], np.arange(0, w.n_atoms, 7))
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y[sel])
+
+
 # ---------------------------------------------------------------- switching function
 
 def test_switch_closed_form(spec):
