@@ -29,14 +29,14 @@ are used.
 """
 from .neighbors import neighbor_list, neighbor_list_cells, neighbor_rows, brute_force_pairs
 from .aev import switch, switch_deriv, aev, AEVLayout
-from .mlp import celu, celu_deriv, mlp_energy, mlp_energy_and_grad, round_bf16
+from .mlp import celu, celu_deriv, mlp_energy, mlp_energy_and_grad, round_bf16, bf16_energy_sigma, mlp_trace
 from .forces import energy_forces, edge_gradients, forces_from_edges, total_energy, energy_forces_f64
 from .md import velocity_verlet, langevin_baoab, langevin_noise
 
 __all__ = [
     "neighbor_list", "neighbor_list_cells", "neighbor_rows", "brute_force_pairs",
     "switch", "switch_deriv", "aev", "AEVLayout",
-    "celu", "celu_deriv", "mlp_energy", "mlp_energy_and_grad", "round_bf16",
+    "celu", "celu_deriv", "mlp_energy", "mlp_energy_and_grad", "round_bf16", "bf16_energy_sigma", "mlp_trace",
     "energy_forces", "edge_gradients", "forces_from_edges", "total_energy", "energy_forces_f64",
     "velocity_verlet", "langevin_baoab", "langevin_noise",
 ]

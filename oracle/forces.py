@@ -145,9 +145,11 @@ def virial_from_edges(nl, v, G, mol=None, n_mol=1, n_atoms=None):
 
 
 def energy_forces(pos, species, mol, n_mol, box, spec, r_list=None, precision="fp64",
-                  nl=None, need_forces=True, need_virial=False, need_nets=False):
+                  nl=None, need_forces=True, need_virial=False, need_nets=False, rng=None):
     """Full evaluation.  Returns dict with E_mol [n_mol], E_atom [N],
-    F [N,3] (if requested), aev [N,D], g [N,D], nl."""
+    F [N,3] (if requested), aev [N,D], g [N,D], nl.  precision: "fp64",
+    "bf16" (the BF16 form's emulation) or "mca" (Monte Carlo arithmetic at
+    its rounding points, drawing from rng)."""
     if r_list is None:
         r_list = spec.rc_r
     N = pos.shape[0]
@@ -157,7 +159,7 @@ def energy_forces(pos, species, mol, n_mol, box, spec, r_list=None, precision="f
         search = neighbor_list if N <= 4096 else neighbor_list_cells
         nl = search(pos, mol, box, r_list)
     A = aev_fn(pos, species, box, nl, spec)
-    E_atom, g = mlp_energy_and_grad(A, species, spec, precision, need_grad=need_forces)
+    E_atom, g = mlp_energy_and_grad(A, species, spec, precision, need_grad=need_forces, rng=rng)
     mol = np.zeros(N, dtype=np.int64) if mol is None else np.asarray(mol)
     E_mol = np.zeros(n_mol)
     for a in range(N):                                  # ascending atom index

@@ -8,6 +8,14 @@ import synthetic
 # Tolerances of the FP32 path against the FP64 oracle.
 E_ATOM_REL = 1e-5      # per-atom energy, relative to max(|E_i|, rms E)
 F_MAX_ABS = 1e-4       # eV/A, max over atoms and components
+E_MOL_REL = 1e-5       # structure energy, relative to sum_i |E_i - e_s| (self energies are exact constants)
+
+# The BF16 form against the FP64 oracle: bounds from the bfloat16 unit
+# roundoff (oracle.bf16_energy_sigma: first-order spread of each energy when
+# every rounding point errs independently by up to u = 2^-8; forces: spread
+# of the oracle re-run in Monte Carlo arithmetic at the same points).
+BF16_K_SIGMA = 6.0     # energies: |dE| <= 6 sigma (+ the FP32 allowance)
+BF16_K_FORCE = 8.0     # forces: max |dF| <= 8 x the rms spread (+ F_MAX_ABS)
 
 
 def dev():
@@ -57,3 +65,56 @@ def organic(n, seed=31, density=0.1):
 def oracle_ef(w, spec, r_list=None, precision="fp64"):
     return oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec,
                                 r_list=r_list, precision=precision)
+
+
+def net_scale(E_atom, species, spec, mol=None, n_mol=1):
+    """Per structure: sum_i |E_i - e_s|, the size of the network's part of
+    the structure energy (the self energies are added exactly)."""
+    se = np.asarray(spec.self_energy, dtype=np.float64)[np.asarray(species, dtype=np.int64)]
+    mol = np.zeros(len(E_atom), dtype=np.int64) if mol is None else np.asarray(mol, dtype=np.int64)
+    out = np.zeros(n_mol)
+    np.add.at(out, mol, np.abs(np.asarray(E_atom, dtype=np.float64) - se))
+    return out
+
+
+def e_mol_error(e_mol, ref, w, spec):
+    """max over structures of |dE_mol| / sum_i |E_i - e_s|."""
+    sc = net_scale(ref["E_atom"], w.species, spec, w.mol if w.n_mol > 1 else None, w.n_mol)
+    return float(np.max(np.abs(np.asarray(e_mol, np.float64) - ref["E_mol"]) / np.maximum(sc, 1e-30)))
+
+
+def bf16_energy_gate(e_atom, e_mol, ref, w, spec):
+    """The BF16 form's energies against the FP64 oracle, in units of the
+    first-order bfloat16 spread (plus the FP32 form's own allowance).
+    Returns (max per-atom ratio, structure ratio); both must be <= 1."""
+    mol = w.mol if w.n_mol > 1 else None
+    sa, sm = oracle.bf16_energy_sigma(ref["aev"], w.species, spec, mol, w.n_mol)
+    Er = ref["E_atom"]
+    rms = np.sqrt(np.mean(Er ** 2))
+    allow_a = E_ATOM_REL * np.maximum(np.abs(Er), rms)
+    ra = np.abs(np.asarray(e_atom, np.float64) - Er) / (BF16_K_SIGMA * sa + allow_a)
+    sc = net_scale(Er, w.species, spec, mol, w.n_mol)
+    rm = np.abs(np.asarray(e_mol, np.float64) - ref["E_mol"]) / (BF16_K_SIGMA * sm + E_MOL_REL * sc)
+    return float(ra.max()), float(rm.max())
+
+
+def bf16_force_spread(w, spec, ref, runs=6, seed=0):
+    """rms over components and runs of F_mca - F_fp64: the oracle re-run with
+    Monte Carlo arithmetic at the BF16 form's rounding points, on the same
+    list."""
+    rng = np.random.default_rng(seed)
+    acc = []
+    for _ in range(runs):
+        out = oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec,
+                                   nl=ref["nl"], precision="mca", rng=rng)
+        acc.append(np.mean((out["F"] - ref["F"]) ** 2))
+    return float(np.sqrt(np.mean(acc)))
+
+
+def bf16_force_gate(F, F_ref, spread):
+    """(max ratio, rms ratio): max |dF| against 8 x the spread + 1e-4 eV/A,
+    rms |dF| against 2 x the spread + 1e-5; both must be <= 1."""
+    d = np.asarray(F, np.float64) - F_ref
+    return (float(np.abs(d).max() / (BF16_K_FORCE * spread + F_MAX_ABS)),
+            float(np.sqrt(np.mean(d ** 2)) / (2.0 * spread + 1e-5)))
+

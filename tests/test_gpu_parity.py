@@ -10,7 +10,8 @@ import torch
 import oracle
 import synthetic
 import paper_2405_01491_amd as nnp
-from tests.gpu_helpers import E_ATOM_REL, F_MAX_ABS, bf16_flip_error, dev, energy_error, oracle_ef, organic, to_dev
+from tests.gpu_helpers import (E_ATOM_REL, E_MOL_REL, F_MAX_ABS, bf16_energy_gate, bf16_flip_error, bf16_force_gate,
+                               bf16_force_spread, dev, e_mol_error, energy_error, oracle_ef, organic, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -80,8 +81,14 @@ def test_mlp_parity(spec_bias, precision, path):
               % (path, emed, emax, gmed, gmax))
         assert emed < 2e-6 and emax < 1e-2 and gmed < 2e-6 and gmax < 1e-2
         assert ee < 2e-4 and ge < 1e-2
-        E64, _ = oracle.mlp_energy_and_grad(A[:, :spec_bias.aev_dim].astype(np.float64), w.species, spec_bias)
-        print("mlp bf16 vs fp64 oracle: E err %.3g" % energy_error(e, E64))
+        # against the exact network on the same features: within the bfloat16 error model
+        A64 = A[:, :spec_bias.aev_dim].astype(np.float64)
+        E64, _ = oracle.mlp_energy_and_grad(A64, w.species, spec_bias)
+        sa, _ = oracle.bf16_energy_sigma(A64, w.species, spec_bias)
+        z = np.abs(e - E64) / sa
+        print("mlp bf16 vs fp64 oracle: E err %.3g, |dE| / sigma max %.3g rms %.3g"
+              % (energy_error(e, E64), z.max(), np.sqrt(np.mean(z ** 2))))
+        assert z.max() < 6.0
 
 
 def test_fused_and_per_layer_paths_agree(spec_bias):
@@ -114,12 +121,12 @@ def test_energy_forces_parity(model, spec_bias, name):
     nnp.nnp_check(model)
     ref = oracle_ef(w, spec_bias, r_list=r_list)
     ee = energy_error(e_atom.cpu().numpy(), ref["E_atom"])
-    em = np.max(np.abs(e_mol.cpu().numpy() - ref["E_mol"]) / np.maximum(1.0, np.abs(ref["E_mol"])))
+    em = e_mol_error(e_mol.cpu().numpy(), ref, w, spec_bias)
     fe = np.max(np.abs(F.cpu().numpy() - ref["F"]))
-    print("%s: E_atom err %.3g, E_mol err %.3g, F max err %.3g eV/A (max |F| %.3g)"
+    print("%s: E_atom err %.3g, E_mol err %.3g (of sum |E_i - e_s|), F max err %.3g eV/A (max |F| %.3g)"
           % (name, ee, em, fe, np.abs(ref["F"]).max()))
     assert ee < E_ATOM_REL
-    assert em < 1e-5
+    assert em < E_MOL_REL
     assert fe < F_MAX_ABS
 
 
@@ -178,22 +185,76 @@ def test_generic_widths_parity(precision):
 
 
 @pytest.mark.parametrize("path", ["fused", "per_layer"])
-def test_bf16_form_error_table(spec_bias, path):
+@pytest.mark.parametrize("name", ["organic_3000", "water_box_192", "serving_batch"])
+def test_bf16_form_within_error_model(spec_bias, path, name):
+    """The BF16-MLP form against the FP64 oracle, gated by bounds derived
+    from the bfloat16 unit roundoff: every atomic energy within 6 sigma of
+    the first-order error model (plus the FP32 allowance), every structure
+    energy within 6 sigma of its own (the weight roundings are shared by all
+    atoms of a species), forces within 8 x the spread of the oracle re-run in
+    Monte Carlo arithmetic.  Against the oracle's emulation of the same
+    rounding points it agrees to float32 accumulation for the median atom."""
     m = nnp.Model(spec_bias, "bf16")
     m.set_fused_mlp(path == "fused")
-    w = organic(3000)
+    w = {"organic_3000": lambda: organic(3000), "water_box_192": lambda: synthetic.geometry.small_water_box(64),
+         "serving_batch": lambda: synthetic.workload(4, n_mol=24)}[name]()
     pos, sp, mol = to_dev(w)
-    nl = nnp.nnp_neighbors(m, pos, None, 1, w.box, 5.1)
-    e_mol, e_atom, F = nnp.nnp_energy_forces(m, pos, sp, None, 1, w.box, nl, e_atom=True)
+    nl = nnp.nnp_neighbors(m, pos, mol, w.n_mol, w.box, 5.1)
+    e_mol, e_atom, F = nnp.nnp_energy_forces(m, pos, sp, mol, w.n_mol, w.box, nl, e_atom=True)
     ref = oracle_ef(w, spec_bias)
-    emu = oracle_ef(w, spec_bias, precision="bf16")
-    e_atom = e_atom.cpu().numpy()
-    F = F.cpu().numpy()
-    print("bf16 %s vs fp64: E_atom %.3g F max %.3g; vs bf16-emulated: E_atom %.3g F max %.3g"
-          % (path, energy_error(e_atom, ref["E_atom"]), np.abs(F - ref["F"]).max(),
+    emu = oracle.energy_forces(w.pos, w.species, w.mol if w.n_mol > 1 else None, w.n_mol, w.box, spec_bias,
+                               nl=ref["nl"], precision="bf16")
+    e_mol, e_atom, F = e_mol.cpu().numpy(), e_atom.cpu().numpy(), F.cpu().numpy()
+    ra, rm = bf16_energy_gate(e_atom, e_mol, ref, w, spec_bias)
+    spread = bf16_force_spread(w, spec_bias, ref)
+    rf, rr = bf16_force_gate(F, ref["F"], spread)
+    print("bf16 %s %s vs fp64: E_atom %.3g, E_mol %.3g, F max %.3g rms %.3g (MC spread %.3g); bound ratios: "
+          "E_atom %.3f E_mol %.3f F max %.3f F rms %.3f; vs emulation: E_atom %.3g F max %.3g"
+          % (path, name, energy_error(e_atom, ref["E_atom"]), e_mol_error(e_mol, ref, w, spec_bias),
+             np.abs(F - ref["F"]).max(), np.sqrt(np.mean((F - ref["F"]) ** 2)), spread, ra, rm, rf, rr,
              energy_error(e_atom, emu["E_atom"]), np.abs(F - emu["F"]).max()))
-    assert energy_error(e_atom, emu["E_atom"]) < 2e-4
-    assert np.abs(F - emu["F"]).max() < 2e-2
+    assert ra <= 1.0 and rm <= 1.0 and rf <= 1.0 and rr <= 1.0
+    rms = np.sqrt(np.mean((emu["E_atom"] - np.asarray(spec_bias.self_energy)[w.species]) ** 2))
+    emed, _ = bf16_flip_error(e_atom, emu["E_atom"], rms)
+    assert emed < 2e-6
+
+
+def test_autograd_matches_finite_differences(model, spec_bias):
+    """NNPEnergy's gradient (the hand-written adjoint through autograd)
+    against central differences of the energy the same GPU path computes
+    (forces are minus the energy gradient, Sec. 2.4).  Richardson
+    extrapolation of steps h and h/2 removes the h^2 term; what is left is
+    the float32 energy noise divided by h."""
+    w = synthetic.workload(4, n_mol=3)
+    pos, sp, mol = to_dev(w)
+    x = pos.clone().requires_grad_(True)
+    E = nnp.energy(model, x, sp, mol, w.n_mol, None)
+    E.sum().backward()
+    grad = x.grad.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(8)
+    picks = [(int(a), int(k)) for a, k in zip(rng.choice(w.n_atoms, 12, replace=False), rng.integers(0, 3, 12))]
+    x0 = w.pos.astype(np.float64)
+
+    def e_at(a, k, h):
+        y = x0.copy()
+        y[a, k] += h
+        yt = torch.from_numpy(y.astype(np.float32)).to(dev())
+        hh = float(np.float32(y[a, k]) - np.float32(x0[a, k]))     # the step the float32 input really takes
+        with torch.no_grad():
+            return float(nnp.energy(model, yt, sp, mol, w.n_mol, None).sum()), hh
+
+    errs = []
+    for a, k in picks:
+        fd = []
+        for h in (2e-2, 1e-2):
+            ep, hp = e_at(a, k, h)
+            em, hm = e_at(a, k, -h)
+            fd.append((ep - em) / (hp - hm))
+        rich = (4.0 * fd[1] - fd[0]) / 3.0
+        errs.append(abs(rich - grad[a, k]))
+    scale = np.abs(grad).max()
+    print("autograd vs central differences: max |diff| %.3g eV/A (max |dE/dx| %.3g)" % (max(errs), scale))
+    assert max(errs) < 2e-3 + 1e-3 * scale
 
 
 def test_autograd_matches_forces(model, spec_bias):
@@ -333,9 +394,9 @@ def test_isolated_atoms_and_sparse_features(model, spec_bias):
     ref = oracle_ef(w, spec_bias, r_list=5.1)
     ee = energy_error(e_atom.cpu().numpy(), ref["E_atom"])
     fe = np.max(np.abs(F.cpu().numpy() - ref["F"]))
-    em = np.max(np.abs(e_mol.cpu().numpy() - ref["E_mol"]) / np.maximum(1.0, np.abs(ref["E_mol"])))
+    em = e_mol_error(e_mol.cpu().numpy(), ref, w, spec_bias)
     print("isolated + molecules: E_atom err %.3g, E_mol err %.3g, F max err %.3g" % (ee, em, fe))
-    assert ee < E_ATOM_REL and em < 1e-5 and fe < F_MAX_ABS
+    assert ee < E_ATOM_REL and em < E_MOL_REL and fe < F_MAX_ABS
 
 
 def test_angular_neighbour_limit(model, spec_bias):

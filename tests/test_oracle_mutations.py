@@ -130,8 +130,8 @@ def test_mutant_ensemble_self_energy_per_network(monkeypatch):
     # the self energy kept in every network's energy and added again after the mean
     orig = omlp._single_net
 
-    def bad(aev, species, spec, precision, need_grad, weights, with_self=True):
-        return orig(aev, species, spec, precision, need_grad, weights, with_self=True)
+    def bad(aev, species, spec, precision, need_grad, weights, with_self=True, rng=None, trace=None):
+        return orig(aev, species, spec, precision, need_grad, weights, with_self=True, rng=rng, trace=trace)
     monkeypatch.setattr(omlp, "_single_net", bad)
     assert _fails(pins.test_ensemble_is_the_mean_of_its_networks)
 
@@ -147,3 +147,63 @@ def test_mutant_cell_index_rounded(monkeypatch):
     monkeypatch.setattr(onb, "_cell_index",
                         lambda x, lo, cs, nc: np.clip(np.rint((x - lo) / cs).astype(np.int64), 0, nc - 1))
     assert _fails(pins.test_cell_search_matches_all_pairs_scan, "cubic")
+
+
+# ---------------------------------------------------------------- BF16 form: rounding points
+
+def _fails_any(fn, cases):
+    return any(_fails(fn, *c) for c in cases)
+
+
+def test_mutant_bf16_head_weights_rounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_WEIGHTS", (True, True, True, True))
+    assert _fails(pins.test_bf16_weights_enter_rounded_where_stated, spec_bias, 3, False)
+
+
+def test_mutant_bf16_w2_unrounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_WEIGHTS", (True, False, True, False))
+    assert _fails(pins.test_bf16_weights_enter_rounded_where_stated, spec_bias, 1, True)
+
+
+def test_mutant_bf16_features_unrounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_INPUTS", (False, True, True))
+    assert _fails(pins.test_bf16_features_enter_rounded, spec_bias)
+
+
+def test_mutant_bf16_h1_unrounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_INPUTS", (True, False, True))
+    assert _fails(pins.test_bf16_hidden_activations_enter_rounded, spec_bias, 0, True)
+
+
+def test_mutant_bf16_h2_unrounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_INPUTS", (True, True, False))
+    assert _fails(pins.test_bf16_hidden_activations_enter_rounded, spec_bias, 1, True)
+
+
+def test_mutant_bf16_d3_unrounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_ADJOINT", (False, True, True))
+    assert _fails(pins.test_bf16_adjoint_inputs_enter_rounded, spec_bias, "w4")
+
+
+def test_mutant_bf16_d2_unrounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_ADJOINT", (True, False, True))
+    assert _fails(pins.test_bf16_adjoint_inputs_enter_rounded, spec_bias, "b2")
+
+
+def test_mutant_bf16_d1_unrounded(monkeypatch, spec_bias):
+    monkeypatch.setattr(omlp, "BF16_ADJOINT", (True, True, False))
+    assert _fails(pins.test_bf16_adjoint_inputs_enter_rounded, spec_bias, "b1")
+
+
+def test_mutant_bf16_sigma_drops_input_term(monkeypatch, spec_bias):
+    # the closed-form spread without the input roundings (weights only)
+    monkeypatch.setattr(omlp, "BF16_INPUTS", (False, False, False))
+    orig = omlp._single_net
+
+    def single(aev, species, spec, precision, need_grad, weights, with_self=True, rng=None, trace=None):
+        with monkeypatch.context() as m:
+            m.setattr(omlp, "BF16_INPUTS", (True, True, True))
+            return orig(aev, species, spec, precision, need_grad, weights, with_self, rng, trace)
+    monkeypatch.setattr(omlp, "_single_net", single)
+    assert _fails(pins.test_bf16_energy_sigma_matches_monte_carlo_arithmetic, spec_bias)
+

@@ -260,6 +260,149 @@ def test_round_bf16_matches_torch():
     assert np.array_equal(got, want)
 
 
+# ---------------------------------------------------------------- BF16 form: rounding points and error model
+
+def _bf16_case(spec_bias, n=300):
+    """Features of an organic-like box (every species present) and the
+    model with U(+-0.1) biases."""
+    w = synthetic.organic_box(n=n, density=0.1, seed=31)
+    A = oracle.aev(w.pos, w.species, w.box, oracle.neighbor_list(w.pos, None, w.box, 5.1), spec_bias)
+    return A, w.species
+
+
+def _with_weights(spec, fn):
+    """A copy of the model whose (W, b) of species s, layer l are fn(l, W, b)."""
+    import copy
+    out = copy.copy(spec)
+    out.weights = [[fn(l, W, b) for l, (W, b) in enumerate(layers)] for layers in spec.weights]
+    return out
+
+
+def _bf16_f32(x):
+    return oracle.round_bf16(x).astype(np.float32)
+
+
+def _n_changed(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    if a.ndim > 1:
+        return int(np.sum(np.any(a != b, axis=1)))
+    return int(np.sum(a != b))
+
+
+@pytest.mark.parametrize("layer,rounded", [(0, True), (1, True), (2, True), (3, False)])
+def test_bf16_weights_enter_rounded_where_stated(spec_bias, layer, rounded):
+    """The BF16 form sees W1..W3 only through their bfloat16 values (rounding
+    them beforehand changes nothing, bit for bit) and the head's w4 in full
+    precision (rounding it changes every energy)."""
+    A, Z = _bf16_case(spec_bias)
+    E0, g0 = oracle.mlp_energy_and_grad(A, Z, spec_bias, "bf16")
+    pre = _with_weights(spec_bias, lambda l, W, b: (_bf16_f32(W) if l == layer else W, b))
+    E1, g1 = oracle.mlp_energy_and_grad(A, Z, pre, "bf16")
+    if rounded:
+        assert np.array_equal(E0, E1) and np.array_equal(g0, g1)
+    else:
+        assert _n_changed(E0, E1) > 0.9 * len(Z)
+
+
+def test_bf16_features_enter_rounded(spec_bias):
+    A, Z = _bf16_case(spec_bias)
+    E0, g0 = oracle.mlp_energy_and_grad(A, Z, spec_bias, "bf16")
+    E1, g1 = oracle.mlp_energy_and_grad(oracle.round_bf16(A), Z, spec_bias, "bf16")
+    assert np.array_equal(E0, E1) and np.array_equal(g0, g1)
+    # control: the exact network sees the unrounded features
+    assert _n_changed(oracle.mlp_energy(A, Z, spec_bias), oracle.mlp_energy(oracle.round_bf16(A), Z, spec_bias)) \
+        > 0.9 * len(Z)
+
+
+def _nudge(spec, layer, which):
+    """Every bias of one layer (which = 'b') or the head's weights ('W', layer
+    3 only) moved up by one float32 ulp: a change far below one bfloat16 step
+    of the activations it feeds."""
+    def f(l, W, b):
+        if l != layer:
+            return W, b
+        if which == "b":
+            return W, np.nextafter(b, np.float32(np.inf)).astype(np.float32)
+        return np.nextafter(W, np.float32(np.inf)).astype(np.float32), b
+    return _with_weights(spec, f)
+
+
+@pytest.mark.parametrize("layer,feeds_rounded", [(0, True), (1, True), (2, False)])
+def test_bf16_hidden_activations_enter_rounded(spec_bias, layer, feeds_rounded):
+    """h1 and h2 enter the next product as bfloat16 values: nudging the bias
+    that produces them (one float32 ulp) leaves the next layer's
+    pre-activations of every atom unchanged except where an activation sits
+    within that nudge of a bfloat16 rounding boundary (a few per thousand).
+    h3 feeds the full-precision head: nudging b3 moves every energy.  The
+    exact network moves every atom in all three cases."""
+    A, Z = _bf16_case(spec_bias)
+    moved = _nudge(spec_bias, layer, "b")
+    if feeds_rounded:
+        a, b = oracle.mlp_trace(A, Z, spec_bias, "bf16"), oracle.mlp_trace(A, Z, moved, "bf16")
+        nb = _n_changed(a["z"][layer + 1], b["z"][layer + 1])
+        a64, b64 = oracle.mlp_trace(A, Z, spec_bias), oracle.mlp_trace(A, Z, moved)
+        n64 = _n_changed(a64["z"][layer + 1], b64["z"][layer + 1])
+        assert n64 > 0.9 * len(Z) and nb < 0.05 * len(Z)
+    else:
+        nb = _n_changed(oracle.mlp_energy(A, Z, spec_bias, "bf16"), oracle.mlp_energy(A, Z, moved, "bf16"))
+        assert nb > 0.9 * len(Z)
+
+
+@pytest.mark.parametrize("nudge", ["w4", "b2", "b1"])
+def test_bf16_adjoint_inputs_enter_rounded(spec_bias, nudge):
+    """d3 = w4 CELU'(z3), d2 and d1 enter their adjoint products as bfloat16
+    values.  Nudging w4 changes d3 continuously, nudging b2 (b1) changes
+    CELU'(z2) (CELU'(z1)) and so d2 (d1): the product each one feeds
+    (W3^T d3, W2^T d2, W1^T d1 = dE/dAEV) stays put for all but the atoms with
+    a value within the nudge of a rounding boundary, while the exact
+    network's moves for every atom."""
+    A, Z = _bf16_case(spec_bias)
+    layer, which, key = {"w4": (3, "W", ("p", 2)), "b2": (1, "b", ("p", 1)), "b1": (0, "b", ("g", None))}[nudge]
+    moved = _nudge(spec_bias, layer, which)
+
+    def product(tr):
+        return tr["g"] if key[0] == "g" else tr["p"][key[1]]
+    nb = _n_changed(product(oracle.mlp_trace(A, Z, spec_bias, "bf16")), product(oracle.mlp_trace(A, Z, moved, "bf16")))
+    n64 = _n_changed(product(oracle.mlp_trace(A, Z, spec_bias)), product(oracle.mlp_trace(A, Z, moved)))
+    assert n64 > 0.9 * len(Z)
+    assert nb < 0.05 * len(Z)
+
+
+def test_bf16_energy_sigma_matches_monte_carlo_arithmetic(spec_bias):
+    """The first-order error model (closed form through the exact adjoint)
+    against Monte Carlo arithmetic at the same rounding points (the network
+    re-run with random relative perturbations of size u): per atom and per
+    structure, the sampled spread equals the closed form."""
+    A, Z = _bf16_case(spec_bias)
+    E64, _ = oracle.mlp_energy_and_grad(A, Z, spec_bias, need_grad=False)
+    sa, sm = oracle.bf16_energy_sigma(A, Z, spec_bias)
+    rng = np.random.default_rng(0)
+    dev = np.array([oracle.mlp_energy_and_grad(A, Z, spec_bias, "mca", need_grad=False, rng=rng)[0] - E64
+                    for _ in range(48)])
+    ratio = np.sqrt(np.mean(dev ** 2, axis=0)) / sa
+    mol = np.sqrt(np.mean(dev.sum(1) ** 2)) / sm[0]
+    print("MC / closed form: per atom median %.3f (10-90%%: %.3f-%.3f), structure %.3f"
+          % (np.median(ratio), np.quantile(ratio, 0.1), np.quantile(ratio, 0.9), mol))
+    assert 0.9 < np.median(ratio) < 1.1
+    assert 0.7 < mol < 1.4
+
+
+def test_bf16_emulation_error_within_model(spec_bias):
+    """The deterministic emulation's errors against the exact network are
+    of the size the unit roundoff predicts: normalised by the closed-form
+    sigma, rms below 1 (round-to-nearest errors are smaller than the
+    uniform model's) and no atom beyond 5 sigma; a form without roundings
+    would sit orders of magnitude lower."""
+    A, Z = _bf16_case(spec_bias)
+    E64, _ = oracle.mlp_energy_and_grad(A, Z, spec_bias, need_grad=False)
+    Eb, _ = oracle.mlp_energy_and_grad(A, Z, spec_bias, "bf16", need_grad=False)
+    sa, _ = oracle.bf16_energy_sigma(A, Z, spec_bias)
+    z = (Eb - E64) / sa
+    print("emulation error / sigma: rms %.3f, max %.3f" % (np.sqrt(np.mean(z ** 2)), np.abs(z).max()))
+    assert 0.2 < np.sqrt(np.mean(z ** 2)) < 1.0
+    assert np.abs(z).max() < 5.0
+
+
 # ---------------------------------------------------------------- invariances
 
 def _fixed_list_energy(x64, sp, box, spec, nl):
