@@ -63,6 +63,7 @@ typedef enum {
 #define NNP_FLAG_MOL       0x8u   /* mol not non-decreasing or out of [0, n_mol) */
 #define NNP_FLAG_SHIFT     0x10u  /* periodic image shift outside int8 range      */
 #define NNP_FLAG_CAPACITY  0x20u  /* asynchronous list build exceeded its capacity */
+#define NNP_FLAG_REVERSE   0x40u  /* a pair i -> j whose reverse j -> i is absent  */
 
 /* Largest neighbour-row length (pairs within the list cutoff of one atom) the
  * AEV kernels accept.  Longer rows set NNP_FLAG_ROW and contribute nothing. */
@@ -85,7 +86,7 @@ typedef struct {
     const float* shf_r;       /* [n_shf_r] radial shell centres R_k                */
     float rc_a;               /* angular cutoff Rc_A (3.5), rc_a <= rc_r           */
     float eta_a;              /* angular radial width eta_A (12.5)                 */
-    float zeta;               /* angular exponent zeta (14.1)                      */
+    float zeta;               /* angular exponent zeta (14.1); must exceed 1       */
     int32_t n_shf_a;          /* number of angular radial shells (4)               */
     int32_t n_shf_z;          /* number of angle sections (8)                      */
     const float* shf_a;       /* [n_shf_a] angular radial shell centres R_a        */

@@ -443,11 +443,12 @@ __global__ __launch_bounds__(kCellWaves* kWave) void k_rows_cells(
 // Staging rows -> CSR at row_ptr (only the first row_ptr[i+1] - row_ptr[i]
 // entries: a row cut short by a capacity clamp stays in bounds), and the
 // reverse index: rev[p] of i -> j is the position of i in j's sorted staging
-// row (p itself if absent, which only a clamped list can produce).
+// row.  An absent reverse (only a clamped or truncated list can lack one)
+// points the pair at itself and raises NNP_FLAG_REVERSE.
 __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_compact(
     int n, const int32_t* __restrict__ row_count, const int32_t* __restrict__ stage_col,
     const int32_t* __restrict__ stage_sh, const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
-    int8_t* __restrict__ shift, int32_t* __restrict__ rev, const int32_t* gate) {
+    int8_t* __restrict__ shift, int32_t* __restrict__ rev, const int32_t* gate, unsigned* flags) {
     if (gate && *gate == 0) return;
     const int w = threadIdx.x / kWave;
     const int l = lane_id();
@@ -474,7 +475,9 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_compact(
             const int mid = (lo + hi) >> 1;
             if (rj[mid] < i) lo = mid + 1; else hi = mid;
         }
-        rev[p] = (lo < cj && rj[lo] == i) ? bj + lo : p;
+        const bool found = lo < cj && rj[lo] == i;
+        rev[p] = found ? bj + lo : p;
+        if (!found) set_flag(flags, NNP_FLAG_REVERSE);
     }
 }
 
@@ -805,7 +808,7 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         nl->n_pairs = -1;
         if (n > 0)
             k_compact<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
-                n, row_count, stage_col, stage_sh, nl->row_ptr, nl->col, nl->shift, nl->rev, gate);
+                n, row_count, stage_col, stage_sh, nl->row_ptr, nl->col, nl->shift, nl->rev, gate, flags);
         prof_end(model, NNP_STAGE_NEIGHBORS, s);
         return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
     }
@@ -827,7 +830,7 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     if (total > nl->capacity || total > 0x7fffffffLL) return NNP_E_CAPACITY;
     if (n > 0 && total > 0)
         k_compact<<<ceil_div(n, kRowsPerBlock), kRowsPerBlock * kWave, 0, s>>>(
-            n, row_count, stage_col, stage_sh, nl->row_ptr, nl->col, nl->shift, nl->rev, nullptr);
+            n, row_count, stage_col, stage_sh, nl->row_ptr, nl->col, nl->shift, nl->rev, nullptr, flags);
     prof_end(model, NNP_STAGE_NEIGHBORS, s);
     return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
 }
