@@ -46,7 +46,9 @@ typedef enum {
     NNP_E_BUSY = 6,       /* serving: no free request slot                        */
     NNP_E_PENDING = 7,    /* serving: the request has not completed yet           */
     NNP_E_HIP = 8,        /* a HIP runtime call failed                            */
-    NNP_E_ROW = 9         /* an atom has more neighbours than the kernels support */
+    NNP_E_ROW = 9,        /* an atom has more neighbours than the kernels support */
+    NNP_E_SCRATCH = 10    /* the call needs more than the fixed device scratch of
+                             the allocation-free entry point                      */
 } nnp_status;
 
 typedef enum {
@@ -244,6 +246,36 @@ nnp_status nnp_energy_forces_ensemble(nnp_model* model, int32_t n_atoms, const f
                                       const float* box_host, const nnp_nlist* nl, double* e_mol,
                                       double* e_mol_net, float* e_atom, float* forces, void* ws,
                                       size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- allocation-free call */
+
+/* Size of the fixed device scratch nnp_energy_forces_static works in. */
+#define NNP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* nnp_energy_forces without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The intermediates of the call (grouped
+ * features, dE/dAEV, hidden activations, edge gradients, energy partials)
+ * live in one fixed scratch array of NNP_STATIC_SCRATCH_BYTES, which the
+ * library holds on every device it runs on until the process ends; its
+ * device address is resolved once per device when a model is created there.
+ * The call allocates nothing (no hipMalloc, no hipFree, no allocating library
+ * routine) and never synchronises.
+ *   Arguments, layouts, ownership and the device-side error flags as
+ *   nnp_energy_forces; inputs and outputs are still the caller's buffers.
+ *   Returns NNP_E_SCRATCH, before anything is launched, if the call needs
+ *   more than NNP_STATIC_SCRATCH_BYTES (nnp_workspace_bytes(model, n_atoms,
+ *   nl->capacity) gives the need: about 5,000 atoms of water with a list
+ *   sized to its pairs).
+ *   Stage timing (nnp_profile_enable) is not recorded by this call.
+ * Every call on a device shares that device's one scratch array, which keeps
+ * the last call's contents (nothing in it needs to start at zero): calls
+ * that overlap on one device (two streams, two threads) race, and the caller
+ * must serialise them. */
+nnp_status nnp_energy_forces_static(nnp_model* model, int32_t n_atoms, const float* pos,
+                                    const int32_t* species, const int32_t* mol, int32_t n_mol,
+                                    const float* box_host, const nnp_nlist* nl, double* e_mol,
+                                    float* e_atom, float* forces, void* stream);
 
 /* The AEV alone (the radial and angular features of Sec. 2.2 / App. A):
  * writes aev_out, device float32 [n_atoms][aev_stride] (aev_stride =

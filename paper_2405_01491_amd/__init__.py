@@ -265,6 +265,26 @@ def nnp_energy_forces(model, pos, species, mol=None, n_mol=1, box=None, nl=None,
     return e_mol_t, e_at, F
 
 
+def nnp_energy_forces_static(model, pos, species, mol=None, n_mol=1, box=None, nl=None, e_atom=None, forces=None,
+                             e_mol=None):
+    """nnp_energy_forces through the allocation-free entry point: the library
+    works in its fixed device scratch (NNP_STATIC_SCRATCH_BYTES), and the
+    caller passes every output buffer (e_mol float64 [n_mol], forces float32
+    [N,3] or None, e_atom float32 [N] or None), so this wrapper allocates
+    nothing when they are given.  Calls overlapping on one device race."""
+    L = lib()
+    n = pos.shape[0]
+    dev = pos.device
+    if e_mol is None:
+        e_mol = torch.empty(n_mol, dtype=torch.float64, device=dev)
+    _b, bptr = _box_arg(box)
+    with torch.cuda.device(dev):
+        check(L.nnp_energy_forces_static(model.handle, n, _ptr(pos), _ptr(species), _ptr(mol), int(n_mol), bptr,
+                                         ctypes.byref(nl.struct()), _ptr(e_mol), _ptr(e_atom), _ptr(forces),
+                                         _stream(dev)), "nnp_energy_forces_static")
+    return e_mol, e_atom, forces
+
+
 def nnp_energy_forces_ensemble(model, pos, species, mol=None, n_mol=1, box=None, nl=None, forces=True,
                                e_atom=False):
     """Ensemble-mean energies / forces plus every network's structure

@@ -10,10 +10,11 @@ c_int32_p = ctypes.POINTER(ctypes.c_int32)
 c_void_p = ctypes.c_void_p
 
 NNP_OK, NNP_E_ARG, NNP_E_CAPACITY, NNP_E_BOX, NNP_E_NONFINITE, NNP_E_NOMEM, NNP_E_BUSY, \
-    NNP_E_PENDING, NNP_E_HIP, NNP_E_ROW = range(10)
+    NNP_E_PENDING, NNP_E_HIP, NNP_E_ROW, NNP_E_SCRATCH = range(11)
 NNP_FP32, NNP_BF16_MLP = 0, 1
 STATUS_NAMES = ["NNP_OK", "NNP_E_ARG", "NNP_E_CAPACITY", "NNP_E_BOX", "NNP_E_NONFINITE",
-                "NNP_E_NOMEM", "NNP_E_BUSY", "NNP_E_PENDING", "NNP_E_HIP", "NNP_E_ROW"]
+                "NNP_E_NOMEM", "NNP_E_BUSY", "NNP_E_PENDING", "NNP_E_HIP", "NNP_E_ROW", "NNP_E_SCRATCH"]
+NNP_STATIC_SCRATCH_BYTES = 64 << 20
 NNP_MAX_ROW = 256
 NNP_MAX_ANGULAR = 96
 STAGES = ["neighbors", "group", "aev", "mlp", "energy", "aev_adjoint", "forces", "integrate"]
@@ -36,6 +37,9 @@ SIGNATURES = {
     "nnp_energy_forces": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_int32,
                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                          ctypes.c_size_t, c_void_p]),
+    "nnp_energy_forces_static": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
+                                                ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                                c_void_p]),
     "nnp_energy_forces_virial": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
                                                 ctypes.c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                                 c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),

@@ -26,6 +26,34 @@ std::mutex g_stage_mutex;
 
 }  // namespace
 
+// Fixed device scratch of nnp_energy_forces_static (callers that cannot
+// allocate).  In host code this name is only a stand-in for the symbol: the
+// device address comes from hipGetSymbolAddress, once per device, and only
+// that address is ever handed to kernels or runtime calls.
+static __device__ __align__(256) char scratch[NNP_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// the device address of `scratch` on `device` (which must be current),
+// resolved on the first call for that device
+nnp_status scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxScratchDevices) return NNP_E_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NNP_E_HIP;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return NNP_OK;
+}
+
+}  // namespace
+
 struct nnp_prof {
     bool enabled = false;
     uint32_t mask = 0;        // stages timed while enabled
@@ -220,21 +248,24 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     const MdBack* md = opts ? opts->md : nullptr;
     if (md && (!forces || virial || atom_virial)) return NNP_E_ARG;
     const RowsView rows = opts && opts->rows ? *opts->rows : rows_csr(nl);
+    const bool timed = !(opts && opts->no_profile);
+    auto pbeg = [&](int stage) { if (timed) prof_begin(m, stage, s); };
+    auto pend = [&](int stage) { if (timed) prof_end(m, stage, s); };
     if (opts && opts->rows && nl->capacity < (int64_t)n * NNP_MAX_ROW) return NNP_E_ARG;
     if (n > 0 && !(opts && opts->skip_group)) {
-        prof_begin(m, NNP_STAGE_GROUP, s);
+        pbeg(NNP_STAGE_GROUP);
         e = launch_species_group(m, n, species, W.mw, flags, s);
         // the per-layer GEMMs read padding rows; the fused kernel keeps them to their own rows
         if (e == hipSuccess && !(m->fused && !m->force_unfused))
             e = launch_zero_pad_rows(W.mw, m->aev.stride, W.aev, bf, s);
-        prof_end(m, NNP_STAGE_GROUP, s);
+        pend(NNP_STAGE_GROUP);
     }
     if (n > 0) {
-        prof_begin(m, NNP_STAGE_AEV, s);
+        pbeg(NNP_STAGE_AEV);
         if (e == hipSuccess) e = launch_aev_fwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.aev, bf, flags, s,
                                opts ? opts->rev_out : nullptr, opts ? opts->gate : nullptr, W.mw.amask);
-        prof_end(m, NNP_STAGE_AEV, s);
-        prof_begin(m, NNP_STAGE_MLP, s);
+        pend(NNP_STAGE_AEV);
+        pbeg(NNP_STAGE_MLP);
         if (e == hipSuccess) {
             if (mlp_split(m, n) && !(m->force_unfused && m->n_nets == 1))
                 e = launch_mlp_ensemble(m, W.mw, W.aev, forces ? W.g : nullptr, W.E_row, W.E_at, n, W.d1, W.E_net,
@@ -244,10 +275,10 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
             else
                 e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, W.E_at, s);
         }
-        prof_end(m, NNP_STAGE_MLP, s);
+        pend(NNP_STAGE_MLP);
     }
     if (!(md && md->fuse_energy) && !(opts && opts->skip_energy)) {
-        prof_begin(m, NNP_STAGE_ENERGY, s);
+        pbeg(NNP_STAGE_ENERGY);
         if (e == hipSuccess)
             e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at, e_mol, e_atom, flags,
                               s);
@@ -255,14 +286,14 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
         for (int k = 0; e_mol_net && k < m->n_nets && e == hipSuccess && n > 0; ++k)
             e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at_net + (size_t)k * n,
                               e_mol_net + (size_t)k * n_mol, nullptr, flags, s);
-        prof_end(m, NNP_STAGE_ENERGY, s);
+        pend(NNP_STAGE_ENERGY);
     }
     if (e == hipSuccess && forces && n > 0) {
-        prof_begin(m, NNP_STAGE_AEV_ADJ, s);
+        pbeg(NNP_STAGE_AEV_ADJ);
         float* wat = virial || atom_virial ? (atom_virial ? atom_virial : W.Wat) : nullptr;
         e = launch_aev_bwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.g, W.G, wat, flags, s);
-        prof_end(m, NNP_STAGE_AEV_ADJ, s);
-        prof_begin(m, NNP_STAGE_FORCES, s);
+        pend(NNP_STAGE_AEV_ADJ);
+        pbeg(NNP_STAGE_FORCES);
         if (e == hipSuccess) {
             if (md) {
                 // engine: gather + last half kick (+ structure energy) in one kernel
@@ -279,7 +310,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
                 e = launch_force_gather(n, rows, W.G, forces, s);
             }
         }
-        prof_end(m, NNP_STAGE_FORCES, s);
+        pend(NNP_STAGE_FORCES);
     }
     if (e == hipSuccess && virial)
         e = launch_virial(n, n_mol, W.mstart, W.mend, atom_virial ? atom_virial : W.Wat, W.vpart, virial, s);
@@ -301,6 +332,7 @@ const char* nnp_status_str(nnp_status s) {
         case NNP_E_PENDING: return "request pending";
         case NNP_E_HIP: return "HIP runtime error";
         case NNP_E_ROW: return "neighbour row longer than supported";
+        case NNP_E_SCRATCH: return "input larger than the fixed scratch of the allocation-free call";
     }
     return "unknown status";
 }
@@ -339,6 +371,14 @@ nnp_status nnp_model_create_ensemble(const nnp_aev_params* a, const nnp_mlp_para
     if (hipGetDevice(&m->device) != hipSuccess) {
         delete m;
         return NNP_E_HIP;
+    }
+    {
+        void* scratch_dev = nullptr;
+        const nnp_status st = scratch_address(m->device, &scratch_dev);
+        if (st != NNP_OK) {
+            delete m;
+            return st;
+        }
     }
     m->precision = precision;
     AevConst& P = m->aev;
@@ -585,6 +625,22 @@ nnp_status nnp_energy_forces(nnp_model* m, int32_t n, const float* pos, const in
     if (nl->n_atoms != n || nl->n_pairs > nl->capacity) return NNP_E_ARG;
     return energy_forces_impl(m, n, pos, species, mol, n_mol, box_host, nl, e_mol, e_atom, forces, ws, ws_bytes,
                               (hipStream_t)stream, m->flags);
+}
+
+nnp_status nnp_energy_forces_static(nnp_model* m, int32_t n, const float* pos, const int32_t* species,
+                                    const int32_t* mol, int32_t n_mol, const float* box_host, const nnp_nlist* nl,
+                                    double* e_mol, float* e_atom, float* forces, void* stream) {
+    if (!m || !nl || n < 0) return NNP_E_ARG;
+    if (nl->n_atoms != n || nl->n_pairs > nl->capacity) return NNP_E_ARG;
+    const size_t need = ef_layout(m, n, nl->capacity, nullptr).end;
+    if (need > NNP_STATIC_SCRATCH_BYTES) return NNP_E_SCRATCH;
+    void* ws = nullptr;
+    const nnp_status st = scratch_address(m->device, &ws);   // resolved when the model was created
+    if (st != NNP_OK) return st;
+    EfOpts opts;
+    opts.no_profile = true;
+    return energy_forces_impl(m, n, pos, species, mol, n_mol, box_host, nl, e_mol, e_atom, forces, ws,
+                              NNP_STATIC_SCRATCH_BYTES, (hipStream_t)stream, m->flags, nullptr, nullptr, &opts);
 }
 
 nnp_status nnp_energy_forces_virial(nnp_model* m, int32_t n, const float* pos, const int32_t* species,

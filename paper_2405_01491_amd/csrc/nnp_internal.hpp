@@ -182,6 +182,7 @@ struct EfOpts {
     const RowsView* rows = nullptr;
     int32_t* rev_out = nullptr;
     const int32_t* gate = nullptr;
+    bool no_profile = false;    // record no stage events (they may allocate)
 };
 // nnp_energy_forces with an explicit device flags word (n_pairs of nl is not checked)
 nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
