@@ -87,58 +87,103 @@ struct Row {
     int b, len;
 };
 
-// Load the row and classify every slot.  Returns false (and flags) if the
-// row is longer than the kernels support.
-__device__ __forceinline__ bool load_row(Row& R, const AevConst& P, int i, const float* __restrict__ pos,
+// Load row i (slots b .. e - 1) and classify every slot.  Returns false (and flags) if the
+// row is longer than the kernels support.  kPacked: the builder's
+// fixed-stride rows (packed image shifts), else the CSR list.  The loads are
+// issued in two rounds with no wait among them: every slot's column and
+// image shift, then every slot's neighbour position and species (a slot past
+// the row's end reads the row's last entry), so a row costs two dependent
+// memory round trips.  Slots past the row's end are discarded.
+template <bool kPacked>
+__device__ __forceinline__ bool load_row(Row& R, const AevConst& P, int i, int b, int e, const float* __restrict__ pos,
                                          const int32_t* __restrict__ species, const BoxConst& bx, const RowsView& rows,
                                          unsigned* flags) {
     const int l = lane_id();
-    const int b = rows.begin(i), e = rows.end(i);
     R.b = b;
     R.len = e - b;
     if (R.len > kMaxR) {
         if (l == 0) set_flag(flags, NNP_FLAG_ROW);
         return false;
     }
-    const float xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-    int j[kQ];
-    float sx[kQ], sy[kQ], sz[kQ];
+    const int last = e > b ? e - 1 : b;
+    int pc[kQ], j[kQ], s0[kQ], s1[kQ], s2[kQ];
+    bool valid[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         const int p = b + l + kWave * q;
-        j[q] = -1;
-        sx[q] = sy[q] = sz[q] = 0.f;
-        if (p < e) {
-            j[q] = rows.col[p];
-            if (bx.periodic) rows.shift3(p, sx[q], sy[q], sz[q]);
-        }
+        valid[q] = p < e;
+        pc[q] = min(p, last);
     }
-    const float rc_r2 = P.rc_r * P.rc_r, rc_a2 = P.rc_a * P.rc_a;
+    // round 1: columns and shifts.  Fixed-stride rows load every group (a
+    // slot past the row's end re-reads its last entry, or slot b of the
+    // row's own fixed-stride space: no branch, so no wait between the
+    // groups); CSR rows, whose shifts take three byte loads per slot and
+    // whose slot b need not exist for an empty row, skip the groups past the
+    // row's end (wave-uniform)
+    const int nq = (R.len + kWave - 1) / kWave;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-        R.in_r[q] = R.in_a[q] = false;
-        R.z[q] = 0;
-        R.vx[q] = R.vy[q] = R.vz[q] = R.r2[q] = 0.f;
-        if (j[q] >= 0) {
-            const int zz = species[j[q]];
-            float vx = pos[3 * j[q]] - xi, vy = pos[3 * j[q] + 1] - yi, vz = pos[3 * j[q] + 2] - zi;
-            vx += sx[q] * bx.L[0];
-            vy += sy[q] * bx.L[1];
-            vz += sz[q] * bx.L[2];
-            const float r2 = vx * vx + vy * vy + vz * vz;
-            R.vx[q] = vx;
-            R.vy[q] = vy;
-            R.vz[q] = vz;
-            R.r2[q] = r2;
-            if (zz < 0 || zz >= P.ns) {
-                set_flag(flags, NNP_FLAG_SPECIES);
+        j[q] = i;
+        s0[q] = s1[q] = s2[q] = 0;
+        if (kPacked || q < nq) {
+            j[q] = rows.col[pc[q]];
+            if (kPacked) {
+                s0[q] = rows.shift_packed[pc[q]];
             } else {
-                R.z[q] = zz;
-                R.in_r[q] = r2 < rc_r2;
-                R.in_a[q] = R.in_r[q] && r2 < rc_a2;
+                s0[q] = rows.shift[3 * pc[q]];
+                s1[q] = rows.shift[3 * pc[q] + 1];
+                s2[q] = rows.shift[3 * pc[q] + 2];
             }
         }
     }
+    // round 2: neighbour positions and species (the group count passes
+    // through readfirstlane, which keeps the compiler from merging each
+    // group's two rounds into one block with a wait inside)
+    const int nq2 = __builtin_amdgcn_readfirstlane(nq);
+    float px[kQ], py[kQ], pz[kQ];
+    int zz[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        px[q] = py[q] = pz[q] = 0.f;
+        zz[q] = 0;
+        if (kPacked || q < nq2) {
+            const int jj = valid[q] ? j[q] : i;
+            px[q] = pos[3 * jj];
+            py[q] = pos[3 * jj + 1];
+            pz[q] = pos[3 * jj + 2];
+            zz[q] = species[jj];
+        }
+    }
+    const float xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    const float rc_r2 = P.rc_r * P.rc_r, rc_a2 = P.rc_a * P.rc_a;
+    const float Lx = bx.periodic ? bx.L[0] : 0.f, Ly = bx.periodic ? bx.L[1] : 0.f, Lz = bx.periodic ? bx.L[2] : 0.f;
+    bool bad_species = false;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        float sx, sy, sz;
+        if (kPacked) {
+            sx = (float)(int8_t)(s0[q] & 0xff);
+            sy = (float)(int8_t)((s0[q] >> 8) & 0xff);
+            sz = (float)(int8_t)((s0[q] >> 16) & 0xff);
+        } else {
+            sx = (float)s0[q];
+            sy = (float)s1[q];
+            sz = (float)s2[q];
+        }
+        const float vx = (px[q] - xi) + sx * Lx, vy = (py[q] - yi) + sy * Ly, vz = (pz[q] - zi) + sz * Lz;
+        const float r2 = vx * vx + vy * vy + vz * vz;
+        const bool ok_z = zz[q] >= 0 && zz[q] < P.ns;
+        bad_species |= valid[q] && !ok_z;
+        const bool use = valid[q] && ok_z;
+        R.vx[q] = valid[q] ? vx : 0.f;
+        R.vy[q] = valid[q] ? vy : 0.f;
+        R.vz[q] = valid[q] ? vz : 0.f;
+        R.r2[q] = valid[q] ? r2 : 0.f;
+        R.z[q] = use ? zz[q] : 0;
+        R.in_r[q] = use && r2 < rc_r2;
+        R.in_a[q] = use && r2 < rc_a2;
+    }
+    if (bad_species) set_flag(flags, NNP_FLAG_SPECIES);
     return true;
 }
 
@@ -197,17 +242,43 @@ __device__ __forceinline__ bool group_species(const Row& R, int ns, int* pos_r, 
 
 // ---------------------------------------------------------------- forward
 
+constexpr int kMaxBins = kMaxSpecies * (kMaxSpecies + 1) / 2;   // species pairs
+
+// Sum of v over the lanes l, l ^ 8, l ^ 16, l ^ 32, ... (the lanes that share
+// l's bits 0-2): a DPP rotation within each 16-lane row for 8, then the
+// gfx950 row and half swaps for 16 and 32.  Every lane receives the sum.
+__device__ __forceinline__ float sum_over_rows_and_halves(float v, bool with8) {
+    if (with8) v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+    const auto h16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(h16[0]) + __uint_as_float(h16[1]);
+    const auto h32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(h32[0]) + __uint_as_float(h32[1]);
+}
+
+// v of lane l ^ x within the lane's quad (x = 1 or 2), by DPP
+__device__ __forceinline__ float quad_xor(float v, int x) {
+    return x == 1 ? __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false))
+                  : __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false));
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_inclusive_sum(int v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int u = __shfl_up(v, d, kWave);
+        if (l >= d) v += u;
+    }
+    return v;
+}
+
 struct FwdLds {
     float4 au[kMaxA];          // angular list: unit vector, r
     float afc[kMaxA];
     // the radial list is read only before the angular pair tile is first
-    // written, so the two share their space (5 KB per wave, not 7: eight
-    // waves per SIMD instead of five)
+    // written, so the two share their space
     union {
-        struct {
-            float rr[kMaxR];   // radial list: r, fc (species-grouped)
-            float rfc[kMaxR];
-        } rad;
+        float2 rad[kMaxR];     // radial list: (r, fc), species-grouped
         struct {
             alignas(16) float f1[kWave][kNz];   // pair tile: 8 angle factors
             float f2[kWave][kNa];               // 4 radial factors times 2 fc fc
@@ -215,9 +286,24 @@ struct FwdLds {
     };
     int seg_r[kMaxSpecies + 1];
     int seg_a[kMaxSpecies + 1];
+    // species-pair bins that hold at least one pair, in bin order: the
+    // offset of each bin's first pair in the packed pair sequence, and the
+    // bin's index and species (p | s << 8 | t << 16)
+    int bin_off[kMaxBins + 1];
+    int bin_info[kMaxBins];
 };
 
-template <typename OutT>
+// (s, t), s <= t, of species-pair bin p in row-major triangle order
+__device__ __forceinline__ void bin_species(int p, int ns, int& s, int& t) {
+    s = 0;
+    while (p >= ns - s) {
+        p -= ns - s;
+        ++s;
+    }
+    t = s + p;
+}
+
+template <typename OutT, bool kPacked>
 __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
     const RowsView rows, const int32_t* __restrict__ out_row, OutT* __restrict__ out, unsigned* flags,
@@ -228,13 +314,18 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     const int i = blockIdx.x * kWaves + w;
     if (i >= n) return;
     FwdLds& S = lds[w];
+    // the row's extent and grouped row, loaded ahead of the rebuild gate
+    const int rb = rows.begin(i), re = rows.end(i);
+    const int row = out_row ? out_row[i] : i;
     // fixed-stride rows just rebuilt: the reverse index of this row (the rows
     // are sorted by neighbour, so j's slot of i is found by bisection).  A lane
     // searches the rows of its pairs p and p + 64 side by side, so that the
     // dependent loads of the two searches are in flight together; a finished
-    // search issues no load.
+    // search issues no load.  A pair whose reverse is absent (a list that is
+    // not symmetric) is flagged and left pointing at itself.
     if (rev_out && (!gate || *gate)) {
-        const int b = rows.begin(i), e = rows.end(i);
+        const int b = rb, e = re;
+        bool missing = false;
         for (int p0 = b + l; p0 < e; p0 += 2 * kWave) {
             const int p1 = p0 + kWave;
             const bool two = p1 < e;
@@ -255,19 +346,25 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
                     if (c1 < i) lo1 = m1 + 1; else hi1 = m1;
                 }
             }
-            rev_out[p0] = (lo0 < e0 && rows.col[lo0] == i) ? lo0 : p0;
-            if (two) rev_out[p1] = (lo1 < e1 && rows.col[lo1] == i) ? lo1 : p1;
+            const bool f0 = lo0 < e0 && rows.col[lo0] == i;
+            rev_out[p0] = f0 ? lo0 : p0;
+            missing |= !f0;
+            if (two) {
+                const bool f1 = lo1 < e1 && rows.col[lo1] == i;
+                rev_out[p1] = f1 ? lo1 : p1;
+                missing |= !f1;
+            }
         }
+        if (missing) set_flag(flags, NNP_FLAG_REVERSE);
     }
-    const int row = out_row ? out_row[i] : i;
-    if (row < 0) return;   // atom without a grouped row (invalid species, flagged elsewhere)
-    OutT* orow = out + (size_t)row * P.stride;
     const int ns = P.ns;
     Row R;
     int pr_[kQ], pa_[kQ];
     unsigned present = 0;
-    if (!load_row(R, P, i, pos, species, bx, rows, flags) ||
-        !group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, &present, flags)) {
+    const bool loaded = load_row<kPacked>(R, P, i, rb, re, pos, species, bx, rows, flags);
+    if (row < 0) return;   // atom without a grouped row (invalid species, flagged elsewhere)
+    OutT* orow = out + (size_t)row * P.stride;
+    if (!loaded || !group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, &present, flags)) {
         for (int c = l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
         if (amask && l == 0) amask[i] = 0xffffu;
         return;
@@ -277,8 +374,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     for (int q = 0; q < kQ; ++q) {
         if (pr_[q] >= 0) {
             const float r = hw_sqrt(R.r2[q]);
-            S.rad.rr[pr_[q]] = r;
-            S.rad.rfc[pr_[q]] = cutoff_fc(r, P.pi_rc_r);
+            S.rad[pr_[q]] = make_float2(r, cutoff_fc(r, P.pi_rc_r));
             if (pa_[q] >= 0) {
                 const float inv = r > 0.f ? hw_rcp(r) : 0.f;
                 S.au[pa_[q]] = make_float4(R.vx[q] * inv, R.vy[q] * inv, R.vz[q] * inv, r);
@@ -287,102 +383,135 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
         }
     }
     wave_sync();
-    // ---- radial: lane = (k, q); species segments in order
+    // exp(-eta x^2) as exp2(c x^2)
+    const float c_r = -P.eta_r * 1.44269504088896341f, c_a = -P.eta_a * 1.44269504088896341f;
+    // ---- radial: lane = (k, q); only the species present in the row
     {
         const int k = l & 15, q = l >> 4;
         const float rk = P.shf_r[k];
-        for (int s = 0; s < ns; ++s) {
-            if (!((present >> s) & 1u)) {   // wave-uniform: no neighbour of this species
-                if (q == 0) store_out(orow + 16 * s + k, 0.f);
-                continue;
-            }
+        for (unsigned m = present & 0xffu; m; m &= m - 1u) {
+            const int s = __builtin_ctz(m);
             const int sb = S.seg_r[s], se = S.seg_r[s + 1];
             float acc = 0.f;
-            for (int m = sb + q; m < se; m += 4) {
-                const float d = S.rad.rr[m] - rk;
-                acc += __expf(-P.eta_r * d * d) * S.rad.rfc[m];
+            for (int j = sb + q; j < se; j += 4) {
+                const float2 e = S.rad[j];
+                const float d = e.x - rk;
+                acc += hw_exp2(c_r * d * d) * e.y;
             }
-            acc += shfl_xor(acc, 16);
-            acc += shfl_xor(acc, 32);
+            acc = sum_over_rows_and_halves(acc, false);
             if (q == 0) store_out(orow + 16 * s + k, P.pr * acc);
         }
     }
+    // ---- the bins that hold a pair: lane p counts bin p's pairs
+    const int nbins = ns * (ns + 1) / 2;
+    int bs_ = 0, bt_ = 0, cnt = 0;
+    if (l < nbins) {
+        bin_species(l, ns, bs_, bt_);
+        const int cs_ = S.seg_a[bs_ + 1] - S.seg_a[bs_];
+        cnt = bs_ == bt_ ? cs_ * (cs_ - 1) / 2 : cs_ * (S.seg_a[bt_ + 1] - S.seg_a[bt_]);
+    }
+    const unsigned long long binmask = ballot(cnt > 0);
+    const int n_act = __popcll(binmask);
+    const int incl = wave_inclusive_sum(cnt);
+    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
     wave_sync();   // the radial list is read; its space becomes the pair tile
-    // ---- angular: one species-pair bin at a time, one pair per lane into an
-    // LDS tile; then lane (ra, rz, rq) sums f1[z] f2[ra] for the four angle
-    // sections z = 4 rz .. 4 rz + 3 over the tile's pairs rq, rq + 8, ...,
-    // and a three-stage butterfly over rq completes each bin
-    const int az = l & 31, half = l >> 5;
+    if (cnt > 0) {
+        const int rank = rank_below(binmask);
+        S.bin_off[rank] = incl - cnt;
+        S.bin_info[rank] = l | (bs_ << 8) | (bt_ << 16);
+    }
+    if (l == 0) S.bin_off[n_act] = total;
+    wave_sync();
+    // ---- angular: the pairs of every non-empty bin in one packed sequence,
+    // 64 at a time, one per lane, into an LDS tile; then lane (ra, rz, rq)
+    // sums f1[z] f2[ra] over the tile's pairs rq, rq + 8, ... of each bin for
+    // the four angle sections z = 4 rz .. 4 rz + 3, carrying a bin's partial
+    // sums into the next tile, and a butterfly over rq completes the bin
     const int ra = l & 3, rz = (l >> 2) & 1, rq = l >> 3;
-    int p = 0;
-    for (int s = 0; s < ns; ++s) {
-        const int bs = S.seg_a[s], cs_ = S.seg_a[s + 1] - bs;
-        for (int t = s; t < ns; ++t, ++p) {
-            if (!((present >> (8 + s)) & (present >> (8 + t)) & 1u)) {   // wave-uniform: an empty bin
-                if (half == 0) store_out(orow + P.radial_dim + 32 * p + az, 0.f);
-                continue;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    int cb = 0;   // first bin not yet complete (wave-uniform)
+    for (int u0 = 0; u0 < total; u0 += kWave) {
+        const int u = u0 + l;
+        if (u < total) {
+            int b = cb;
+            while (b + 1 < n_act && S.bin_off[b + 1] <= u) ++b;
+            const int info = S.bin_info[b];
+            const int s = (info >> 8) & 0xff, t = (info >> 16) & 0xff;
+            const int v = u - S.bin_off[b];
+            const int bs = S.seg_a[s];
+            int ja, ka;
+            if (s == t) {
+                tri_decode(v, S.seg_a[s + 1] - bs, ja, ka);
+                ja += bs;
+                ka += bs;
+            } else {
+                // v = j' ct + k': the float quotient, corrected to the exact one
+                const int bt = S.seg_a[t], ct = S.seg_a[t + 1] - bt;
+                int qd = (int)((float)v * hw_rcp((float)ct));
+                qd -= __mul24(qd, ct) > v;
+                qd += __mul24(qd + 1, ct) <= v;
+                ja = bs + qd;
+                ka = bt + (v - __mul24(qd, ct));
             }
-            const int bt = S.seg_a[t], ct = S.seg_a[t + 1] - bt;
-            const int np_ = (s == t) ? cs_ * (cs_ - 1) / 2 : cs_ * ct;
-            const float inv_ct = hw_rcp((float)ct);
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
-            for (int u0 = 0; u0 < np_; u0 += kWave) {
-                const int u = u0 + l;
-                if (u < np_) {
-                    int ja, ka;
-                    if (s == t) {
-                        tri_decode(u, cs_, ja, ka);
-                        ja += bs;
-                        ka += bs;
-                    } else {
-                        // u = j' ct + k': the float quotient, corrected to the exact one
-                        int qd = (int)((float)u * inv_ct);
-                        qd -= __mul24(qd, ct) > u;
-                        qd += __mul24(qd + 1, ct) <= u;
-                        ja = bs + qd;
-                        ka = bt + (u - __mul24(qd, ct));
-                    }
-                    const float4 A = S.au[ja], B = S.au[ka];
-                    float c = A.x * B.x + A.y * B.y + A.z * B.z;
-                    c = fminf(1.f, fmaxf(-1.f, c));
-                    const float uu = P.cs * c;
-                    const float sq = hw_sqrt(1.f - uu * uu);
-                    const float rbar = 0.5f * (A.w + B.w);
-                    const float w2 = 2.f * S.afc[ja] * S.afc[ka];
+            const float4 A = S.au[ja], B = S.au[ka];
+            float c = A.x * B.x + A.y * B.y + A.z * B.z;
+            c = fminf(1.f, fmaxf(-1.f, c));
+            const float uu = P.cs * c;
+            const float sq = hw_sqrt(1.f - uu * uu);
+            const float rbar = 0.5f * (A.w + B.w);
+            const float w2 = 2.f * S.afc[ja] * S.afc[ka];
 #pragma unroll
-                    for (int a = 0; a < kNa; ++a) {
-                        const float d = rbar - P.shf_a[a];
-                        S.tile.f2[l][a] = w2 * __expf(-P.eta_a * d * d);
-                    }
+            for (int a = 0; a < kNa; ++a) {
+                const float d = rbar - P.shf_a[a];
+                S.tile.f2[l][a] = w2 * hw_exp2(c_a * d * d);
+            }
 #pragma unroll
-                    for (int z = 0; z < kNz; ++z)
-                        S.tile.f1[l][z] = pow_zeta(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), P.zeta);
+            for (int z = 0; z < kNz; ++z)
+                S.tile.f1[l][z] = pow_zeta(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), P.zeta);
+        }
+        wave_sync();
+        const int u1 = min(u0 + kWave, total);
+        for (int b = cb; b < n_act; ++b) {
+            const int off = __builtin_amdgcn_readfirstlane(S.bin_off[b]);
+            if (off >= u1) break;
+            const int end = __builtin_amdgcn_readfirstlane(S.bin_off[b + 1]);
+            const int lo = max(off, u0) - u0, hi = min(end, u1) - u0;
+            for (int m = lo + ((rq - lo) & 7); m < hi; m += 8) {
+                const float4 f1v = *(const float4*)&S.tile.f1[m][4 * rz];
+                const float f2v = S.tile.f2[m][ra];
+                acc[0] += f1v.x * f2v;
+                acc[1] += f1v.y * f2v;
+                acc[2] += f1v.z * f2v;
+                acc[3] += f1v.w * f2v;
+            }
+            if (end <= u1) {   // the bin is complete
+                const int p = __builtin_amdgcn_readfirstlane(S.bin_info[b]) & 0xff;
+#pragma unroll
+                for (int x = 0; x < 4; ++x) acc[x] = sum_over_rows_and_halves(acc[x], true);
+                if (rq == 0) {
+                    OutT* o = orow + P.radial_dim + 32 * p + 8 * ra + 4 * rz;
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) store_out(o + x, acc[x]);
                 }
-                wave_sync();
-                const int nv = min(kWave, np_ - u0);
-                for (int m = rq; m < nv; m += 8) {
-                    const float4 f1v = *(const float4*)&S.tile.f1[m][4 * rz];
-                    const float f2v = S.tile.f2[m][ra];
-                    acc[0] += f1v.x * f2v;
-                    acc[1] += f1v.y * f2v;
-                    acc[2] += f1v.z * f2v;
-                    acc[3] += f1v.w * f2v;
-                }
-                wave_sync();
-            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                acc[i] += shfl_xor(acc[i], 8);
-                acc[i] += shfl_xor(acc[i], 16);
-                acc[i] += shfl_xor(acc[i], 32);
-            }
-            if (rq == 0) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) store_out(orow + P.radial_dim + 32 * p + 8 * ra + 4 * rz + i, acc[i]);
+                for (int x = 0; x < 4; ++x) acc[x] = 0.f;
+                cb = b + 1;
             }
         }
+        wave_sync();
     }
-    for (int c = P.dim + l; c < P.stride; c += kWave) store_out(orow + c, 0.f);
+    // ---- zeros for every other 16-feature block (species absent from the
+    // row, bins without a pair, padding columns), 16 bytes per lane store
+    constexpr int kPer16 = 16 / (int)sizeof(OutT);       // features per 16-byte store
+    const int nblk_r = ns, nblk = P.dim / 16;
+    for (int c = l; c < P.stride / kPer16; c += kWave) {
+        const int blk = (c * kPer16) >> 4;
+        bool live;
+        if (blk < nblk_r) live = (present >> blk) & 1u;
+        else if (blk < nblk) live = (binmask >> ((blk - nblk_r) >> 1)) & 1ull;
+        else live = false;
+        if (!live) *(uint4*)(orow + c * kPer16) = make_uint4(0u, 0u, 0u, 0u);
+    }
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -394,6 +523,7 @@ struct BwdLds {
     float afc[kMaxA], adfc[kMaxA];
     int azs[kMaxA];             // species | slot << 8
     union {
+        float2 rl[kMaxR];       // first: radial list (r, species bits), then (dE/dr, -)
         float pb[kPairTile][6]; // pair tile: contributions to the two edges
         float ga[kMaxA][3];     // then: angular gradient per angular neighbour
     };
@@ -404,7 +534,7 @@ struct BwdLds {
 
 // kVir: also the per-centre virial W_i = -sum_j v_ij (outer) G_ij, row-major
 // [n][9] (the strain derivative of E_i is -W_i transposed).
-template <bool kVir>
+template <bool kVir, bool kPacked>
 __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
     const RowsView rows, const int32_t* __restrict__ g_row, const float* __restrict__ g, float4* __restrict__ G,
@@ -420,7 +550,7 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
     int pr_[kQ], pa_[kQ];
     unsigned present = 0;
     const int row = g_row ? g_row[i] : i;
-    const bool ok = load_row(R, P, i, pos, species, bx, rows, flags) &&
+    const bool ok = load_row<kPacked>(R, P, i, rows.begin(i), rows.end(i), pos, species, bx, rows, flags) &&
                     group_species(R, ns, pr_, pa_, S.seg_r, S.seg_a, &present, flags) && row >= 0;
     if (!ok) {
         const int b = rows.begin(i), e = rows.end(i);
@@ -437,11 +567,12 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
         const int slot = l + kWave * q;
         if (slot < R.len) S.amap[slot] = 255;
     }
-    // angular list entries
+    // angular list entries; the radial list (r and species, species-grouped)
     float r_[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         r_[q] = hw_sqrt(R.r2[q]);
+        if (pr_[q] >= 0) S.rl[pr_[q]] = make_float2(r_[q], __int_as_float(R.z[q]));
         if (pa_[q] >= 0) {
             const float r = r_[q];
             const float inv = r > 0.f ? hw_rcp(r) : 0.f;
@@ -452,37 +583,65 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
         }
     }
     wave_sync();
-    // ---- radial gradient by the lane holding the slot
+    // ---- radial dE/dr, one radial-list entry per lane (the list holds only
+    // the pairs within Rc_R, so the lanes are full up to its length):
+    //   dE/dr = p_R sum_k g_k e_k (-2 eta_R (r - R_k) fc + fc')
+    //         = p_R (-2 eta_R fc sum_k g_k e_k (r - R_k) + fc' sum_k g_k e_k)
+    const float c_r = -P.eta_r * 1.44269504088896341f;   // exp(-eta x^2) = exp2(c_r x^2)
+    const int n_r = S.seg_r[ns];
+    for (int m = l; m < n_r; m += kWave) {
+        const float2 e = S.rl[m];
+        const float r = e.x;
+        const float4* __restrict__ g4 = (const float4*)(grow + 16 * __float_as_int(e.y));
+        float gk[kNr];
+#pragma unroll
+        for (int v = 0; v < kNr / 4; ++v) {
+            const float4 q4 = g4[v];
+            gk[4 * v] = q4.x;
+            gk[4 * v + 1] = q4.y;
+            gk[4 * v + 2] = q4.z;
+            gk[4 * v + 3] = q4.w;
+        }
+        float a1 = 0.f, a2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kNr; ++k) {
+            const float d = r - P.shf_r[k];
+            const float ge = gk[k] * hw_exp2(c_r * d * d);
+            a1 = fmaf(ge, d, a1);
+            a2 += ge;
+        }
+        const float fc = cutoff_fc(r, P.pi_rc_r);
+        const float dfc = -0.5f * P.pi_rc_r * __sinf(P.pi_rc_r * r);
+        S.rl[m].x = P.pr * (-2.f * P.eta_r * fc * a1 + dfc * a2);
+    }
+    wave_sync();
+    // ---- radial gradient of each slot: dE/dr times the unit vector
     float gx[kQ], gy[kQ], gz[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         gx[q] = gy[q] = gz[q] = 0.f;
-        if (R.in_r[q]) {
+        if (pr_[q] >= 0) {
             const float r = r_[q];
-            const float fc = cutoff_fc(r, P.pi_rc_r);
-            const float dfc = -0.5f * P.pi_rc_r * __sinf(P.pi_rc_r * r);
-            const float* gs = grow + 16 * R.z[q];
-            float dEdr = 0.f;
-#pragma unroll
-            for (int k = 0; k < kNr; ++k) {
-                const float d = r - P.shf_r[k];
-                const float ek = __expf(-P.eta_r * d * d);
-                dEdr += gs[k] * ek * (-2.f * P.eta_r * d * fc + dfc);
-            }
-            dEdr *= P.pr;
+            const float dEdr = S.rl[pr_[q]].x;
             const float inv = r > 0.f ? hw_rcp(r) : 0.f;
             gx[q] = dEdr * R.vx[q] * inv;
             gy[q] = dEdr * R.vy[q] * inv;
             gz[q] = dEdr * R.vz[q] * inv;
         }
     }
+    wave_sync();   // the radial list is read; its space becomes the pair tile
     // ---- angular: unordered pairs (j < k) of the species-grouped list in
     // triangle order, one per lane, into a tile of up to kPairTile pairs; then
     // every angular neighbour m sums its contributions from the tile in a
     // fixed order: pairs (j, m) by ascending j, then pairs (m, k) by ascending k
     const int n_a = S.seg_a[ns];
     const int total = n_a * (n_a - 1) / 2;
+    const float c_a = -P.eta_a * 1.44269504088896341f, m2eta_a = -2.f * P.eta_a;
+    const float zm1 = P.zeta - 1.f, l2hz = __log2f(0.5f * P.zeta);   // dF1/dw = 2^((zeta-1) log2 w + log2(zeta/2))
     float ax_[2] = {0.f, 0.f}, ay_[2] = {0.f, 0.f}, az_[2] = {0.f, 0.f};
+    // lanes per angular neighbour in the per-neighbour sums: 4 up to 16
+    // neighbours, 2 up to 32, else 1 (wave-uniform)
+    const int lp = n_a <= 16 ? 2 : (n_a <= 32 ? 1 : 0);
     for (int c0 = 0; c0 < total; c0 += kPairTile) {
         const int c1 = min(c0 + kPairTile, total);
         for (int u0 = c0; u0 < c1; u0 += kWave) {
@@ -515,13 +674,12 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
 #pragma unroll
                 for (int a = 0; a < kNa; ++a) {
                     const float d = rbar - P.shf_a[a];
-                    F2[a] = __expf(-P.eta_a * d * d);
-                    dF2[a] = -2.f * P.eta_a * d * F2[a];
+                    F2[a] = hw_exp2(c_a * d * d);
+                    dF2[a] = m2eta_a * d * F2[a];
                 }
                 float Rz[kNa] = {0.f, 0.f, 0.f, 0.f};
                 float sum_c = 0.f, Ssum = 0.f;
                 const float us = uu * hw_rcp(sq);                 // u / sqrt(1 - u^2)
-                const float zm1 = P.zeta - 1.f, l2hz = __log2f(0.5f * P.zeta);
 #pragma unroll
                 for (int z = 0; z < kNz; ++z) {
                     // base^zeta and its derivative (zeta/2) base^(zeta-1), the factor
@@ -562,14 +720,16 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
             }
         }
         wave_sync();
+        // lanes (m, part): the 2^lp lanes of neighbour m take every 2^lp-th
+        // j, and their partial sums are combined after the last tile
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            if (q * kWave >= n_a) break;   // wave-uniform
-            const int m = l + q * kWave;
+            if (q * kWave >= (n_a << lp)) break;   // wave-uniform
+            const int m = (l >> lp) + q * kWave;
             const int Tm = __mul24(m, 2 * n_a - m - 1) >> 1;   // first pair (m, m + 1)
-            int Tj = 0;                                 // first pair (j, j + 1)
-            for (int j = 0; j + 1 < n_a; ++j) {
+            for (int j = l & ((1 << lp) - 1); j + 1 < n_a; j += 1 << lp) {
                 const bool before = j < m;              // pair (j, m), else pair (m, j + 1)
+                const int Tj = __mul24(j, 2 * n_a - j - 1) >> 1;   // first pair (j, j + 1)
                 const int t = before ? Tj + (m - j - 1) : Tm + (j - m);
                 if (m < n_a && t >= c0 && t < c1) {
                     const float* e = &S.pb[0][0] + __mul24(t - c0, 6) + (before ? 3 : 0);
@@ -577,16 +737,26 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
                     ay_[q] += e[1];
                     az_[q] += e[2];
                 }
-                Tj += n_a - j - 1;
             }
         }
         wave_sync();
     }
+    // the 2^lp partial sums of each neighbour (lanes adjacent in a quad)
+    if (lp >= 1) {
+        ax_[0] += quad_xor(ax_[0], 1);
+        ay_[0] += quad_xor(ay_[0], 1);
+        az_[0] += quad_xor(az_[0], 1);
+    }
+    if (lp >= 2) {
+        ax_[0] += quad_xor(ax_[0], 2);
+        ay_[0] += quad_xor(ay_[0], 2);
+        az_[0] += quad_xor(az_[0], 2);
+    }
     // the tile is dead: its space now holds the per-neighbour sums
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int m = l + q * kWave;
-        if (m < n_a) {
+        const int m = (l >> lp) + q * kWave;
+        if (m < n_a && (l & ((1 << lp) - 1)) == 0) {
             S.ga[m][0] = ax_[q];
             S.ga[m][1] = ay_[q];
             S.ga[m][2] = az_[q];
@@ -641,12 +811,18 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
                           hipStream_t s, int32_t* rev_out, const int32_t* gate, uint32_t* amask_out) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
-    if (bf16)
-        k_aev_fwd<uint16_t><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, out_row, (uint16_t*)out,
-                                                            flags, rev_out, gate, amask_out);
-    else
-        k_aev_fwd<float><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, out_row, (float*)out, flags,
-                                                         rev_out, gate, amask_out);
+    const bool packed = rows.row_ptr == nullptr;
+#define NNP_AEV_FWD(T, PK) \
+    k_aev_fwd<T, PK><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, out_row, (T*)out, flags, rev_out, \
+                                                     gate, amask_out)
+    if (bf16) {
+        if (packed) NNP_AEV_FWD(uint16_t, true);
+        else NNP_AEV_FWD(uint16_t, false);
+    } else {
+        if (packed) NNP_AEV_FWD(float, true);
+        else NNP_AEV_FWD(float, false);
+    }
+#undef NNP_AEV_FWD
     return hipGetLastError();
 }
 
@@ -655,12 +831,17 @@ hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int3
                           float* atom_virial, unsigned* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
-    if (atom_virial)
-        k_aev_bwd<true><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, G,
-                                                        atom_virial, flags);
-    else
-        k_aev_bwd<false><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, G, nullptr,
-                                                         flags);
+    const bool packed = rows.row_ptr == nullptr;
+#define NNP_AEV_BWD(V, PK) \
+    k_aev_bwd<V, PK><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, G, atom_virial, flags)
+    if (atom_virial) {
+        if (packed) NNP_AEV_BWD(true, true);
+        else NNP_AEV_BWD(true, false);
+    } else {
+        if (packed) NNP_AEV_BWD(false, true);
+        else NNP_AEV_BWD(false, false);
+    }
+#undef NNP_AEV_BWD
     return hipGetLastError();
 }
 
