@@ -72,23 +72,6 @@ __device__ __forceinline__ float celu(float v, float alpha, float ia) {
 }
 __device__ __forceinline__ float celu_grad_from_h(float h, float ia) { return h > 0.f ? 1.f : fmaf(h, ia, 1.f); }
 
-// one MFMA k-step: A fragment from LDS activations (row stride ld), B fragment given
-template <bool BF>
-__device__ __forceinline__ f32x4 mfma_step(const typename Cfg<BF>::act_t* act, int ld, int row, int k, const void* bfrag,
-                                           f32x4 c);
-template <>
-__device__ __forceinline__ f32x4 mfma_step<false>(const float* act, int ld, int row, int k, const void* bfrag,
-                                                  f32x4 c) {
-    const float a = act[row * ld + k];
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, *(const float*)bfrag, c, 0, 0, 0);
-}
-template <>
-__device__ __forceinline__ f32x4 mfma_step<true>(const uint16_t* act, int ld, int row, int k, const void* bfrag,
-                                                 f32x4 c) {
-    const bf16x8 a = *(const bf16x8*)(act + row * ld + k);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, *(const bf16x8*)bfrag, c, 0, 0, 0);
-}
-
 // B fragments of one k-step (FP32: 16 k, four MFMA k-steps; BF16: 32 k)
 template <bool BF>
 struct Frag;
@@ -105,36 +88,61 @@ struct Frag<true> {
     static constexpr int kK = 32;
 };
 
-// The MFMAs of k-step kq: acc[mb][nb] += A[16 mb.., kq] B[kq, nb] with A from
-// LDS (row stride ld) and the B fragments given.
-template <bool BF, int MB, int NCB>
-__device__ __forceinline__ void mfma_kstep(const typename Cfg<BF>::act_t* act, int ld, int kq,
-                                           const typename Frag<BF>::reg_t (&b)[NCB], f32x4 (&acc)[MB][NCB]) {
+// A fragments of one k-step, one 16-byte LDS read per 16-row block: FP32,
+// the four values a lane feeds the four 16x16x4 MFMAs of the step (features
+// 16 kq + 4 (l / 16) .. + 3; the packed weights use the same order within the
+// step); BF16, the eight values of one 16x16x32 MFMA.
+template <bool BF>
+struct AFrag;
+template <>
+struct AFrag<false> {
+    typedef f32x4 type;
+};
+template <>
+struct AFrag<true> {
+    typedef bf16x8 type;
+};
+
+template <bool BF, int MB>
+__device__ __forceinline__ void load_a(const typename Cfg<BF>::act_t* act, int ld, int kq,
+                                       typename AFrag<BF>::type (&a)[MB]) {
     const int l = lane_id();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        if (!BF)
+            a[mb] = *(const typename AFrag<BF>::type*)((const float*)act + (16 * mb + (l & 15)) * ld + 16 * kq +
+                                                       4 * (l >> 4));
+        else
+            a[mb] = *(const typename AFrag<BF>::type*)((const uint16_t*)act + (16 * mb + (l & 15)) * ld + 32 * kq +
+                                                       8 * (l >> 4));
+    }
+}
+
+// The MFMAs of one k-step: acc[mb][nb] += A[16 mb.., step] B[step, nb] from
+// the A fragments and B fragments given.
+template <bool BF, int MB, int NCB>
+__device__ __forceinline__ void mfma_kstep(const typename AFrag<BF>::type (&a)[MB],
+                                           const typename Frag<BF>::reg_t (&b)[NCB], f32x4 (&acc)[MB][NCB]) {
     if (!BF) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = 16 * kq + 4 * j + (l >> 4);
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
-                const float a = ((const float*)act)[(16 * mb + (l & 15)) * ld + k];
+                const f32x4 av = __builtin_bit_cast(f32x4, a[mb]);
 #pragma unroll
                 for (int nb = 0; nb < NCB; ++nb) {
                     const f32x4 bq = __builtin_bit_cast(f32x4, b[nb]);
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq[j], acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bq[j], acc[mb][nb], 0, 0, 0);
                 }
             }
-        }
     } else {
-        const int k = 32 * kq + 8 * (l >> 4);
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const bf16x8 a = *(const bf16x8*)((const uint16_t*)act + (16 * mb + (l & 15)) * ld + k);
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NCB; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b[nb]),
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[mb]),
+                                                                      __builtin_bit_cast(bf16x8, b[nb]),
                                                                       acc[mb][nb], 0, 0, 0);
-        }
     }
 }
 
@@ -187,6 +195,15 @@ __device__ __forceinline__ void gemm_run(const typename Cfg<BF>::act_t* act, int
 #pragma unroll
             for (int nb = 0; nb < NCB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
+    // FP32 with up to two 16-row blocks: the A fragments one k-step ahead,
+    // in a ring indexed like the B ring (slot indices known at compile time;
+    // two slots live at a time).  BF16, and four row blocks, read theirs at
+    // the step among its MFMAs: their ring would cost the registers of a
+    // wave per SIMD (BF16, 32 rows: 180 against 168 VGPRs, two waves per
+    // SIMD instead of three) or spill (64 rows)
+    constexpr bool kAhead = !BF && MB <= 2;
+    typename AFrag<BF>::type a[kAhead ? RS : 1][MB];
+    if (kAhead) load_a<BF, MB>(act, ld, 0, a[0]);
     for (int k0 = 0; k0 < NK; k0 += RS) {
 #pragma unroll
         for (int u = 0; u < RS; ++u) {
@@ -196,8 +213,10 @@ __device__ __forceinline__ void gemm_run(const typename Cfg<BF>::act_t* act, int
                 for (int nb = 0; nb < NCB; ++nb)
                     p.rb[(u + 2) % RS][nb] = p.B[((size_t)p.blk[nb] * NK + kq + 2) * 64 + l];
             }
-            __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
-            mfma_kstep<BF, MB, NCB>(act, ld, kq, p.rb[u], acc);
+            if (kAhead && kq + 1 < NK) load_a<BF, MB>(act, ld, kq + 1, a[kAhead ? (u + 1) % RS : 0]);
+            __builtin_amdgcn_sched_barrier(0);   // keep the prefetches ahead of this step's MFMAs
+            if (!kAhead) load_a<BF, MB>(act, ld, kq, a[0]);
+            mfma_kstep<BF, MB, NCB>(a[kAhead ? u : 0], p.rb[u], acc);
         }
     }
 }
@@ -254,6 +273,19 @@ struct FusedArgs {
     // 8-15 angular); null: every feature block may be non-zero
     const uint32_t* amask;
 };
+
+constexpr int kXcds = 8;   // accelerator complex dies of one MI355X, each with its own L2
+
+// The tile of this block.  A launch's blocks are dealt to the XCDs in turn
+// (block b runs on XCD b mod 8); each XCD takes a contiguous range of tiles,
+// so that tiles of one species, which stream the same weight packs, share
+// an XCD's L2 instead of every L2 holding every species' packs.  The grid
+// (x) is padded to a multiple of 8 blocks; the map is a bijection of the
+// padded range, and a block past the last tile exits.
+__device__ __forceinline__ int xcd_tile(int n_tiles) {
+    const int per = (n_tiles + kXcds - 1) / kXcds;
+    return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
 
 // The 16-feature blocks (bit b: features 16 b .. 16 b + 15) that some atom of
 // the tile rows row0 .. row0 + TM - 1 can have non-zero: a species' radial
@@ -326,9 +358,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
     __shared__ __attribute__((aligned(16))) char smem[kLdsBytes];
     __shared__ float epart[TM][4];
     act_t* act = (act_t*)smem;
-    const int row0 = blockIdx.x * TM;
+    const int tile = xcd_tile((A.rows + TM - 1) / TM);
+    const int row0 = tile * TM;
     const int32_t* meta = A.meta;
-    if (row0 >= meta[8 + A.ns]) return;
+    if (row0 >= A.rows || row0 >= meta[8 + A.ns]) return;
     int s = 0;
     for (int q = 1; q < A.ns; ++q)
         if (meta[8 + q] <= row0) s = q;
@@ -456,12 +489,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_mlp_fused(const FusedArgs A) {
                 const int c = c0 + cc;
                 if (c + 1 < nch) gload(c + 1);
                 const act_t* cur = stage + (c & 1) * TM * CLD;
+                // one k-step ahead within the chunk (as in gemm_run)
+                constexpr bool kAhead = !BF && MB <= 2;
+                typename AFrag<BF>::type a[2][MB];
+                if (kAhead) load_a<BF, MB>(cur, CLD, 0, a[0]);
 #pragma unroll
                 for (int kq = 0; kq < TPC; ++kq) {
                     const int e = c * TPC + kq, slot = (cc * TPC + kq) % RS;
                     if (e + PD < nk) loadB(e + PD, rb[(slot + PD) % RS]);
-                    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of this step's MFMAs
-                    mfma_kstep<BF, MB, 4>(cur, CLD, kq, rb[slot], h1);
+                    if (kAhead && kq + 1 < TPC) load_a<BF, MB>(cur, CLD, kq + 1, a[(kq + 1) & 1]);
+                    __builtin_amdgcn_sched_barrier(0);   // keep the prefetches ahead of this step's MFMAs
+                    if (!kAhead) load_a<BF, MB>(cur, CLD, kq, a[kq & 1]);
+                    mfma_kstep<BF, MB, 4>(a[kq & 1], rb[slot], h1);
                 }
                 if (c + 1 < nch) sstore((c + 1) & 1);
                 __syncthreads();
@@ -648,7 +687,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_ens_adj1(const FusedArgs A, int
     constexpr int MB = TM / 16;
     constexpr int LD = Cfg<BF>::kLd;
     __shared__ __attribute__((aligned(16))) act_t act[TM * LD];
-    const int row0 = blockIdx.x * TM, pass = blockIdx.y;
+    const int row0 = xcd_tile((A.rows + TM - 1) / TM) * TM, pass = blockIdx.y;
     const int32_t* meta = A.meta;
     if (row0 >= meta[8 + A.ns]) return;
     int s = 0;
@@ -734,7 +773,7 @@ static void pack_fp32(float* out, int K, int N, F B) {
             for (int lane = 0; lane < 64; ++lane)
                 for (int j = 0; j < 4; ++j)
                     out[(((size_t)nb * (K / 16) + kq) * 64 + lane) * 4 + j] =
-                        B(16 * kq + 4 * j + lane / 16, 16 * nb + lane % 16);
+                        B(16 * kq + 4 * (lane / 16) + j, 16 * nb + lane % 16);
 }
 
 uint16_t host_bf16_bits(float f);
@@ -853,7 +892,7 @@ hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev,
     const bool bf = m->precision == NNP_BF16_MLP;
     const FusedArgs A = fused_args(m, W, aev, g_out, E_row, E_atomo);
     const int tm = fused_tile_rows(n_atoms, bf, false);
-    const int grid = ceil_div(W.rows_max, tm);
+    const int grid = ceil_div(ceil_div(W.rows_max, tm), kXcds) * kXcds;   // whole rounds of the XCDs (xcd_tile)
     if (bf) {
         if (tm == 32) k_mlp_fused<true, 32, false><<<grid, kThreads, 0, s>>>(A);
         else k_mlp_fused<true, 16, false><<<grid, kThreads, 0, s>>>(A);
@@ -877,7 +916,8 @@ hipError_t launch_mlp_ensemble(const nnp_model* m, const MlpWs& W, const void* a
     A.d1_out = d1_scratch;
     A.E_net = E_net;
     const int tm = fused_tile_rows(n_atoms, bf, true);
-    const dim3 g1(ceil_div(W.rows_max, tm), m->n_nets), g2(ceil_div(W.rows_max, tm), g_out ? 4 : 1);
+    const int gx = ceil_div(ceil_div(W.rows_max, tm), kXcds) * kXcds;   // whole rounds of the XCDs (xcd_tile)
+    const dim3 g1(gx, m->n_nets), g2(gx, g_out ? 4 : 1);
     const float inv = 1.f / (float)m->n_nets;
     if (bf) {
         if (tm == 64) {
