@@ -160,6 +160,10 @@ __device__ __forceinline__ bool load_row(Row& R, const AevConst& P, int i, int b
     bool bad_species = false;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
+        R.vx[q] = R.vy[q] = R.vz[q] = R.r2[q] = 0.f;
+        R.z[q] = 0;
+        R.in_r[q] = R.in_a[q] = false;
+        if (q >= nq2) continue;   // wave-uniform: a group past the row's end
         float sx, sy, sz;
         if (kPacked) {
             sx = (float)(int8_t)(s0[q] & 0xff);
@@ -410,16 +414,22 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
         const int cs_ = S.seg_a[bs_ + 1] - S.seg_a[bs_];
         cnt = bs_ == bt_ ? cs_ * (cs_ - 1) / 2 : cs_ * (S.seg_a[bt_ + 1] - S.seg_a[bt_]);
     }
+    // packed order: the same-species bins first, then the mixed ones, so
+    // that few tiles hold both kinds (their pair decodes differ)
     const unsigned long long binmask = ballot(cnt > 0);
+    const unsigned long long same_m = ballot(cnt > 0 && bs_ == bt_);
     const int n_act = __popcll(binmask);
-    const int incl = wave_inclusive_sum(cnt);
-    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
-    wave_sync();   // the radial list is read; its space becomes the pair tile
     if (cnt > 0) {
-        const int rank = rank_below(binmask);
-        S.bin_off[rank] = incl - cnt;
+        const int rank = bs_ == bt_ ? rank_below(same_m) : __popcll(same_m) + rank_below(binmask & ~same_m);
+        S.bin_off[rank] = cnt;   // the count for now; its offset below
         S.bin_info[rank] = l | (bs_ << 8) | (bt_ << 16);
     }
+    wave_sync();
+    const int cnt_r = l < n_act ? S.bin_off[l] : 0;
+    const int incl = wave_inclusive_sum(cnt_r);
+    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    wave_sync();   // the radial list is read; its space becomes the pair tile
+    if (l < n_act) S.bin_off[l] = incl - cnt_r;
     if (l == 0) S.bin_off[n_act] = total;
     wave_sync();
     // ---- angular: the pairs of every non-empty bin in one packed sequence,
@@ -467,7 +477,7 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
             }
 #pragma unroll
             for (int z = 0; z < kNz; ++z)
-                S.tile.f1[l][z] = pow_zeta(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), P.zeta);
+                S.tile.f1[l][z] = pow_zeta(fmaf(uu, P.hcos_z[z], fmaf(sq, P.hsin_z[z], 0.5f)), P.zeta);
         }
         wave_sync();
         const int u1 = min(u0 + kWave, total);
@@ -500,8 +510,9 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
         }
         wave_sync();
     }
-    // ---- zeros for every other 16-feature block (species absent from the
-    // row, bins without a pair, padding columns), 16 bytes per lane store
+    // ---- zeros for the 16-feature blocks not written above (species absent
+    // from the row, bins without a pair, padding columns), 16 bytes per lane
+    // store
     constexpr int kPer16 = 16 / (int)sizeof(OutT);       // features per 16-byte store
     const int nblk_r = ns, nblk = P.dim / 16;
     for (int c = l; c < P.stride / kPer16; c += kWave) {
@@ -569,8 +580,11 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
     }
     // angular list entries; the radial list (r and species, species-grouped)
     float r_[kQ];
+    const int nq = (R.len + kWave - 1) / kWave;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
+        r_[q] = 0.f;
+        if (q >= nq) continue;   // wave-uniform: a group past the row's end
         r_[q] = hw_sqrt(R.r2[q]);
         if (pr_[q] >= 0) S.rl[pr_[q]] = make_float2(r_[q], __int_as_float(R.z[q]));
         if (pa_[q] >= 0) {
@@ -684,7 +698,7 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
                 for (int z = 0; z < kNz; ++z) {
                     // base^zeta and its derivative (zeta/2) base^(zeta-1), the factor
                     // folded into the exponent; base = 0 gives log2 = -inf and both 0
-                    const float base = fmaxf(0.5f + 0.5f * (uu * P.cos_z[z] + sq * P.sin_z[z]), 0.f);
+                    const float base = fmaxf(fmaf(uu, P.hcos_z[z], fmaf(sq, P.hsin_z[z], 0.5f)), 0.f);
                     const float lg = hw_log2(base);
                     const float F1 = hw_exp2(P.zeta * lg);
                     const float dF1 = hw_exp2(fmaf(zm1, lg, l2hz));

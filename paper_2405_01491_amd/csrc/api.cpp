@@ -266,11 +266,13 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
                                opts ? opts->rev_out : nullptr, opts ? opts->gate : nullptr, W.mw.amask);
         pend(NNP_STAGE_AEV);
         pbeg(NNP_STAGE_MLP);
+        const bool ens = mlp_split(m, n) && !(m->force_unfused && m->n_nets == 1);
+        const bool fused_nets = ens || (m->fused && !m->force_unfused);
         if (e == hipSuccess) {
-            if (mlp_split(m, n) && !(m->force_unfused && m->n_nets == 1))
+            if (ens)
                 e = launch_mlp_ensemble(m, W.mw, W.aev, forces ? W.g : nullptr, W.E_row, W.E_at, n, W.d1, W.E_net,
                                         e_mol_net ? W.E_at_net : nullptr, s);
-            else if (m->fused && !m->force_unfused)
+            else if (fused_nets)
                 e = launch_mlp_fused(m, W.mw, W.aev, forces ? W.g : nullptr, W.E_row, W.E_at, n, s);
             else
                 e = launch_mlp(m, W.mw, W.aev, bf, W.h, forces ? W.g : nullptr, W.E_row, W.E_at, s);
@@ -400,6 +402,8 @@ nnp_status nnp_model_create_ensemble(const nnp_aev_params* a, const nnp_mlp_para
     for (int k = 0; k < kNz; ++k) {
         P.cos_z[k] = (float)std::cos((double)a->shf_z[k]);
         P.sin_z[k] = (float)std::sin((double)a->shf_z[k]);
+        P.hcos_z[k] = 0.5f * P.cos_z[k];
+        P.hsin_z[k] = 0.5f * P.sin_z[k];
     }
     m->n_layers = L;
     for (int l = 0; l <= L; ++l) {

@@ -30,6 +30,8 @@ struct AevConst {
     float shf_a[kNa];
     float cos_z[kNz];
     float sin_z[kNz];
+    float hcos_z[kNz];   // cos_z / 2 and sin_z / 2 (exact halves)
+    float hsin_z[kNz];
 };
 
 // Orthorhombic box as kernels see it (periodic == 0: open boundaries).
