@@ -232,57 +232,30 @@ __device__ __forceinline__ int stencil_sources(const Grid& g, int ci, const int3
     return n_src;
 }
 
-// Slot in cell_atoms (or atom index without cells) of candidate t: source k
-// is the last one with off[k] <= t (off[n_src] = total > t)
-__device__ __forceinline__ int cand_slot(const int* off, const int* beg, int n_src, int t) {
+// Slot in cell_atoms (or atom index without cells) of candidate t, and its
+// source k: the last one with off[k] <= t (off[n_src] = total > t)
+__device__ __forceinline__ int cand_slot(const int* off, const int* beg, int n_src, int t, int& k) {
     int lo = 0, hi = n_src;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (off[mid] <= t) lo = mid; else hi = mid;
     }
+    k = lo;
     return beg[lo] + (t - off[lo]);
 }
+__device__ __forceinline__ int cand_slot(const int* off, const int* beg, int n_src, int t) {
+    int k;
+    return cand_slot(off, beg, n_src, t, k);
+}
 
-// The row of atom i (position xi) over candidates t = 0 .. total - 1:
-// fetch(t, j, xj) gives candidate t's index j and returns whether it may be
-// a neighbour, then with its position xj.  The kept pairs are compacted into
-// the wave's LDS row (s_col, s_sh), rank-sorted by neighbour index and
+// The kept pairs of row i, compacted in candidate order into the wave's LDS
+// row (s_col, s_sh) with their count, are rank-sorted by neighbour index and
 // written to the staging row i * kRowLds with the count; a row longer than
 // kRowLds raises NNP_FLAG_ROW and is left empty.  Wave-level.
-template <class Fetch>
-__device__ __forceinline__ void build_row(int i, float3 xi, int total, Fetch fetch, const Grid& g, double r2,
-                                          float rf, int* s_col, int* s_sh, int32_t* row_count, int32_t* stage_col,
-                                          int32_t* stage_sh, unsigned* flags) {
+__device__ __forceinline__ void finish_row(int i, int count, int* s_col, int* s_sh, int32_t* row_count,
+                                           int32_t* stage_col, int32_t* stage_sh, unsigned* flags) {
     const int l = lane_id();
-    int count = 0;
-    bool overflow = false;
-    for (int base = 0; base < total; base += kWave) {
-        const int t = base + l;
-        bool keep = false;
-        int j = -1, sh = 0;
-        float3 xj;
-        if (t < total && fetch(t, j, xj)) {
-            PairOut o = pair_predicate(xi, xj, g, r2, rf);
-            keep = o.keep;
-            sh = o.packed_shift;
-            if (keep && sh == -1) {
-                set_flag(flags, NNP_FLAG_SHIFT);
-                sh = 0;
-            }
-        }
-        const unsigned long long m = ballot(keep);
-        if (keep) {
-            const int pos_in_row = count + rank_below(m);
-            if (pos_in_row < kRowLds) {
-                s_col[pos_in_row] = j;
-                s_sh[pos_in_row] = sh;
-            } else {
-                overflow = true;
-            }
-        }
-        count += __popcll(m);
-    }
-    if (overflow || count > kRowLds) {
+    if (count > kRowLds) {
         if (l == 0) {
             set_flag(flags, NNP_FLAG_ROW);
             row_count[i] = 0;
@@ -291,8 +264,8 @@ __device__ __forceinline__ void build_row(int i, float3 xi, int total, Fetch fet
         return;
     }
     wave_sync();
-    // rank sort by neighbour index (indices in a row are distinct); the row
-    // is read four entries per 16-byte LDS load, several loads in flight
+    // rank sort (indices in a row are distinct); the row is read four entries
+    // per 16-byte LDS load, several loads in flight
     int32_t* oc = stage_col + (size_t)i * kRowLds;
     int32_t* os = stage_sh + (size_t)i * kRowLds;
     for (int e = l; e < count; e += kWave) {
@@ -309,6 +282,140 @@ __device__ __forceinline__ void build_row(int i, float3 xi, int total, Fetch fet
     }
     if (l == 0) row_count[i] = count;
     wave_sync();   // the LDS row is free for the wave's next row
+}
+
+// Compaction of one 64-candidate round: the kept lanes' (j, sh) appended to
+// the LDS row in lane order.  Returns the new count (may exceed kRowLds: the
+// entries past it are dropped and finish_row rejects the row).
+__device__ __forceinline__ int append_kept(bool keep, int j, int sh, int count, int* s_col, int* s_sh) {
+    const unsigned long long m = ballot(keep);
+    if (keep) {
+        const int p = count + rank_below(m);
+        if (p < kRowLds) {
+            s_col[p] = j;
+            s_sh[p] = sh;
+        }
+    }
+    return count + __popcll(m);
+}
+
+// The row of atom i (position xi) over candidates t = 0 .. total - 1:
+// fetch(t, j, xj) gives candidate t's index j and returns whether it may be
+// a neighbour, then with its position xj.  Wave-level.
+template <class Fetch>
+__device__ __forceinline__ void build_row(int i, float3 xi, int total, Fetch fetch, const Grid& g, double r2,
+                                          float rf, int* s_col, int* s_sh, int32_t* row_count, int32_t* stage_col,
+                                          int32_t* stage_sh, unsigned* flags) {
+    int count = 0;
+    for (int base = 0; base < total; base += kWave) {
+        const int t = base + lane_id();
+        bool keep = false;
+        int j = -1, sh = 0;
+        float3 xj;
+        if (t < total && fetch(t, j, xj)) {
+            PairOut o = pair_predicate(xi, xj, g, r2, rf);
+            keep = o.keep;
+            sh = o.packed_shift;
+            if (keep && sh == -1) {
+                set_flag(flags, NNP_FLAG_SHIFT);
+                sh = 0;
+            }
+        }
+        count = append_kept(keep, j, sh, count, s_col, s_sh);
+    }
+    finish_row(i, count, s_col, s_sh, row_count, stage_col, stage_sh, flags);
+}
+
+// The row of atom i of a periodic box over the block's staged candidates
+// s_x[0 .. total) (position; the index in w of s_j).
+// The float32 screen of pair_predicate without branches, with one magnitude
+// bound for the block: lo / hi = r^2 -/+ the band of pair_predicate for M
+// the largest coordinate magnitude or box side of any staged atom (at least
+// each pair's own M, so the band is at least as wide as that pair's).  The
+// rare lanes inside the band take the exact float64 predicate.  The same
+// pairs as build_row.
+__device__ __forceinline__ void build_row_staged(int i, float3 xi, int total, const float4* s_x, const float4* s_j,
+                                                 const Grid& g, double r2, float lo, float hi, int* s_col, int* s_sh,
+                                                 int32_t* row_count, int32_t* stage_col, int32_t* stage_sh,
+                                                 unsigned* flags) {
+    const int l = lane_id();
+    int count = 0;
+    bool bad_shift = false;
+    for (int base = 0; base < total; base += kWave) {
+        const int t = min(base + l, total - 1);
+        const float4 q = s_x[t];
+        const int j = __float_as_int(s_j[t].w);
+        const float d0x = q.x - xi.x, d0y = q.y - xi.y, d0z = q.z - xi.z;
+        const float nx = -rintf(d0x * g.inv_Lf[0]), ny = -rintf(d0y * g.inv_Lf[1]), nz = -rintf(d0z * g.inv_Lf[2]);
+        const float dx = d0x + nx * g.Lf[0], dy = d0y + ny * g.Lf[1], dz = d0z + nz * g.Lf[2];
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        const bool valid = base + l < total && j != i;
+        bool keep = valid && d2 < lo;
+        const bool undecided = valid && d2 >= lo && d2 <= hi;
+        int sh = ((int)nx & 0xff) | (((int)ny & 0xff) << 8) | (((int)nz & 0xff) << 16);
+        bool wide = fmaxf(fabsf(nx), fmaxf(fabsf(ny), fabsf(nz))) > 127.f;
+        if (ballot(undecided)) {   // wave-uniform; rare
+            if (undecided) {
+                const PairOut o = pair_predicate_exact(xi, make_float3(q.x, q.y, q.z), g, r2);
+                keep = o.keep;
+                sh = o.packed_shift;
+                wide = o.packed_shift == -1;
+            }
+        }
+        if (keep && wide) {
+            bad_shift = true;
+            sh = 0;
+        }
+        count = append_kept(keep, j, sh, count, s_col, s_sh);
+    }
+    if (ballot(bad_shift) && l == 0) set_flag(flags, NNP_FLAG_SHIFT);
+    finish_row(i, count, s_col, s_sh, row_count, stage_col, stage_sh, flags);
+}
+
+// The row of atom i of a periodic box with at least three cells along every
+// dimension and every staged atom inside [0, L): each staged candidate also
+// has its position with the image shift of its stencil cell applied (s_xs:
+// x_j + n L, n in {-1, 0, 1}, index j in w; s_x: the unshifted position,
+// the packed n in w), which for a pair within the cutoff is the minimum
+// image (L > 2 r_list), so the float32 screen is a plain distance.  The
+// shifted position is one rounding from the exact one, well inside the
+// float32 error pair_predicate's band allows for; lanes inside the band take
+// the exact predicate on the unshifted positions.  The same pairs as
+// build_row.
+__device__ __forceinline__ void build_row_shifted(int i, float3 xi, int total, const float4* s_x, const float4* s_xs,
+                                                  const Grid& g, double r2, float lo, float hi, int* r_col,
+                                                  int* r_sh, int32_t* row_count, int32_t* stage_col,
+                                                  int32_t* stage_sh, unsigned* flags) {
+    const int l = lane_id();
+    int count = 0;
+    bool bad_shift = false;
+    for (int base = 0; base < total; base += kWave) {
+        const int t = min(base + l, total - 1);
+        const float4 q = s_xs[t];
+        const int j = __float_as_int(q.w);
+        const float dx = q.x - xi.x, dy = q.y - xi.y, dz = q.z - xi.z;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        const bool valid = base + l < total && j != i;
+        bool keep = valid && d2 < lo;
+        const bool undecided = valid && d2 >= lo && d2 <= hi;
+        int sh = 0;
+        if (keep) sh = __float_as_int(s_x[t].w);
+        if (ballot(undecided)) {   // wave-uniform; rare
+            if (undecided) {
+                const float4 x = s_x[t];
+                const PairOut o = pair_predicate_exact(xi, make_float3(x.x, x.y, x.z), g, r2);
+                keep = o.keep;
+                sh = o.packed_shift;
+                if (keep && sh == -1) {
+                    bad_shift = true;
+                    sh = 0;
+                }
+            }
+        }
+        count = append_kept(keep, j, sh, count, r_col, r_sh);
+    }
+    if (ballot(bad_shift) && l == 0) set_flag(flags, NNP_FLAG_SHIFT);
+    finish_row(i, count, r_col, r_sh, row_count, stage_col, stage_sh, flags);
 }
 
 // One wave per row: the row's pairs are found once, rank-sorted by
@@ -372,61 +479,107 @@ __global__ __launch_bounds__(kRowsPerBlock* kWave) void k_rows(
     build_row(i, xi, total, fetch, g, r2, rf, s_col[w], s_sh[w], row_count, stage_col, stage_sh, flags);
 }
 
-// The same rows for a periodic system without structure ids, one block per
-// cell: the block stages the positions of its stencil's atoms in LDS once,
-// and its waves build the rows of the cell's atoms from there (each atom's
-// position is read once per stencil it belongs to, not once per neighbour
-// search that visits it).  A stencil of more than kCellCand atoms is read
-// from global memory per row instead.  Every block also empties the rows of
-// its share of the atoms outside every cell (non-finite coordinates).
-constexpr int kCellWaves = 16;
-constexpr int kCellCand = 1536;
-__global__ __launch_bounds__(kCellWaves* kWave) void k_rows_cells(
+// The same rows for a periodic system without structure ids, one block of
+// W waves per cell: the block stages the positions of its stencil's atoms
+// in LDS once, and its waves build the rows of the cell's atoms from there
+// (each atom's position is read once per stencil it belongs to, not once
+// per neighbour search that visits it).  A stencil of more than
+// cell_cand(W) atoms is read from global memory per row instead.  Every
+// block also empties the rows of its share of the atoms outside every cell
+// (non-finite coordinates).  Large boxes take 8 waves per cell (about 20
+// rows: 2-3 each), small ones 16, so that the launch still has many waves.
+constexpr int kCellBlocksForW8 = 1024;
+__host__ __device__ constexpr int cell_cand(int W) { return W == 16 ? 960 : 1024; }
+template <int W>
+__global__ __launch_bounds__(W* kWave) void k_rows_cells(
     const float* pos, int n, int n_cells, const Grid g, double r2, const int32_t* cell_of, const int32_t* cell_start,
     const int32_t* cell_atoms, int32_t* row_count, int32_t* stage_col, int32_t* stage_sh, unsigned* flags,
     const int32_t* gate) {
     if (gate && *gate == 0) return;
+    constexpr int kCand = cell_cand(W);
     __shared__ int s_off[28];
     __shared__ int s_beg[28];
-    __shared__ float4 s_x[kCellCand];
-    __shared__ __attribute__((aligned(16))) int s_col[kCellWaves][kRowLds];
-    __shared__ int s_sh[kCellWaves][kRowLds];
+    __shared__ int s_mbits;
+    __shared__ int s_outside;
+    // staged atoms: position and index; with three or more cells along every
+    // dimension the index moves to s_xs, beside the position shifted by the
+    // stencil cell's image, and s_x holds that packed shift in its place
+    __shared__ float4 s_x[kCand];
+    __shared__ float4 s_xs[kCand];
+    __shared__ __attribute__((aligned(16))) int s_col[W][kRowLds];
+    __shared__ int s_sh[W][kRowLds];
     const int c = blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     {
         const int per = (n + n_cells - 1) / n_cells;
         const int a1 = min(n, (c + 1) * per);
-        for (int a = c * per + (int)threadIdx.x; a < a1; a += kCellWaves * kWave)
+        for (int a = c * per + (int)threadIdx.x; a < a1; a += W * kWave)
             if (cell_of[a] < 0) row_count[a] = 0;
     }
     const int h0 = cell_start[c], h1 = cell_start[c + 1];
     if (h1 <= h0) return;
     int n_src = 0;
     if (w == 0) n_src = stencil_sources(g, c, cell_start, s_off, s_beg);
+    if (threadIdx.x == 0) {
+        s_mbits = 0;
+        s_outside = 0;
+    }
     __syncthreads();
     n_src = g.ns[0] * g.ns[1] * g.ns[2];
     const int total = s_off[n_src];
     const float rf = (float)sqrt(r2);
-    if (total <= kCellCand) {
-        for (int t = threadIdx.x; t < total; t += kCellWaves * kWave) {
-            const int j = cell_atoms[cand_slot(s_off, s_beg, n_src, t)];
+    if (total <= kCand) {
+        // the staged atoms include the cell's own (its cell is in the stencil);
+        // with three or more cells along every dimension each also gets the
+        // image shift of its stencil cell: source k = 9 a + 3 b + c is cell
+        // (cx + a - 1, cy + b - 1, cz + c - 1) wrapped, and an atom of a cell
+        // wrapped up by the box (index -1 -> nc - 1) is shifted down by L
+        const bool cells3 = g.nc[0] >= 3 && g.nc[1] >= 3 && g.nc[2] >= 3;
+        const int ccz = c % g.nc[2], ccy = (c / g.nc[2]) % g.nc[1], ccx = c / (g.nc[2] * g.nc[1]);
+        float mx = 0.f;
+        bool outside = false;
+        for (int t = threadIdx.x; t < total; t += W * kWave) {
+            int k;
+            const int j = cell_atoms[cand_slot(s_off, s_beg, n_src, t, k)];
             const float3 x = load_pos(pos, j);
-            s_x[t] = make_float4(x.x, x.y, x.z, __int_as_float(j));
+            mx = fmaxf(mx, fmaxf(fabsf(x.x), fmaxf(fabsf(x.y), fabsf(x.z))));
+            outside |= !(x.x >= 0.f && x.x < g.Lf[0] && x.y >= 0.f && x.y < g.Lf[1] && x.z >= 0.f && x.z < g.Lf[2]);
+            if (!cells3) s_x[t] = make_float4(x.x, x.y, x.z, __int_as_float(j));
+            if (cells3) {
+                const int ox = ccx + k / 9 - 1, oy = ccy + (k / 3) % 3 - 1, oz = ccz + k % 3 - 1;
+                const int nx = ox < 0 ? -1 : (ox >= g.nc[0] ? 1 : 0);
+                const int ny = oy < 0 ? -1 : (oy >= g.nc[1] ? 1 : 0);
+                const int nz = oz < 0 ? -1 : (oz >= g.nc[2] ? 1 : 0);
+                const int sh = (nx & 0xff) | ((ny & 0xff) << 8) | ((nz & 0xff) << 16);
+                s_x[t] = make_float4(x.x, x.y, x.z, __int_as_float(sh));
+                s_xs[t] = make_float4(x.x + (float)nx * g.Lf[0], x.y + (float)ny * g.Lf[1], x.z + (float)nz * g.Lf[2],
+                                      __int_as_float(j));
+            }
         }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) mx = fmaxf(mx, shfl_xor(mx, d));
+        if (lane_id() == 0) atomicMax(&s_mbits, __float_as_int(mx));   // non-negative floats order as their bits
+        if (ballot(outside) && lane_id() == 0) s_outside = 1;
         __syncthreads();
-        for (int r = h0 + w; r < h1; r += kCellWaves) {
+        float M = fmaxf(1.f, __int_as_float(s_mbits));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) M = fmaxf(M, g.Lf[k]);
+        const float e = 1e-5f * M, band = e * (2.0f * rf + e), r2f = rf * rf;
+        // positions outside the box (not wrapped): the rows take the minimum
+        // image pair by pair from the unshifted positions
+        const bool shifted = cells3 && !s_outside;   // block-uniform
+        for (int r = h0 + w; r < h1; r += W) {
             const int i = cell_atoms[r];
             const float3 xi = load_pos(pos, i);
-            auto fetch = [&](int t, int& j, float3& xj) {
-                const float4 q = s_x[t];
-                j = __float_as_int(q.w);
-                xj = make_float3(q.x, q.y, q.z);
-                return j != i;
-            };
-            build_row(i, xi, total, fetch, g, r2, rf, s_col[w], s_sh[w], row_count, stage_col, stage_sh, flags);
+            if (shifted)
+                build_row_shifted(i, xi, total, s_x, s_xs, g, r2, r2f - band, r2f + band, s_col[w], s_sh[w],
+                                  row_count, stage_col, stage_sh, flags);
+            else
+                build_row_staged(i, xi, total, s_x, cells3 ? s_xs : s_x, g, r2, r2f - band, r2f + band, s_col[w],
+                                 s_sh[w], row_count, stage_col, stage_sh, flags);
         }
     } else {
-        for (int r = h0 + w; r < h1; r += kCellWaves) {
+        for (int r = h0 + w; r < h1; r += W) {
             const int i = cell_atoms[r];
             const float3 xi = load_pos(pos, i);
             auto fetch = [&](int t, int& j, float3& xj) {
@@ -767,7 +920,12 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
             k_finite<<<nb, tb, 0, s>>>(pos, n, flags, gate);
         }
         if (g.periodic && !mol) {
-            k_rows_cells<<<(int)n_cells, kCellWaves * kWave, 0, s>>>(pos, n, (int)n_cells, g, r2, cell_of,
+            if (n_cells >= kCellBlocksForW8)
+                k_rows_cells<8><<<(int)n_cells, 8 * kWave, 0, s>>>(pos, n, (int)n_cells, g, r2, cell_of, cell_start,
+                                                                    cell_atoms, row_count, stage_col, stage_sh, flags,
+                                                                    gate);
+            else
+                k_rows_cells<16><<<(int)n_cells, 16 * kWave, 0, s>>>(pos, n, (int)n_cells, g, r2, cell_of,
                                                                       cell_start, cell_atoms, row_count, stage_col,
                                                                       stage_sh, flags, gate);
         } else {
