@@ -265,6 +265,16 @@ __device__ __forceinline__ float quad_xor(float v, int x) {
                   : __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false));
 }
 
+// Sum of v over the 64 lanes (every lane receives it): the quad's lanes by
+// DPP, then a row's four quads by two DPP rotations, then the row and half
+// swaps.  A fixed order of additions.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += quad_xor(v, 1);
+    v += quad_xor(v, 2);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));   // row_ror:4
+    return sum_over_rows_and_halves(v, true);
+}
+
 // inclusive prefix sum over the 64 lanes
 __device__ __forceinline__ int wave_inclusive_sum(int v) {
     const int l = lane_id();
@@ -549,7 +559,7 @@ template <bool kVir, bool kPacked>
 __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
     const AevConst P, int n, const float* __restrict__ pos, const int32_t* __restrict__ species, const BoxConst bx,
     const RowsView rows, const int32_t* __restrict__ g_row, const float* __restrict__ g, float4* __restrict__ G,
-    float* __restrict__ Wat, unsigned* flags) {
+    float4* __restrict__ Gown, float* __restrict__ Wat, unsigned* flags) {
     __shared__ BwdLds lds[kWaves];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: the atom is a scalar
     const int l = lane_id();
@@ -566,6 +576,7 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
     if (!ok) {
         const int b = rows.begin(i), e = rows.end(i);
         for (int p = b + l; p < e; p += kWave) G[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (l == 0) Gown[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (kVir && l < 9) Wat[9 * (size_t)i + l] = 0.f;
         return;
     }
@@ -779,9 +790,11 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
     }
     wave_sync();
     // ---- one value per row slot: radial part + angular part (zero outside Rc_R)
+    // and the row's own sum, slots in order on each lane, then over the lanes
     float wv[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) wv[k] = 0.f;
+    float ox = 0.f, oy = 0.f, oz = 0.f;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         const int slot = l + kWave * q;
@@ -795,6 +808,9 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
             }
             const int p = R.b + slot;
             G[p] = make_float4(x, y, z, 0.f);
+            ox += x;
+            oy += y;
+            oz += z;
             if (kVir) {
                 const float v[3] = {R.vx[q], R.vy[q], R.vz[q]}, G[3] = {x, y, z};
 #pragma unroll
@@ -804,6 +820,10 @@ __global__ __launch_bounds__(kWaves* kWave, kVir ? 4 : 5) void k_aev_bwd(
             }
         }
     }
+    ox = wave_sum(ox);
+    oy = wave_sum(oy);
+    oz = wave_sum(oz);
+    if (l == 0) Gown[i] = make_float4(ox, oy, oz, 0.f);
     if (kVir) {
 #pragma unroll
         for (int k = 0; k < 9; ++k)
@@ -841,13 +861,13 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
 }
 
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const RowsView& rows, const int32_t* g_row, const float* g, float4* G,
+                          const RowsView& rows, const int32_t* g_row, const float* g, float4* G, float4* Gown,
                           float* atom_virial, unsigned* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = ceil_div(n, kWaves);
     const bool packed = rows.row_ptr == nullptr;
 #define NNP_AEV_BWD(V, PK) \
-    k_aev_bwd<V, PK><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, G, atom_virial, flags)
+    k_aev_bwd<V, PK><<<grid, kWaves * kWave, 0, s>>>(P, n, pos, species, bx, rows, g_row, g, G, Gown, atom_virial, flags)
     if (atom_virial) {
         if (packed) NNP_AEV_BWD(true, true);
         else NNP_AEV_BWD(true, false);

@@ -136,6 +136,7 @@ struct EfWs {
     float* E_row;
     float* E_at;        // network energies in atom order
     float4* G;      // edge gradients dE/dv_ij, one (x, y, z, 0) per list slot
+    float4* Gown;       // per atom, the sum of its row's edge gradients
     float* Wat;         // per-centre virials [n][9] when the caller passes none
     double* vpart;      // chunk partials of the structure virial
     void* d1;           // ensembles: per-network dE/dh1 [n_nets][rows_max][256]
@@ -168,6 +169,7 @@ EfWs ef_layout(const nnp_model* m, int n, int64_t cap, char* base) {
     W.E_at = (float*)take(sizeof(float) * nn);
     const int64_t c = cap > 0 ? cap : 1;
     W.G = (float4*)take(sizeof(float4) * c);
+    W.Gown = (float4*)take(sizeof(float4) * nn);
     W.Wat = (float*)take(sizeof(float) * 9 * (size_t)nn);
     W.vpart = (double*)take(sizeof(double) * virial_partial_doubles(nn));
     if (mlp_split(m, nn)) {
@@ -293,7 +295,7 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     if (e == hipSuccess && forces && n > 0) {
         pbeg(NNP_STAGE_AEV_ADJ);
         float* wat = virial || atom_virial ? (atom_virial ? atom_virial : W.Wat) : nullptr;
-        e = launch_aev_bwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.g, W.G, wat, flags, s);
+        e = launch_aev_bwd(m->aev, n, pos, species, bx, rows, W.mw.prow, W.g, W.G, W.Gown, wat, flags, s);
         pend(NNP_STAGE_AEV_ADJ);
         pbeg(NNP_STAGE_FORCES);
         if (e == hipSuccess) {
@@ -307,9 +309,9 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
                 ein.e_pot = e_mol;
                 ein.part = md->e_part;
                 ein.ticket = md->e_ticket;
-                e = md_launch_back(n, rows, W.G, forces, *md, &ein, s);
+                e = md_launch_back(n, rows, W.G, W.Gown, forces, *md, &ein, s);
             } else {
-                e = launch_force_gather(n, rows, W.G, forces, s);
+                e = launch_force_gather(n, rows, W.G, W.Gown, forces, s);
             }
         }
         pend(NNP_STAGE_FORCES);

@@ -2,9 +2,10 @@
 //
 // With G_ij = dE_i/dv_ij and v_ij = x_j + n L - x_i, the force on atom a is
 //   F_a = -dE/dx_a = sum_{j in N(a)} (G_aj - G_ja),
-// where G_ja sits at rev[p] of the pair a -> j (the list is symmetric).  Each
-// atom's sum runs over its own row in a fixed order (gather_row_force), so no
-// atomics are involved (Sec. 2.4: forces as the gradient of the total energy).
+// where G_ja sits at rev[p] of the pair a -> j (the list is symmetric) and
+// the adjoint kernel has summed each row's own part.  Each atom's sum runs
+// over its own row in a fixed order (gather_row_force), so no atomics are
+// involved (Sec. 2.4: forces as the gradient of the total energy).
 #include "nnp_internal.hpp"
 
 namespace nnp {
@@ -12,10 +13,10 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_force_gather(int n, const RowsView rows,
                                                      const int32_t* __restrict__ rev, const float4* __restrict__ G,
-                                                     float* __restrict__ F) {
+                                                     const float4* __restrict__ Gown, float* __restrict__ F) {
     const int a = (blockIdx.x * blockDim.x + threadIdx.x) / kGatherLanes;
     const int sub = threadIdx.x % kGatherLanes;
-    const float3 f = gather_row_force(rows, rev, G, a, n, sub);
+    const float3 f = gather_row_force(rows, rev, G, Gown, a, n, sub);
     if (a < n && sub == 0) {
         F[3 * a] = f.x;
         F[3 * a + 1] = f.y;
@@ -135,10 +136,10 @@ hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_force_gather(int n, const RowsView& rows, const float4* G, float* F,
+hipError_t launch_force_gather(int n, const RowsView& rows, const float4* G, const float4* Gown, float* F,
                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_force_gather<<<ceil_div((long)n * kGatherLanes, 256), 256, 0, s>>>(n, rows, rows.rev, G, F);
+    k_force_gather<<<ceil_div((long)n * kGatherLanes, 256), 256, 0, s>>>(n, rows, rows.rev, G, Gown, F);
     return hipGetLastError();
 }
 

@@ -120,7 +120,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 template <bool kEnergy>
 __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, int ne, const RowsView rows,
                                                          const int32_t* __restrict__ rev, const float4* __restrict__ G,
-                                                         float* __restrict__ F, float* __restrict__ vel,
+                                                         const float4* __restrict__ Gown, float* __restrict__ F, float* __restrict__ vel,
                                                          const float* __restrict__ inv_mass, float dt, double* ke_part,
                                                          const MdEnergyIn E) {
     __shared__ double red[kBackThreads];
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, int ne, const R
     }
     const int a = blk * kBackAtoms + threadIdx.x / kGatherLanes;
     const int sub = threadIdx.x % kGatherLanes;
-    const float3 fs = gather_row_force(rows, rev, G, a, n, sub);
+    const float3 fs = gather_row_force(rows, rev, G, Gown, a, n, sub);
     double ke = 0.0;
     if (a < n && sub == 0) {
         const float f[3] = {fs.x, fs.y, fs.z};
@@ -229,15 +229,15 @@ int md_ke_parts(int n) { return ceil_div(n > 0 ? n : 1, kBackAtoms); }
 
 int md_energy_parts(int n) { return ceil_div(n > 0 ? n : 1, kEChunk); }
 
-hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, float* F,
+hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, const float4* Gown, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s) {
     if (b.fuse_energy && e) {
         const int ne = md_energy_parts(n);
         if (ne > 1 && (!e->part || !e->ticket)) return hipErrorInvalidValue;
-        k_md_back<true><<<md_ke_parts(n) + ne, kBackThreads, 0, s>>>(n, ne, rows, rows.rev, G, F, b.vel,
+        k_md_back<true><<<md_ke_parts(n) + ne, kBackThreads, 0, s>>>(n, ne, rows, rows.rev, G, Gown, F, b.vel,
                                                                      b.inv_mass, b.dt, b.ke_part, *e);
     } else {
-        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, 0, rows, rows.rev, G, F, b.vel,
+        k_md_back<false><<<md_ke_parts(n), kBackThreads, 0, s>>>(n, 0, rows, rows.rev, G, Gown, F, b.vel,
                                                                  b.inv_mass, b.dt, b.ke_part, MdEnergyIn{});
     }
     return hipGetLastError();

@@ -177,7 +177,7 @@ hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int 
 hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx, const MdState* st, hipStream_t s);
 int md_ke_parts(int n);
 int md_energy_parts(int n);
-hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, float* F,
+hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, const float4* Gown, float* F,
                           const MdBack& b, const MdEnergyIn* e, hipStream_t s);
 // neighbors.hip: the fused front of a step for small systems
 bool md_front_fits(int n, const float* box_host, float r_list);

@@ -224,24 +224,28 @@ struct RowsView {
     }
 };
 
-// Force on atom a from the edge gradients of its row (Sec. 2.4: forces as
-// the gradient of the total energy), F_a = sum_j G_aj - G_ja, G_ja at rev[p]:
-// kGatherLanes lanes per atom stride over the row, then a fixed butterfly.
-// The plain path's gather and the MD engine's last kernel both use it, so
-// the two give the same forces bit for bit at the same positions.
+// Force on atom a from the edge gradients (Sec. 2.4: forces as the gradient
+// of the total energy), F_a = sum_j G_aj - G_ja: the own part sum_j G_aj
+// comes summed by the adjoint kernel (Gown[a]), the reverse part G_ja is
+// read at rev[p] by kGatherLanes lanes striding over the row, then summed by
+// a fixed butterfly.  The plain path's gather and the MD engine's last
+// kernel both use it, so the two give the same forces bit for bit at the
+// same positions.
 constexpr int kGatherLanes = 32;
 
 __device__ __forceinline__ float3 gather_row_force(const RowsView& rows, const int32_t* __restrict__ rev,
-                                                   const float4* __restrict__ G, int a, int n, int sub) {
+                                                   const float4* __restrict__ G, const float4* __restrict__ Gown,
+                                                   int a, int n, int sub) {
     float fx = 0.f, fy = 0.f, fz = 0.f;
+    float4 own = make_float4(0.f, 0.f, 0.f, 0.f);
     if (a < n) {
+        if (sub == 0) own = Gown[a];
         const int b = rows.begin(a), e = rows.end(a);
         for (int p = b + sub; p < e; p += kGatherLanes) {
-            const int q = rev[p];
-            const float4 gp = G[p], gq = G[q];
-            fx += gp.x - gq.x;
-            fy += gp.y - gq.y;
-            fz += gp.z - gq.z;
+            const float4 gq = G[rev[p]];
+            fx += gq.x;
+            fy += gq.y;
+            fz += gq.z;
         }
     }
 #pragma unroll
@@ -250,7 +254,7 @@ __device__ __forceinline__ float3 gather_row_force(const RowsView& rows, const i
         fy += shfl_xor(fy, m);
         fz += shfl_xor(fz, m);
     }
-    return make_float3(fx, fy, fz);
+    return make_float3(own.x - fx, own.y - fy, own.z - fz);   // lane sub == 0 of the atom
 }
 
 inline RowsView rows_csr(const nnp_nlist* nl) {
@@ -269,8 +273,9 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
                           const RowsView& rows, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
                           hipStream_t s, int32_t* rev_out = nullptr, const int32_t* gate = nullptr,
                           uint32_t* amask_out = nullptr);
+// G: one edge gradient per list slot; Gown: per atom, the sum of its row's
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
-                          const RowsView& rows, const int32_t* g_row, const float* g, float4* G,
+                          const RowsView& rows, const int32_t* g_row, const float* g, float4* G, float4* Gown,
                           float* atom_virial, unsigned* flags, hipStream_t s);
 
 hipError_t launch_species_group(const nnp_model* m, int n, const int32_t* species, const MlpWs& W, unsigned* flags,
@@ -303,7 +308,7 @@ hipError_t launch_gather_e(const int32_t* prow, int n, const int32_t* species, c
 size_t virial_partial_doubles(int n);
 hipError_t launch_virial(int n, int n_mol, const int32_t* mstart, const int32_t* mend, const float* Wat, double* part,
                          double* virial, hipStream_t s);
-hipError_t launch_force_gather(int n, const RowsView& rows, const float4* G,
+hipError_t launch_force_gather(int n, const RowsView& rows, const float4* G, const float4* Gown,
                                float* F, hipStream_t s);
 hipError_t launch_kick_drift(int n, float* pos, float* vel, const float* F, const float* inv_mass, float dt,
                              const float* ref, float* max_d2, hipStream_t s);
