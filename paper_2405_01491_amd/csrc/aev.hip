@@ -331,12 +331,17 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
     // the row's extent and grouped row, loaded ahead of the rebuild gate
     const int rb = rows.begin(i), re = rows.end(i);
     const int row = out_row ? out_row[i] : i;
-    // fixed-stride rows just rebuilt: the reverse index of this row (the rows
-    // are sorted by neighbour, so j's slot of i is found by bisection).  A lane
-    // searches the rows of its pairs p and p + 64 side by side, so that the
-    // dependent loads of the two searches are in flight together; a finished
-    // search issues no load.  A pair whose reverse is absent (a list that is
-    // not symmetric) is flagged and left pointing at itself.
+    // fixed-stride rows just rebuilt: the reverse index, found once per
+    // unordered pair by the row of its lower index.  For a pair i -> j with
+    // j > i, i's slot q in the row of j is found by bisection (rows are
+    // sorted by neighbour) and both rev[p] = q and rev[q] = p are written;
+    // the pairs with j < i are written by the row of j.  A lane searches the
+    // rows of its pairs p and p + 64 side by side, so that the dependent
+    // loads of the two searches are in flight together; a finished search
+    // issues no load.  A pair i -> j, j > i, whose reverse is absent is
+    // flagged and left pointing at itself.  (The builder's lists are
+    // symmetric; only a row emptied for overflowing, which is flagged on its
+    // own, leaves a slot of another row unresolved.)
     if (rev_out && (!gate || *gate)) {
         const int b = rb, e = re;
         bool missing = false;
@@ -345,9 +350,10 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
             const bool two = p1 < e;
             const int j0 = rows.col[p0];
             const int j1 = two ? rows.col[p1] : j0;
+            const bool s0 = j0 > i, s1 = two && j1 > i;
             const int e0 = rows.end(j0), e1 = two ? rows.end(j1) : e0;
-            int lo0 = rows.begin(j0), hi0 = e0;
-            int lo1 = rows.begin(j1), hi1 = two ? e1 : lo1;
+            int lo0 = rows.begin(j0), hi0 = s0 ? e0 : lo0;
+            int lo1 = rows.begin(j1), hi1 = s1 ? e1 : lo1;
             while (lo0 < hi0 || lo1 < hi1) {
                 const int m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
                 int c0 = 0, c1 = 0;
@@ -360,12 +366,16 @@ __global__ __launch_bounds__(kWaves* kWave) void k_aev_fwd(
                     if (c1 < i) lo1 = m1 + 1; else hi1 = m1;
                 }
             }
-            const bool f0 = lo0 < e0 && rows.col[lo0] == i;
-            rev_out[p0] = f0 ? lo0 : p0;
-            missing |= !f0;
-            if (two) {
+            if (s0) {
+                const bool f0 = lo0 < e0 && rows.col[lo0] == i;
+                rev_out[p0] = f0 ? lo0 : p0;
+                if (f0) rev_out[lo0] = p0;
+                missing |= !f0;
+            }
+            if (s1) {
                 const bool f1 = lo1 < e1 && rows.col[lo1] == i;
                 rev_out[p1] = f1 ? lo1 : p1;
+                if (f1) rev_out[lo1] = p1;
                 missing |= !f1;
             }
         }

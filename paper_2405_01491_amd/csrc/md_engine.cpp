@@ -71,6 +71,10 @@ nnp_status alloc_rows(nnp_md* md) {
     const int64_t capacity = (int64_t)md->n * NNP_MAX_ROW;
     md->nl.capacity = capacity;
     if (dmalloc(&md->nl.rev, (size_t)capacity) != hipSuccess) return NNP_E_NOMEM;
+    // every reverse slot a valid index from the start (a slot of a row
+    // emptied for overflowing may go unresolved by a build; that build is
+    // flagged)
+    if (hipMemset(md->nl.rev, 0, sizeof(int32_t) * (size_t)capacity) != hipSuccess) return NNP_E_HIP;
     md->ws_ef_bytes = nnp_workspace_bytes(md->model, md->n, capacity);
     if (hipMalloc(&md->ws_ef, md->ws_ef_bytes) != hipSuccess) return NNP_E_NOMEM;
     return NNP_OK;
