@@ -171,6 +171,87 @@ __global__ void k_bin(const float* pos, int n, const Grid g, int32_t* cell_of, i
     cell_slot[i] = atomicAdd(&cell_count[c], 1);
 }
 
+// Cell binning as k_bin, and by the block that finishes last (an integer
+// ticket) the exclusive scan of the n_cells <= kBinScanCells counts into
+// cell_start (n_cells + 1 entries, the total also to *total), after which it
+// zeroes the counts and the ticket for the next build: a build on a
+// workspace left by this kernel needs no zero fill.  The counts are read
+// after the ticket with device-coherent loads.
+constexpr int kBinScanThreads = 1024, kBinScanItems = 8, kBinScanCells = kBinScanThreads * kBinScanItems;
+__device__ __forceinline__ long long wave_inclusive_ll(long long v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const long long u = __shfl_up(v, d, kWave);
+        if (l >= d) v += u;
+    }
+    return v;
+}
+__global__ __launch_bounds__(kBinScanThreads) void k_bin_scan(const float* pos, int n, const Grid g, int n_cells,
+                                                              int32_t* cell_of, int32_t* cell_slot,
+                                                              int32_t* cell_count, int32_t* cell_start,
+                                                              int64_t* total, unsigned* ticket, unsigned* flags,
+                                                              const int32_t* gate) {
+    if (gate && *gate == 0) return;
+    __shared__ long long wsum[kBinScanThreads / kWave];
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kBinScanThreads + t;
+    if (i < n) {
+        const float3 p = load_pos(pos, i);
+        if (!finite3(p)) {
+            set_flag(flags, NNP_FLAG_NONFINITE);
+            cell_of[i] = -1;
+        } else {
+            const int cx = cell_coord(p.x, g.L[0], g.inv_cs[0], g.nc[0]);
+            const int cy = cell_coord(p.y, g.L[1], g.inv_cs[1], g.nc[1]);
+            const int cz = cell_coord(p.z, g.L[2], g.inv_cs[2], g.nc[2]);
+            const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+            cell_of[i] = c;
+            cell_slot[i] = atomicAdd(&cell_count[c], 1);
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        __threadfence();   // this block's counts before the ticket
+        s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();   // every block's counts after the last ticket
+    const int w = t / kWave, base = t * kBinScanItems;
+    int32_t v[kBinScanItems];
+    long long sum = 0;
+#pragma unroll
+    for (int k = 0; k < kBinScanItems; ++k) {
+        v[k] = base + k < n_cells ? __hip_atomic_load(&cell_count[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0;
+        sum += v[k];
+    }
+    const long long inc = wave_inclusive_ll(sum);
+    if (lane_id() == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    long long off = 0, all = 0;
+    for (int q = 0; q < kBinScanThreads / kWave; ++q) {
+        if (q < w) off += wsum[q];
+        all += wsum[q];
+    }
+    long long ex = off + inc - sum;
+#pragma unroll
+    for (int k = 0; k < kBinScanItems; ++k) {
+        if (base + k < n_cells) {
+            cell_start[base + k] = (int32_t)ex;
+            cell_count[base + k] = 0;
+        }
+        ex += v[k];
+    }
+    if (t == 0) {
+        *total = all;
+        cell_start[n_cells] = (int32_t)all;
+        *ticket = 0u;
+    }
+}
+
 __global__ void k_scatter(int n, const int32_t* cell_of, const int32_t* cell_slot, const int32_t* cell_start,
                           int32_t* cell_atoms, const int32_t* gate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -912,9 +993,22 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
         if (cells_ready) {
             // binned (and checked for finite coordinates) by the caller's front kernel
         } else if (g.periodic) {
-            fill(cell_count, n_cells + 1);
-            k_bin<<<nb, tb, 0, s>>>(pos, n, g, cell_of, cell_slot, cell_count, flags, gate);
-            chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s, gate));
+            // up to kBinScanCells cells: binning and scan in one kernel, which
+            // leaves the counts and its ticket zero, so that gated builds (the
+            // MD engine's, always on the same workspace after an ungated
+            // first build) skip the zero fill
+            unsigned* ticket = (unsigned*)(totals + 2);
+            const bool fused = n_cells <= kBinScanCells;
+            if (!gate || !fused) fill(cell_count, n_cells + 1);
+            if (fused) {
+                if (!gate) fill((int32_t*)ticket, 1);
+                k_bin_scan<<<ceil_div(n, kBinScanThreads), kBinScanThreads, 0, s>>>(
+                    pos, n, g, (int)n_cells, cell_of, cell_slot, cell_count, cell_start, totals + 1, ticket, flags,
+                    gate);
+            } else {
+                k_bin<<<nb, tb, 0, s>>>(pos, n, g, cell_of, cell_slot, cell_count, flags, gate);
+                chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s, gate));
+            }
             k_scatter<<<nb, tb, 0, s>>>(n, cell_of, cell_slot, cell_start, cell_atoms, gate);
         } else {
             k_finite<<<nb, tb, 0, s>>>(pos, n, flags, gate);
