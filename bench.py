@@ -130,8 +130,8 @@ def stage_bytes(stage, N, P, precision, D, Fg=None):
     nl = 4 * (N + 1) + 7 * P                     # row_ptr, col (int32), shift (3 x int8)
     atoms = 20 * N                               # position, species, species-grouped row
     return {"aev": atoms + nl + feat * D * N,
-            "aev_adjoint": atoms + nl + 4 * Fg * N + 12 * P,
-            "forces": 4 * (N + 1) + 16 * P + 12 * N,
+            "aev_adjoint": atoms + nl + 4 * Fg * N + 12 * P + 12 * N,   # edge gradients, own-row sums
+            "forces": 4 * (N + 1) + 4 * P + 16 * P + 16 * N + 12 * N,   # rev, reverse gradients, own sums, F
             "neighbors": 12 * N + nl + 4 * P}.get(stage, 0)
 
 
