@@ -289,6 +289,35 @@ def adversarial_cases(r_list=5.1):
     pos = rng.uniform(0, 1, size=(40, 3)).astype(f) * box2
     cases.append(Workload("thin_box", pos.astype(f), (np.arange(40) % 7).astype(np.int32),
                           np.zeros(40, np.int32), 1, box2))
+    # three cells along every dimension (the row builder's stencil-shift
+    # path): atoms on faces, at L - ulp, outside the box (the blocks then
+    # take the minimum image pair by pair)
+    L3 = f(16.0)
+    box3 = np.array([L3, L3, L3], dtype=f)
+    pts = [[0, 0, 0], [np.nextafter(L3, f(0)), 0, 0], [L3 / 2, L3 / 2, L3 / 2],
+           [-0.5, 15.9, 4.0], [16.4, -0.1, 8.0], [5.1, 0, 0], [8.0, 8.0, 0.0],
+           [15.0, 15.0, 15.0], [1.0, 1.0, 1.0], [8.0, 0.0, 8.0], [-15.5, 31.0, 0.5],
+           [16.0 / 3, 16.0 / 3, 32.0 / 3], [32.0 / 3, 0.01, 15.99]]
+    pos = np.array(pts, dtype=f)
+    cases.append(Workload("faces_periodic_3cells", pos, (np.arange(len(pts)) % 7).astype(np.int32),
+                          np.zeros(len(pts), np.int32), 1, box3))
+    # every atom inside the box, three cells per dimension: pairs across the
+    # periodic boundary at r_list and one or two ulp either side of it (their
+    # float32 distance falls in the band the exact predicate decides)
+    pts = []
+    for k, base in enumerate([0.25, 0.75, 1.5]):
+        xb = f(f(base) + L3 - rl)
+        for step in (-2, -1, 0, 1, 2):
+            v = xb
+            for _ in range(abs(step)):
+                v = np.nextafter(v, f(np.inf) if step > 0 else f(-np.inf))
+            a = [base, 2.0 + 3 * k + 0.3 * (step + 2), 7.0]
+            b = [float(v), a[1], a[2]]
+            pts += [a, b] if k != 1 else [[a[1], a[0], a[2]], [b[1], b[0], b[2]]]
+    pts += [[3.0, 12.0, 12.5], [13.0, 4.0, 2.0], [9.5, 9.5, 9.5]]
+    pos = np.array(pts, dtype=f)
+    cases.append(Workload("boundary_cutoff_3cells", pos, (np.arange(len(pts)) % 7).astype(np.int32),
+                          np.zeros(len(pts), np.int32), 1, box3))
     # single atom, and a molecule of one atom beside a molecule of two
     cases.append(Workload("single_atom", np.zeros((1, 3), f), np.zeros(1, np.int32),
                           np.zeros(1, np.int32), 1, None))
