@@ -14,7 +14,9 @@
 //
 // The pair predicate is evaluated in float64 with every operation rounded
 // (floating-point contraction is disabled in that function), so the pair set
-// is reproducible bit for bit by any IEEE implementation.
+// is reproducible bit for bit by any IEEE implementation.  A float32 screen
+// decides every candidate outside a band around r_list^2 that covers its
+// rounding; only the candidates inside the band reach the float64 predicate.
 #include "md_internal.hpp"
 #include "nnp_internal.hpp"
 
