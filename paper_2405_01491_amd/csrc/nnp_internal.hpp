@@ -273,7 +273,8 @@ hipError_t launch_aev_fwd(const AevConst& P, int n, const float* pos, const int3
                           const RowsView& rows, const int32_t* out_row, void* out, bool bf16, unsigned* flags,
                           hipStream_t s, int32_t* rev_out = nullptr, const int32_t* gate = nullptr,
                           uint32_t* amask_out = nullptr);
-// G: one edge gradient per list slot; Gown: per atom, the sum of its row's
+// G: one edge gradient per list slot; Gown: per atom, the sum of its own
+// row's edge gradients (the own part of the force)
 hipError_t launch_aev_bwd(const AevConst& P, int n, const float* pos, const int32_t* species, const BoxConst& bx,
                           const RowsView& rows, const int32_t* g_row, const float* g, float4* G, float4* Gown,
                           float* atom_virial, unsigned* flags, hipStream_t s);
