@@ -373,8 +373,8 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n_atoms, const float* pos, co
 /* Advance n_steps steps.  The steps are enqueued without waiting; the call
  * synchronises `stream` once at the end to read the error flags.  Errors
  * (the state is then that of a run that went on with the faulty values;
- * the step counter is not advanced): NNP_E_NONFINITE, NNP_E_ROW (a rebuild
- * found an atom with more than NNP_MAX_ROW neighbours). */
+ * the step counter counts every step enqueued): NNP_E_NONFINITE, NNP_E_ROW
+ * (a rebuild found an atom with more than NNP_MAX_ROW neighbours). */
 nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream);
 /* Copy the current state into caller device buffers (any may be NULL):
  * pos, vel, forces float32 [n][3], e_pot float64 [1] (the potential energy

@@ -18,9 +18,11 @@
 //   rho_k = sqrt(-2 ln u_k).
 // A run replayed from the same state therefore draws the same noise.
 //
-// Neighbour-list rebuilds are decided on the device (k_md_decide), so the
-// host enqueues whole runs without waiting: the list build kernels read the
-// decision through a gate word and do nothing on steps without a rebuild.
+// Neighbour-list rebuilds are decided on the device (by the cell-binning
+// kernel of the neighbour builder for periodic boxes of up to 8,192 cells,
+// else by k_md_decide), so the host enqueues whole runs without waiting: the
+// later list build kernels read the decision through a gate word and do
+// nothing on steps without a rebuild.
 #include "nnp_internal.hpp"
 #include "md_internal.hpp"
 
@@ -56,13 +58,14 @@ __global__ __launch_bounds__(kFirstThreads) void k_md_first(int n, float* __rest
 }
 
 // Rebuild decision for this step from the blocks' displacements (large
-// systems; small ones decide in the fused front kernel of the neighbour
-// builder).  One block.
-__global__ __launch_bounds__(256) void k_md_decide(MdState* st, const float* __restrict__ d2_part, int n_parts,
-                                                   int rebuild_every, float trig_len) {
+// systems whose binning does not take it; small ones decide in the fused
+// front kernel of the neighbour builder).  One block.
+__global__ __launch_bounds__(256) void k_md_decide(const MdState* cur_st, MdState* nxt,
+                                                   const float* __restrict__ d2_part, int n_parts, int rebuild_every,
+                                                   float trig_len) {
     __shared__ float s_m[256 / kWave][2];
     MdState cur{};
-    if (threadIdx.x == 0) cur = *st;
+    if (threadIdx.x == 0) cur = *cur_st;
     float m1 = 0.f, m2 = 0.f;
     for (int q = threadIdx.x; q < n_parts; q += 256) top2_merge(m1, m2, d2_part[2 * q], d2_part[2 * q + 1]);
     top2_wave(m1, m2);
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(256) void k_md_decide(MdState* st, const float* __r
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int q = 1; q < 256 / kWave; ++q) top2_merge(m1, m2, s_m[q][0], s_m[q][1]);
-        md_decide(st, cur, m1, m2, rebuild_every, trig_len);
+        md_decide(nxt, cur, m1, m2, rebuild_every, trig_len);
     }
 }
 
@@ -85,10 +88,7 @@ __global__ void k_md_wrap_ref(int n, float* pos, float* ref, BoxConst bx, const 
     for (int k = 0; k < 3; ++k) {
         float x = pos[3 * a + k];
         if (bx.periodic) {
-            const float L = bx.L[k];
-            x -= L * floorf(x / L);
-            if (x >= L) x -= L;
-            if (x < 0.f) x = 0.f;
+            x = md_wrap_coord(x, bx.L[k]);
             pos[3 * a + k] = x;
         }
         ref[3 * a + k] = x;
@@ -213,9 +213,9 @@ hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const 
     return hipGetLastError();
 }
 
-hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trig_len,
-                            hipStream_t s) {
-    k_md_decide<<<1, 256, 0, s>>>(st, d2_part, n_parts, rebuild_every, trig_len);
+hipError_t md_launch_decide(const MdState* cur, MdState* nxt, const float* d2_part, int n_parts, int rebuild_every,
+                            float trig_len, hipStream_t s) {
+    k_md_decide<<<1, 256, 0, s>>>(cur, nxt, d2_part, n_parts, rebuild_every, trig_len);
     return hipGetLastError();
 }
 

@@ -34,12 +34,13 @@ struct nnp_md {
     float trig_len = -1.f;     // trigger * skin, or -1 without a skin
     uint64_t step = 0;
     bool small = false;       // fused front / back kernels (md_front_fits)
+    bool fuse_front = false;  // decision and wrap inside the binning kernel (md_front_fuses)
     bool grouped = false;     // species grouping in ws_ef is current
     // device state
     float *pos = nullptr, *vel = nullptr, *F = nullptr, *inv_mass = nullptr, *ref = nullptr;
     int32_t* species = nullptr;
     double* e_pot = nullptr;
-    MdState* st = nullptr;
+    MdState* st = nullptr;    // [2]: step s decides from st[s % 2] into st[(s + 1) % 2]
     unsigned* flags = nullptr;
     double* ke_part = nullptr;
     float* d2_part = nullptr;   // per-block two largest displacements (general path)
@@ -91,31 +92,48 @@ nnp_status status_of_flags(unsigned fl) {
 // row kernel, AEV (with the reverse index on rebuild steps), networks, AEV
 // adjoint, and a fused back kernel (force gather, last half kick and the
 // float64 structure energy): six launches.  Larger systems use the general
-// multi-kernel path for the front and the cell binning.  The potential
-// energy is summed on every step, in the back kernel.
+// multi-kernel path for the front and the cell binning; up to 8,192 cells
+// (md_front_fuses) the binning kernel also takes the rebuild decision and
+// the wrap.  The potential energy is summed on every step, in the back
+// kernel.
 nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     nnp_model* m = md->model;
     const bool langevin = md->p.integrator == NNP_MD_LANGEVIN;
     const float* bptr = md->bx.periodic ? md->box : nullptr;
+    const MdState* cur = md->st + (step & 1);
+    MdState* nxt = md->st + ((step + 1) & 1);
+    MdFront front{};
     prof_begin(m, NNP_STAGE_INTEGRATE, s);
     hipError_t e = hipSuccess;
     if (md->small) {
-        nnp_status st = launch_md_front(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->st,
+        nnp_status st = launch_md_front(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, cur, nxt,
                                         md->p.rebuild_every, md->trig_len, langevin, bptr, md->r_list, md->ws_nb,
                                         md->ws_nb_bytes, md->flags, s);
         if (st != NNP_OK) return st;
     } else {
         e = md_launch_first(md->n, md->pos, md->vel, md->F, md->inv_mass, md->c, step, md->ref, md->d2_part,
                             langevin, s);
-        if (e == hipSuccess)
-            e = md_launch_decide(md->st, md->d2_part, md_first_parts(md->n), md->p.rebuild_every, md->trig_len, s);
-        if (e == hipSuccess) e = md_launch_wrap_ref(md->n, md->pos, md->ref, md->bx, md->st, s);
+        if (md->fuse_front) {
+            front.cur = cur;
+            front.nxt = nxt;
+            front.d2_part = md->d2_part;
+            front.n_parts = md_first_parts(md->n);
+            front.rebuild_every = md->p.rebuild_every;
+            front.trig_len = md->trig_len;
+            front.pos = md->pos;
+            front.ref = md->ref;
+        } else {
+            if (e == hipSuccess)
+                e = md_launch_decide(cur, nxt, md->d2_part, md_first_parts(md->n), md->p.rebuild_every,
+                                     md->trig_len, s);
+            if (e == hipSuccess) e = md_launch_wrap_ref(md->n, md->pos, md->ref, md->bx, nxt, s);
+        }
     }
     prof_end(m, NNP_STAGE_INTEGRATE, s);
     if (e != hipSuccess) return NNP_E_HIP;
     nnp_status st = build_neighbors(m, md->n, md->pos, nullptr, 1, bptr, md->r_list, &md->nl, nullptr, md->ws_nb,
-                                    md->ws_nb_bytes, s, false, md->flags, &md->st->gate, nullptr, md->small,
-                                    &md->rows);
+                                    md->ws_nb_bytes, s, false, md->flags, &nxt->gate, nullptr, md->small,
+                                    &md->rows, md->fuse_front ? &front : nullptr);
     if (st != NNP_OK) return st;
     md->rows.rev = md->nl.rev;
     const bool log = md->p.log_every > 0 && ((step + 1) % (uint64_t)md->p.log_every) == 0 &&
@@ -133,7 +151,7 @@ nnp_status enqueue_step(nnp_md* md, uint64_t step, hipStream_t s) {
     opts.md = &back;
     opts.rows = &md->rows;
     opts.rev_out = md->nl.rev;
-    opts.gate = &md->st->gate;
+    opts.gate = &nxt->gate;
     st = energy_forces_impl(m, md->n, md->pos, md->species, nullptr, 1, bptr, &md->nl, md->e_pot, nullptr, md->F,
                             md->ws_ef, md->ws_ef_bytes, s, md->flags, nullptr, nullptr, &opts);
     if (st != NNP_OK) return st;
@@ -187,6 +205,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     }
     md->r_list = model->aev.rc_r + p.skin;
     md->small = md_front_fits(n, box_host, md->r_list);
+    md->fuse_front = !md->small && md_front_fuses(n, box_host, md->r_list);
     if (box_host)
         for (int k = 0; k < 3; ++k)
             if (!(2.f * md->r_list <= box_host[k])) {
@@ -211,7 +230,7 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     bool ok = dmalloc(&md->pos, v3) == hipSuccess && dmalloc(&md->vel, v3) == hipSuccess &&
               dmalloc(&md->F, v3) == hipSuccess && dmalloc(&md->ref, v3) == hipSuccess &&
               dmalloc(&md->inv_mass, (size_t)n) == hipSuccess && dmalloc(&md->species, (size_t)n) == hipSuccess &&
-              dmalloc(&md->e_pot, 1) == hipSuccess && dmalloc(&md->st, 1) == hipSuccess &&
+              dmalloc(&md->e_pot, 1) == hipSuccess && dmalloc(&md->st, 2) == hipSuccess &&
               dmalloc(&md->flags, 1) == hipSuccess && dmalloc(&md->ke_part, (size_t)md_ke_parts(n)) == hipSuccess &&
               dmalloc(&md->d2_part, 2 * (size_t)md_first_parts(n)) == hipSuccess &&
               dmalloc(&md->e_part, (size_t)md_energy_parts(n)) == hipSuccess && dmalloc(&md->e_ticket, 1) == hipSuccess &&
@@ -229,11 +248,12 @@ nnp_status nnp_md_create(nnp_model* model, int32_t n, const float* pos, const fl
     hipError_t e = hipMemcpyAsync(md->pos, pos, sizeof(float) * v3, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(md->vel, vel, sizeof(float) * v3, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(md->species, species, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(md->st, 0, sizeof(MdState), s);
+    if (e == hipSuccess) e = hipMemsetAsync(md->st, 0, 2 * sizeof(MdState), s);
     if (e == hipSuccess) e = hipMemsetAsync(md->flags, 0, sizeof(unsigned), s);
     if (e == hipSuccess) e = hipMemsetAsync(md->e_ticket, 0, sizeof(unsigned), s);
     if (e == hipSuccess) e = md_launch_inv_mass(n, masses, md->inv_mass, md->flags, s);
-    // the starting configuration: wrapped, reference for displacements, list, forces
+    // the starting configuration: wrapped, reference for displacements, list,
+    // forces; step 0 decides from slot 0
     MdState st0{};
     st0.gate = 1;
     if (e == hipSuccess) e = hipMemcpyAsync(md->st, &st0, sizeof(MdState), hipMemcpyHostToDevice, s);
@@ -278,16 +298,19 @@ nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream) {
     if (!md || n_steps < 0) return NNP_E_ARG;
     if (n_steps == 0) return NNP_OK;
     hipStream_t s = (hipStream_t)stream;
-    for (int k = 0; k < n_steps; ++k) {
-        nnp_status st = enqueue_step(md, md->step + (uint64_t)k, s);
-        if (st != NNP_OK) return st;
+    // steps count once enqueued whole (the state slots and the noise
+    // counters follow md->step), also when a later step or the flags fail
+    nnp_status st = NNP_OK;
+    int k = 0;
+    for (; k < n_steps && st == NNP_OK; ++k) {
+        st = enqueue_step(md, md->step, s);
+        if (st == NNP_OK) md->step += 1;
     }
-    unsigned fl = 0;
-    nnp_status st = read_flags(md, s, &fl);
     if (st != NNP_OK) return st;
-    if (fl) return status_of_flags(fl);
-    md->step += (uint64_t)n_steps;
-    return NNP_OK;
+    unsigned fl = 0;
+    st = read_flags(md, s, &fl);
+    if (st != NNP_OK) return st;
+    return fl ? status_of_flags(fl) : NNP_OK;
 }
 
 nnp_status nnp_md_get(nnp_md* md, float* pos, float* vel, float* forces, double* e_pot, void* stream) {
@@ -319,8 +342,8 @@ nnp_status nnp_md_log(nnp_md* md, double* host_rows, int32_t max_rows, int32_t* 
 nnp_status nnp_md_info(nnp_md* md, nnp_md_stats* out, void* stream) {
     if (!md || !out) return NNP_E_ARG;
     hipStream_t s = (hipStream_t)stream;
-    MdState st;
-    if (hipMemcpyAsync(md->host, md->st, sizeof(MdState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    MdState st;   // the state after the last step's decision
+    if (hipMemcpyAsync(md->host, md->st + (md->step & 1), sizeof(MdState), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return NNP_E_HIP;
     std::memcpy(&st, md->host, sizeof(MdState));

@@ -6,6 +6,9 @@
 namespace nnp {
 
 // Lives in device memory; read by the host only after a synchronisation.
+// The engine keeps two: the decision of step s reads slot s mod 2 and writes
+// slot (s + 1) mod 2, so that every block of a kernel can take the same
+// decision from the old state while one of them records the new one.
 struct MdState {
     int32_t gate;              // 1 on steps that rebuild the neighbour list
     int32_t since;             // steps since the last rebuild
@@ -128,23 +131,53 @@ __device__ __forceinline__ void top2_wave(float& m1, float& m2) {
 // outside the list was at least r_list = Rc + skin apart at the build and
 // its distance has since shrunk by at most d_i + d_j <= d1 + d2, so no pair
 // can come within Rc before the check fires (the Verlet-list bound).  cur is
-// the state as read at the start of the kernel (loaded early, off the
-// critical path); the new state is written to st.
-__device__ __forceinline__ int md_decide(MdState* st, const MdState& cur, float m1, float m2, int rebuild_every,
+// the state before this step's decision; the new state is written whole to
+// nxt unless nxt is null.
+__device__ __forceinline__ int md_decide(MdState* nxt, const MdState& cur, float m1, float m2, int rebuild_every,
                                          float trig_len) {
     const int since = cur.since + 1;
     const bool due = since >= rebuild_every;
     const bool moved = trig_len >= 0.f && !(sqrtf(m1) + sqrtf(m2) <= trig_len);   // NaN rebuilds
     const int gate = due || moved ? 1 : 0;
-    st->gate = gate;
-    st->since = gate ? 0 : since;
-    st->max_d2 = m1;
-    if (gate) {
-        st->rebuilds = cur.rebuilds + 1;
-        if (!due) st->early_rebuilds = cur.early_rebuilds + 1;
+    if (nxt) {
+        MdState o = cur;
+        o.gate = gate;
+        o.since = gate ? 0 : since;
+        o.max_d2 = m1;
+        if (gate) {
+            o.rebuilds = cur.rebuilds + 1;
+            if (!due) o.early_rebuilds = cur.early_rebuilds + 1;
+        }
+        *nxt = o;
     }
     return gate;
 }
+
+// One coordinate wrapped into [0, L) on a rebuild step (the same arithmetic
+// wherever the engine wraps).
+__device__ __forceinline__ float md_wrap_coord(float x, float L) {
+    x -= L * floorf(x / L);
+    if (x >= L) x -= L;
+    if (x < 0.f) x = 0.f;
+    return x;
+}
+
+// The rebuild decision and the wrap of a step, taken by the cell-binning
+// kernel of the neighbour builder (periodic boxes binned and scanned in one
+// kernel): every block reduces d2_part to the same two largest
+// displacements and decides; block 0 records the new state in nxt; on
+// rebuild steps each atom is wrapped into the box and becomes its own
+// displacement reference.
+struct MdFront {
+    const MdState* cur;     // state before this step's decision
+    MdState* nxt;           // state after it
+    const float* d2_part;   // [2 n_parts] per-block two largest squared displacements
+    int n_parts;
+    int rebuild_every;
+    float trig_len;
+    float* pos;             // the positions being binned (wrapped in place)
+    float* ref;             // displacement reference (written on rebuild steps)
+};
 
 // Energy fused into the last kernel of a step: what it needs.
 struct MdEnergyIn {
@@ -172,8 +205,8 @@ struct MdBack {
 int md_first_parts(int n);
 hipError_t md_launch_first(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
                            uint64_t step, const float* ref, float* d2_part, bool langevin, hipStream_t s);
-hipError_t md_launch_decide(MdState* st, const float* d2_part, int n_parts, int rebuild_every, float trig_len,
-                            hipStream_t s);
+hipError_t md_launch_decide(const MdState* cur, MdState* nxt, const float* d2_part, int n_parts, int rebuild_every,
+                            float trig_len, hipStream_t s);
 hipError_t md_launch_wrap_ref(int n, float* pos, float* ref, const BoxConst& bx, const MdState* st, hipStream_t s);
 int md_ke_parts(int n);
 int md_energy_parts(int n);
@@ -182,9 +215,12 @@ hipError_t md_launch_back(int n, const RowsView& rows, const float4* G, const fl
 // neighbors.hip: the fused front of a step for small systems
 bool md_front_fits(int n, const float* box_host, float r_list);
 nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
-                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trig_len, bool langevin,
-                           const float* box_host, float r_list, void* ws, size_t ws_bytes, unsigned* flags,
-                           hipStream_t s);
+                           uint64_t step, float* ref, const MdState* cur, MdState* nxt, int rebuild_every,
+                           float trig_len, bool langevin, const float* box_host, float r_list, void* ws,
+                           size_t ws_bytes, unsigned* flags, hipStream_t s);
+// neighbors.hip: whether build_neighbors can take an MdFront (the binning
+// and scan of this box run as one kernel)
+bool md_front_fuses(int n, const float* box_host, float r_list);
 hipError_t md_launch_log(int n, const double* ke_part, const double* e_pot, double* row, hipStream_t s);
 hipError_t md_launch_inv_mass(int n, const float* masses, float* inv_mass, unsigned* flags, hipStream_t s);
 

@@ -178,7 +178,8 @@ __global__ void k_bin(const float* pos, int n, const Grid g, int32_t* cell_of, i
 // cell_start (n_cells + 1 entries, the total also to *total), after which it
 // zeroes the counts and the ticket for the next build: a build on a
 // workspace left by this kernel needs no zero fill.  The counts are read
-// after the ticket with device-coherent loads.
+// after the ticket with device-coherent loads.  kMd: the MD engine's
+// rebuild decision and wrap come first (MdFront), in place of a gate word.
 constexpr int kBinScanThreads = 1024, kBinScanItems = 8, kBinScanCells = kBinScanThreads * kBinScanItems;
 __device__ __forceinline__ long long wave_inclusive_ll(long long v) {
     const int l = lane_id();
@@ -189,18 +190,53 @@ __device__ __forceinline__ long long wave_inclusive_ll(long long v) {
     }
     return v;
 }
+template <bool kMd>
 __global__ __launch_bounds__(kBinScanThreads) void k_bin_scan(const float* pos, int n, const Grid g, int n_cells,
                                                               int32_t* cell_of, int32_t* cell_slot,
                                                               int32_t* cell_count, int32_t* cell_start,
                                                               int64_t* total, unsigned* ticket, unsigned* flags,
-                                                              const int32_t* gate) {
-    if (gate && *gate == 0) return;
+                                                              const int32_t* gate, const MdFront md) {
     __shared__ long long wsum[kBinScanThreads / kWave];
     __shared__ int s_last;
     const int t = threadIdx.x;
     const int i = blockIdx.x * kBinScanThreads + t;
+    if (kMd) {
+        // the same two largest displacements, in the same order, in every block
+        __shared__ float s_m[kBinScanThreads / kWave][2];
+        MdState cur{};
+        if (t == 0) cur = *md.cur;
+        float m1 = 0.f, m2 = 0.f;
+        for (int q = t; q < md.n_parts; q += kBinScanThreads)
+            top2_merge(m1, m2, md.d2_part[2 * q], md.d2_part[2 * q + 1]);
+        top2_wave(m1, m2);
+        if (lane_id() == 0) {
+            s_m[t / kWave][0] = m1;
+            s_m[t / kWave][1] = m2;
+        }
+        __syncthreads();
+        __shared__ int s_gate;
+        if (t == 0) {
+            for (int q = 1; q < kBinScanThreads / kWave; ++q) top2_merge(m1, m2, s_m[q][0], s_m[q][1]);
+            s_gate = md_decide(blockIdx.x == 0 ? md.nxt : nullptr, cur, m1, m2, md.rebuild_every, md.trig_len);
+        }
+        __syncthreads();
+        if (!s_gate) return;
+    } else if (gate && *gate == 0) {
+        return;
+    }
     if (i < n) {
-        const float3 p = load_pos(pos, i);
+        float3 p = load_pos(pos, i);
+        if (kMd) {   // periodic boxes only: the kernel bins periodic boxes
+            p.x = md_wrap_coord(p.x, g.Lf[0]);
+            p.y = md_wrap_coord(p.y, g.Lf[1]);
+            p.z = md_wrap_coord(p.z, g.Lf[2]);
+            const float w[3] = {p.x, p.y, p.z};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                md.pos[3 * (size_t)i + k] = w[k];
+                md.ref[3 * (size_t)i + k] = w[k];
+            }
+        }
         if (!finite3(p)) {
             set_flag(flags, NNP_FLAG_NONFINITE);
             cell_of[i] = -1;
@@ -739,8 +775,9 @@ constexpr int kFrontPer = kFrontAtoms / kFrontThreads;
 template <bool kLangevin>
 __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     int n, float* __restrict__ pos, float* __restrict__ vel, const float* __restrict__ F,
-    const float* __restrict__ inv_mass, const MdStepConst c, uint64_t step, float* __restrict__ ref, MdState* st,
-    int rebuild_every, float trig_len, const Grid g, int n_cells, int32_t* __restrict__ cell_of,
+    const float* __restrict__ inv_mass, const MdStepConst c, uint64_t step, float* __restrict__ ref,
+    const MdState* cur_st, MdState* nxt, int rebuild_every, float trig_len, const Grid g, int n_cells,
+    int32_t* __restrict__ cell_of,
     int32_t* __restrict__ cell_start, int32_t* __restrict__ cell_atoms, unsigned* flags) {
     __shared__ int s_cnt[kFrontCells + 1];
     __shared__ float s_max[kFrontThreads / kWave][2];
@@ -748,7 +785,7 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     __shared__ int s_gate;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     MdState cur{};
-    if (t == 0) cur = *st;   // read now, used by the decision below
+    if (t == 0) cur = *cur_st;   // read now, used by the decision below
     float m1 = 0.f, m2 = 0.f;   // the two largest squared displacements
     float xs[kFrontPer][3];   // this thread's atoms after the half step (kept for the wrap and binning)
 #pragma unroll
@@ -764,7 +801,7 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     __syncthreads();
     if (t == 0) {
         for (int q = 1; q < kFrontThreads / kWave; ++q) top2_merge(m1, m2, s_max[q][0], s_max[q][1]);
-        s_gate = md_decide(st, cur, m1, m2, rebuild_every, trig_len);
+        s_gate = md_decide(nxt, cur, m1, m2, rebuild_every, trig_len);
     }
     __syncthreads();
     if (!s_gate) return;
@@ -909,6 +946,12 @@ nnp_status make_grid(const float* box_host, float r_list, Grid* g) {
 
 }  // namespace
 
+bool md_front_fuses(int n, const float* box_host, float r_list) {
+    Grid g;
+    if (make_grid(box_host, r_list, &g) != NNP_OK) return false;
+    return n > 0 && g.periodic && (long)g.nc[0] * g.nc[1] * g.nc[2] <= kBinScanCells;
+}
+
 bool md_front_fits(int n, const float* box_host, float r_list) {
     Grid g;
     if (make_grid(box_host, r_list, &g) != NNP_OK) return false;
@@ -917,9 +960,9 @@ bool md_front_fits(int n, const float* box_host, float r_list) {
 }
 
 nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const float* inv_mass, const MdStepConst& c,
-                           uint64_t step, float* ref, MdState* st, int rebuild_every, float trig_len, bool langevin,
-                           const float* box_host, float r_list, void* ws, size_t ws_bytes, unsigned* flags,
-                           hipStream_t s) {
+                           uint64_t step, float* ref, const MdState* cur, MdState* nxt, int rebuild_every,
+                           float trig_len, bool langevin, const float* box_host, float r_list, void* ws,
+                           size_t ws_bytes, unsigned* flags, hipStream_t s) {
     Grid g;
     nnp_status stt = make_grid(box_host, r_list, &g);
     if (stt != NNP_OK) return stt;
@@ -932,12 +975,13 @@ nnp_status launch_md_front(int n, float* pos, float* vel, const float* F, const 
     int32_t* cell_start = (int32_t*)(base + L.cell_start);
     int32_t* cell_atoms = (int32_t*)(base + L.cell_atoms);
     if (langevin)
-        k_md_front<true><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st, rebuild_every,
-                                                     trig_len, g, (int)n_cells, cell_of, cell_start, cell_atoms, flags);
+        k_md_front<true><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, cur, nxt,
+                                                     rebuild_every, trig_len, g, (int)n_cells, cell_of, cell_start,
+                                                     cell_atoms, flags);
     else
-        k_md_front<false><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, st, rebuild_every,
-                                                      trig_len, g, (int)n_cells, cell_of, cell_start, cell_atoms,
-                                                      flags);
+        k_md_front<false><<<1, kFrontThreads, 0, s>>>(n, pos, vel, F, inv_mass, c, step, ref, cur, nxt,
+                                                      rebuild_every, trig_len, g, (int)n_cells, cell_of, cell_start,
+                                                      cell_atoms, flags);
     return hipGetLastError() == hipSuccess ? NNP_OK : NNP_E_HIP;
 }
 
@@ -954,11 +998,15 @@ nnp_status read_and_clear_flags(nnp_model* m, hipStream_t s, uint32_t* out, int6
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host,
                            void* ws, size_t ws_bytes, hipStream_t s, bool sync, unsigned* flags_override,
-                           const int32_t* gate, int64_t* need_pairs, bool cells_ready, RowsView* rows_out) {
+                           const int32_t* gate, int64_t* need_pairs, bool cells_ready, RowsView* rows_out,
+                           const MdFront* front) {
     Grid g;
     nnp_status st = make_grid(box_host, r_list, &g);
     if (st != NNP_OK) return st;
     const long n_cells = g.periodic ? (long)g.nc[0] * g.nc[1] * g.nc[2] : 1;
+    // the MD front rides on the one-kernel binning of a gated build
+    if (front && !(gate && g.periodic && !mol && !cells_ready && n > 0 && n_cells <= kBinScanCells))
+        return NNP_E_ARG;
     const WsLayout L = ws_layout(n, n_mol, n_cells);
     if (!ws || ws_bytes < L.end) return NNP_E_ARG;
     char* base = (char*)ws;
@@ -1004,9 +1052,14 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
             if (!gate || !fused) fill(cell_count, n_cells + 1);
             if (fused) {
                 if (!gate) fill((int32_t*)ticket, 1);
-                k_bin_scan<<<ceil_div(n, kBinScanThreads), kBinScanThreads, 0, s>>>(
-                    pos, n, g, (int)n_cells, cell_of, cell_slot, cell_count, cell_start, totals + 1, ticket, flags,
-                    gate);
+                if (front)
+                    k_bin_scan<true><<<ceil_div(n, kBinScanThreads), kBinScanThreads, 0, s>>>(
+                        pos, n, g, (int)n_cells, cell_of, cell_slot, cell_count, cell_start, totals + 1, ticket,
+                        flags, gate, *front);
+                else
+                    k_bin_scan<false><<<ceil_div(n, kBinScanThreads), kBinScanThreads, 0, s>>>(
+                        pos, n, g, (int)n_cells, cell_of, cell_slot, cell_count, cell_start, totals + 1, ticket,
+                        flags, gate, MdFront{});
             } else {
                 k_bin<<<nb, tb, 0, s>>>(pos, n, g, cell_of, cell_slot, cell_count, flags, gate);
                 chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s, gate));

@@ -164,11 +164,14 @@ size_t neighbors_ws_bytes(int32_t n_atoms, int32_t n_mol, const float* box_host,
 // there instead of compacting into nl (its CSR arrays are not touched; the
 // reverse index is left to the caller).
 struct RowsView;
+struct MdFront;
+// front (MD engine, with gate = &front->nxt->gate): the step's rebuild
+// decision and wrap, taken by the binning kernel (md_front_fuses)
 nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const int32_t* mol, int32_t n_mol,
                            const float* box_host, float r_list, nnp_nlist* nl, int64_t* n_pairs_host, void* ws,
                            size_t ws_bytes, hipStream_t s, bool sync = true, unsigned* flags_override = nullptr,
                            const int32_t* gate = nullptr, int64_t* need_pairs = nullptr, bool cells_ready = false,
-                           RowsView* rows_out = nullptr);
+                           RowsView* rows_out = nullptr, const MdFront* front = nullptr);
 struct MdBack;
 struct MdEnergyIn;
 // Options of the MD engine's calls: skip the species grouping (species and
