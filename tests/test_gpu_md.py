@@ -250,8 +250,9 @@ def test_engine_forces_equal_plain_path(spec_bias, n_mol):
 
 
 def test_engine_general_path_tracks_oracle(spec_bias):
-    """Above 8,192 atoms the engine runs the general multi-kernel step (separate
-    integrator, decision, wrap, binning and energy-sum kernels)."""
+    """Above 8,192 atoms the engine runs the general multi-kernel step (its own
+    integrator kernel; the rebuild decision and the wrap inside the binning
+    kernel of the periodic box)."""
     w = synthetic.geometry.water_box(3000, seed=21)          # 9,000 atoms
     model = nnp.Model(spec_bias, "fp32")
     masses = synthetic.MASSES[w.species]
@@ -270,3 +271,27 @@ def test_engine_general_path_tracks_oracle(spec_bias):
           % (dx, dv, abs(float(e[0]) - en[-1][0]), eng.info()))
     assert dx < 1e-4 and dv < 1e-5
     assert abs(float(e[0]) - en[-1][0]) < 1e-5 * max(1.0, abs(en[-1][0]))
+
+
+def test_engine_open_general_path_tracks_oracle(spec_bias):
+    """An open system above 8,192 atoms: the rebuild decision and the new
+    reference run as kernels of their own (the binning kernel takes them only
+    for periodic boxes).  Rebuilt every second step."""
+    wb = synthetic.geometry.water_box(3000, seed=23)          # 9,000 atoms, taken without the box
+    w = synthetic.geometry.Workload("water_cube_open_9000", wb.pos, wb.species, wb.mol, wb.n_mol, None)
+    model = nnp.Model(spec_bias, "fp32")
+    masses = synthetic.MASSES[w.species]
+    v0 = nmd.maxwell_boltzmann(masses, 300.0, seed=24)
+    eng = _engine(model, w, v0, dt=0.5, skin=0.5, rebuild_every=2)
+    eng.run(4)
+    x, v, F, e = [t.cpu().numpy() for t in eng.state()]
+    nl = oracle.neighbor_list(w.pos, None, None, 5.6)
+    xr, vr, en = oracle.velocity_verlet(w.pos, v0, masses,
+                                        lambda y: oracle.energy_forces_f64(y, w.species, None, spec_bias, nl),
+                                        0.5, 4)
+    info = eng.info()
+    print("engine open general path 4 steps: max |dx| %.3g A, max |dv| %.3g A/fs, |dE| %.3g eV, info %s"
+          % (np.abs(x - xr).max(), np.abs(v - vr).max(), abs(float(e[0]) - en[-1][0]), info))
+    assert np.abs(x - xr).max() < 1e-4 and np.abs(v - vr).max() < 1e-5
+    assert abs(float(e[0]) - en[-1][0]) < 1e-5 * max(1.0, abs(en[-1][0]))
+    assert info["steps"] == 4 and info["rebuilds"] >= 3
