@@ -300,13 +300,12 @@ nnp_status nnp_md_run(nnp_md* md, int32_t n_steps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     // steps count once enqueued whole (the state slots and the noise
     // counters follow md->step), also when a later step or the flags fail
-    nnp_status st = NNP_OK;
-    int k = 0;
-    for (; k < n_steps && st == NNP_OK; ++k) {
-        st = enqueue_step(md, md->step, s);
-        if (st == NNP_OK) md->step += 1;
+    for (int k = 0; k < n_steps; ++k) {
+        const nnp_status st = enqueue_step(md, md->step, s);
+        if (st != NNP_OK) return st;
+        md->step += 1;
     }
-    if (st != NNP_OK) return st;
+    nnp_status st;
     unsigned fl = 0;
     st = read_flags(md, s, &fl);
     if (st != NNP_OK) return st;
