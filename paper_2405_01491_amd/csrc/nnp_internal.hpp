@@ -231,10 +231,14 @@ struct RowsView {
 // of the total energy), F_a = sum_j G_aj - G_ja: the own part sum_j G_aj
 // comes summed by the adjoint kernel (Gown[a]), the reverse part G_ja is
 // read at rev[p] by kGatherLanes lanes striding over the row, then summed by
-// a fixed butterfly.  The plain path's gather and the MD engine's last
-// kernel both use it, so the two give the same forces bit for bit at the
-// same positions.
+// a fixed butterfly.  A lane takes its slots kGatherBatch at a time: every
+// reverse index of a batch is loaded before any gradient, so that its loads
+// are in flight together (one slot at a time, each slot cost two dependent
+// memory latencies); each lane still adds its slots in ascending order.  The
+// plain path's gather and the MD engine's last kernel both use it, so the two
+// give the same forces bit for bit at the same positions.
 constexpr int kGatherLanes = 32;
+constexpr int kGatherBatch = 4;
 
 __device__ __forceinline__ float3 gather_row_force(const RowsView& rows, const int32_t* __restrict__ rev,
                                                    const float4* __restrict__ G, const float4* __restrict__ Gown,
@@ -244,11 +248,23 @@ __device__ __forceinline__ float3 gather_row_force(const RowsView& rows, const i
     if (a < n) {
         if (sub == 0) own = Gown[a];
         const int b = rows.begin(a), e = rows.end(a);
-        for (int p = b + sub; p < e; p += kGatherLanes) {
-            const float4 gq = G[rev[p]];
-            fx += gq.x;
-            fy += gq.y;
-            fz += gq.z;
+        for (int p0 = b + sub; p0 < e; p0 += kGatherBatch * kGatherLanes) {
+            int q[kGatherBatch];
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                const int p = p0 + u * kGatherLanes;
+                q[u] = p < e ? rev[p] : -1;   // a slot's reverse index is >= 0
+            }
+            float4 gq[kGatherBatch];
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) gq[u] = q[u] >= 0 ? G[q[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                if (q[u] < 0) continue;
+                fx += gq[u].x;
+                fy += gq[u].y;
+                fz += gq[u].z;
+            }
         }
     }
 #pragma unroll
