@@ -237,8 +237,8 @@ struct RowsView {
 // memory latencies); each lane still adds its slots in ascending order.  The
 // plain path's gather and the MD engine's last kernel both use it, so the two
 // give the same forces bit for bit at the same positions.
-constexpr int kGatherLanes = 32;
-constexpr int kGatherBatch = 4;
+constexpr int kGatherLanes = 8;
+constexpr int kGatherBatch = 16;
 
 __device__ __forceinline__ float3 gather_row_force(const RowsView& rows, const int32_t* __restrict__ rev,
                                                    const float4* __restrict__ G, const float4* __restrict__ Gown,
