@@ -106,6 +106,7 @@ __global__ void k_md_wrap_ref(int n, float* pos, float* ref, BoxConst bx, const 
 // scheduling.
 constexpr int kBackThreads = 256, kBackAtoms = kBackThreads / kGatherLanes;
 constexpr int kEChunk = 4096;
+static_assert(kEChunk % kBackThreads == 0, "whole energy chunks per thread");
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
     red[threadIdx.x] = v;
@@ -124,15 +125,32 @@ __global__ __launch_bounds__(kBackThreads) void k_md_back(int n, int ne, const R
                                                          const float* __restrict__ inv_mass, float dt, double* ke_part,
                                                          const MdEnergyIn E) {
     __shared__ double red[kBackThreads];
+    __shared__ double s_se[kMaxSpecies];
     __shared__ int last;
     int blk = blockIdx.x;
     if (kEnergy) {
         if (blk < ne) {
+            // a thread's kEPer atoms: every load first, then the sum in
+            // ascending atom order (the self energies from LDS)
+            constexpr int kEPer = kEChunk / kBackThreads;
+            if (threadIdx.x < kMaxSpecies) s_se[threadIdx.x] = E.se[threadIdx.x];
             const int base = blk * kEChunk;
             const int stop = min(n, base + kEChunk);
+            int pr[kEPer], sp[kEPer];
+            float ea[kEPer];
+#pragma unroll
+            for (int u = 0; u < kEPer; ++u) {
+                const int a = base + (int)threadIdx.x + u * kBackThreads;
+                const bool in = a < stop;
+                pr[u] = in ? E.prow[a] : -1;
+                sp[u] = in ? E.species[a] : 0;
+                ea[u] = in ? E.E_at[a] : 0.f;
+            }
+            __syncthreads();   // s_se
             double acc = 0.0;
-            for (int a = base + threadIdx.x; a < stop; a += kBackThreads)
-                if (E.prow[a] >= 0) acc += (double)E.E_at[a] + E.se[E.species[a]];
+#pragma unroll
+            for (int u = 0; u < kEPer; ++u)
+                if (pr[u] >= 0) acc += (double)ea[u] + s_se[sp[u]];   // a grouped atom has a valid species
             const double tot = block_sum(acc, red);
             if (ne == 1) {
                 if (threadIdx.x == 0) *E.e_pot = tot;

@@ -67,24 +67,43 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t step, int a, floa
 // First part of a step for atom a: velocity Verlet B(dt/2) A(dt), or BAOAB
 // B(dt/2) A(dt/2) O A(dt/2).  Returns the squared displacement from ref
 // (+inf if it is not finite, so that the list is rebuilt and the rebuild
-// flags the coordinates).
+// flags the coordinates).  md_first_load reads what the step needs, so that
+// a thread with several atoms can issue every load before the first use;
+// md_first_finish computes and stores.
+struct MdAtomIn {
+    float im, v[3], f[3], x[3], r[3];
+};
+
+__device__ __forceinline__ MdAtomIn md_first_load(int a, const float* __restrict__ pos,
+                                                  const float* __restrict__ vel, const float* __restrict__ F,
+                                                  const float* __restrict__ inv_mass, const float* __restrict__ ref) {
+    MdAtomIn q;
+    q.im = inv_mass[a];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        q.v[k] = vel[3 * a + k];
+        q.f[k] = F[3 * a + k];
+        q.x[k] = pos[3 * a + k];
+        q.r[k] = ref[3 * a + k];
+    }
+    return q;
+}
+
 template <bool kLangevin>
-__device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, float* __restrict__ vel,
-                                               const float* __restrict__ F, const float* __restrict__ inv_mass,
-                                               const MdStepConst& c, uint64_t step, const float* __restrict__ ref,
-                                               float* xout = nullptr) {
-    const float im = inv_mass[a];
-    const float kick = 0.5f * c.dt * kAccUnit * im;
+__device__ __forceinline__ float md_first_finish(int a, const MdAtomIn& q, float* __restrict__ pos,
+                                                 float* __restrict__ vel, const MdStepConst& c, uint64_t step,
+                                                 float* xout = nullptr) {
+    const float kick = 0.5f * c.dt * kAccUnit * q.im;
     float x[3], v[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        v[k] = vel[3 * a + k] + kick * F[3 * a + k];
-        x[k] = pos[3 * a + k];
+        v[k] = q.v[k] + kick * q.f[k];
+        x[k] = q.x[k];
     }
     if (kLangevin) {
         float xi[3];
         gauss3(c.seed, step, a, xi);
-        const float sig = c.c2 * sqrtf(c.kT * kAccUnit * im);
+        const float sig = c.c2 * sqrtf(c.kT * kAccUnit * q.im);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             x[k] += 0.5f * c.dt * v[k];
@@ -101,10 +120,18 @@ __device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, f
         vel[3 * a + k] = v[k];
         pos[3 * a + k] = x[k];
         if (xout) xout[k] = x[k];
-        const float d = x[k] - ref[3 * a + k];
+        const float d = x[k] - q.r[k];
         d2 += d * d;
     }
     return d2 <= INFINITY ? d2 : INFINITY;
+}
+
+template <bool kLangevin>
+__device__ __forceinline__ float md_first_atom(int a, float* __restrict__ pos, float* __restrict__ vel,
+                                               const float* __restrict__ F, const float* __restrict__ inv_mass,
+                                               const MdStepConst& c, uint64_t step, const float* __restrict__ ref,
+                                               float* xout = nullptr) {
+    return md_first_finish<kLangevin>(a, md_first_load(a, pos, vel, F, inv_mass, ref), pos, vel, c, step, xout);
 }
 
 // The two largest squared displacements of a set of atoms (m1 >= m2):

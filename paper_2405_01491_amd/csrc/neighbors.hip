@@ -771,6 +771,8 @@ constexpr int kFrontThreads = 1024;
 constexpr int kFrontAtoms = 8192;
 constexpr int kFrontCells = 4096;
 constexpr int kFrontPer = kFrontAtoms / kFrontThreads;
+constexpr int kFrontBatch = 4;
+static_assert(kFrontPer % kFrontBatch == 0, "whole batches of atoms per thread");
 
 template <bool kLangevin>
 __global__ __launch_bounds__(kFrontThreads) void k_md_front(
@@ -788,10 +790,20 @@ __global__ __launch_bounds__(kFrontThreads) void k_md_front(
     if (t == 0) cur = *cur_st;   // read now, used by the decision below
     float m1 = 0.f, m2 = 0.f;   // the two largest squared displacements
     float xs[kFrontPer][3];   // this thread's atoms after the half step (kept for the wrap and binning)
+    // the atoms kFrontBatch at a time: every load of a batch before its first use
 #pragma unroll
-    for (int k = 0; k < kFrontPer; ++k) {
-        const int a = t + k * kFrontThreads;
-        if (a < n) top2_add(m1, m2, md_first_atom<kLangevin>(a, pos, vel, F, inv_mass, c, step, ref, xs[k]));
+    for (int k0 = 0; k0 < kFrontPer; k0 += kFrontBatch) {
+        MdAtomIn in[kFrontBatch];
+#pragma unroll
+        for (int u = 0; u < kFrontBatch; ++u) {
+            const int a = t + (k0 + u) * kFrontThreads;
+            if (a < n) in[u] = md_first_load(a, pos, vel, F, inv_mass, ref);
+        }
+#pragma unroll
+        for (int u = 0; u < kFrontBatch; ++u) {
+            const int a = t + (k0 + u) * kFrontThreads;
+            if (a < n) top2_add(m1, m2, md_first_finish<kLangevin>(a, in[u], pos, vel, c, step, xs[k0 + u]));
+        }
     }
     top2_wave(m1, m2);
     if (l == 0) {
