@@ -18,11 +18,12 @@
 //   rho_k = sqrt(-2 ln u_k).
 // A run replayed from the same state therefore draws the same noise.
 //
-// Neighbour-list rebuilds are decided on the device (by the cell-binning
-// kernel of the neighbour builder for periodic boxes of up to 8,192 cells,
-// else by k_md_decide), so the host enqueues whole runs without waiting: the
-// later list build kernels read the decision through a gate word and do
-// nothing on steps without a rebuild.
+// Neighbour-list rebuilds are decided on the device (by the fused front
+// kernel of small systems, by the cell-binning kernel of the neighbour
+// builder for larger periodic boxes of up to 8,192 cells, else by
+// k_md_decide), so the host enqueues whole runs without waiting: the later
+// list build kernels read the decision through a gate word and do nothing on
+// steps without a rebuild.
 #include "nnp_internal.hpp"
 #include "md_internal.hpp"
 
