@@ -8,6 +8,7 @@ import oracle
 import synthetic
 import paper_2405_01491_amd as nnp
 from paper_2405_01491_amd import md as nmd
+from paper_2405_01491_amd import _lib
 from tests.gpu_helpers import dev, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -295,3 +296,22 @@ def test_engine_open_general_path_tracks_oracle(spec_bias):
     assert np.abs(x - xr).max() < 1e-4 and np.abs(v - vr).max() < 1e-5
     assert abs(float(e[0]) - en[-1][0]) < 1e-5 * max(1.0, abs(en[-1][0]))
     assert info["steps"] == 4 and info["rebuilds"] >= 3
+
+
+@pytest.mark.parametrize("n_mol", [64, 3000])
+def test_engine_nonfinite_velocity_is_flagged(spec, n_mol):
+    """A non-finite velocity makes the step's displacement infinite, so the
+    list is rebuilt and the rebuild flags the coordinate: the run returns
+    NNP_E_NONFINITE, and the steps it enqueued still count (the engine's state
+    slots and noise counters follow them).  192 atoms take the fused front
+    kernel, 9,000 the binning kernel's decision."""
+    w = synthetic.geometry.water_box(n_mol, seed=41)
+    model = nnp.Model(spec, "fp32")
+    masses = synthetic.MASSES[w.species]
+    v0 = nmd.maxwell_boltzmann(masses, 300.0, seed=42)
+    v0[7, 1] = np.nan
+    eng = _engine(model, w, v0, dt=0.5, skin=0.5, rebuild_every=20)
+    with pytest.raises(nnp.NNPError) as e:
+        eng.run(3)
+    assert e.value.status == _lib.NNP_E_NONFINITE
+    assert eng.info()["steps"] == 3
