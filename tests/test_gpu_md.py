@@ -315,3 +315,29 @@ def test_engine_nonfinite_velocity_is_flagged(spec, n_mol):
         eng.run(3)
     assert e.value.status == _lib.NNP_E_NONFINITE
     assert eng.info()["steps"] == 3
+
+
+@pytest.mark.parametrize("case", ["faces_periodic_3cells", "boundary_cutoff_3cells"])
+def test_engine_forces_equal_plain_path_adversarial(spec_bias, case):
+    """The builder's adversarial boxes at the engine's list radius (atoms on
+    the faces, at L - ulp and outside the box; pairs across the periodic
+    boundary within two ulp of r_list): the engine's set-up (wrap into the
+    box, fixed-stride rows, reverse index from the AEV kernel, force gather)
+    and one step (the fused front's wrap and binning, the row kernel, the
+    last kernel's gather) give the plain path's forces bit for bit at the
+    engine's own positions."""
+    model = nnp.Model(spec_bias, "fp32")
+    w = next(c for c in synthetic.geometry.adversarial_cases(r_list=float(model.spec.rc_r)) if c.name == case)
+    v0 = np.zeros((w.n_atoms, 3), np.float32)
+    eng = _engine(model, w, v0, dt=0.01)                # no skin: the list is rebuilt every step
+    sp = torch.from_numpy(w.species).to(dev())
+    for k in range(2):
+        x, _, F, _ = eng.state()
+        assert bool(((x >= 0) & (x < torch.from_numpy(w.box).to(dev()))).all())   # wrapped into the box
+        nl = nnp.nnp_neighbors(model, x, None, 1, w.box, model.spec.rc_r)
+        _, _, F2 = nnp.nnp_energy_forces(model, x, sp, None, 1, w.box, nl)
+        print("%s, after %d steps: %d pairs, max |F| %.3g, max |dF| %.3g"
+              % (case, k, nl.n_pairs, float(F2.abs().max()), float((F - F2).abs().max())))
+        assert torch.isfinite(F).all()
+        assert torch.equal(F, F2)
+        eng.run(1)
