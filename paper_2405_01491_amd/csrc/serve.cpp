@@ -87,26 +87,37 @@ struct Arena {
     }
 };
 
+// A launch's inputs and outputs in one buffer (device, and pinned host
+// staging of the same layout), packed for its n atoms and nm requests:
+//   positions [3n] f32 | species [n] i32 | structure index [n] i32 |
+//   flags (8 bytes) | energies [nm] f64 | forces [3n] f32
+// so that one copy takes the inputs and the zeroed flags word up, and one
+// copy brings the flags, energies and forces back.
+struct IoLayout {
+    size_t sp, mol, flags, e, f, end;
+};
+
+IoLayout io_layout(int n, int nm) {
+    IoLayout o;
+    o.sp = 12 * (size_t)n;
+    o.mol = 16 * (size_t)n;
+    o.flags = (20 * (size_t)n + 7) & ~(size_t)7;
+    o.e = o.flags + 8;
+    o.f = o.e + 8 * (size_t)nm;
+    o.end = o.f + 12 * (size_t)n;
+    return o;
+}
+
 struct Launch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    float* d_pos = nullptr;
-    int32_t* d_sp = nullptr;
-    int32_t* d_mol = nullptr;
-    double* d_e = nullptr;
-    float* d_f = nullptr;
-    unsigned* d_flags = nullptr;
+    char* d_io = nullptr;         // IoLayout for kLaunchAtoms, kLaunchRequests
+    char* h_io = nullptr;         // pinned, the same size
     nnp_nlist nl{};
     void* d_nbws = nullptr;
     size_t nbws_bytes = 0;
     void* d_ws = nullptr;
     size_t ws_bytes = 0;
-    float* h_pos = nullptr;
-    int32_t* h_sp = nullptr;
-    int32_t* h_mol = nullptr;
-    double* h_e = nullptr;
-    float* h_f = nullptr;
-    unsigned* h_flags = nullptr;
     std::vector<uint64_t> tickets;
     std::vector<int> offsets;
     int n_atoms = 0;
@@ -147,9 +158,9 @@ void free_launch(Launch& L) {
     auto df = [](void* p) { if (p) (void)hipFree(p); };
     auto hf = [](void* p) { if (p) (void)hipHostFree(p); };
     if (L.stream) (void)hipStreamSynchronize(L.stream);
-    df(L.d_pos); df(L.d_sp); df(L.d_mol); df(L.d_e); df(L.d_f); df(L.d_flags);
+    df(L.d_io);
     df(L.nl.row_ptr); df(L.nl.col); df(L.nl.shift); df(L.nl.rev); df(L.d_nbws); df(L.d_ws);
-    hf(L.h_pos); hf(L.h_sp); hf(L.h_mol); hf(L.h_e); hf(L.h_f); hf(L.h_flags);
+    hf(L.h_io);
     if (L.done) (void)hipEventDestroy(L.done);
     if (L.stream) (void)hipStreamDestroy(L.stream);
     L = Launch();
@@ -160,12 +171,8 @@ bool alloc_launch(nnp_server* S, Launch& L) {
     const int64_t P = S->pair_cap;
     bool ok = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipMalloc(&L.d_pos, sizeof(float) * 3 * A) == hipSuccess;
-    ok = ok && hipMalloc(&L.d_sp, sizeof(int32_t) * A) == hipSuccess;
-    ok = ok && hipMalloc(&L.d_mol, sizeof(int32_t) * A) == hipSuccess;
-    ok = ok && hipMalloc(&L.d_e, sizeof(double) * R) == hipSuccess;
-    ok = ok && hipMalloc(&L.d_f, sizeof(float) * 3 * A) == hipSuccess;
-    ok = ok && hipMalloc(&L.d_flags, 256) == hipSuccess;
+    const size_t io = io_layout(A, R).end;   // the largest launch's layout
+    ok = ok && hipMalloc(&L.d_io, io) == hipSuccess;
     ok = ok && hipMalloc(&L.nl.row_ptr, sizeof(int32_t) * (A + 1)) == hipSuccess;
     ok = ok && hipMalloc(&L.nl.col, sizeof(int32_t) * P) == hipSuccess;
     ok = ok && hipMalloc(&L.nl.shift, 3 * P) == hipSuccess;
@@ -175,12 +182,7 @@ bool alloc_launch(nnp_server* S, Launch& L) {
     L.ws_bytes = nnp_workspace_bytes(S->model, A, P);
     ok = ok && hipMalloc(&L.d_nbws, L.nbws_bytes) == hipSuccess;
     ok = ok && hipMalloc(&L.d_ws, L.ws_bytes) == hipSuccess;
-    ok = ok && hipHostMalloc(&L.h_pos, sizeof(float) * 3 * A, 0) == hipSuccess;
-    ok = ok && hipHostMalloc(&L.h_sp, sizeof(int32_t) * A, 0) == hipSuccess;
-    ok = ok && hipHostMalloc(&L.h_mol, sizeof(int32_t) * A, 0) == hipSuccess;
-    ok = ok && hipHostMalloc(&L.h_e, sizeof(double) * R, 0) == hipSuccess;
-    ok = ok && hipHostMalloc(&L.h_f, sizeof(float) * 3 * A, 0) == hipSuccess;
-    ok = ok && hipHostMalloc(&L.h_flags, 256, 0) == hipSuccess;
+    ok = ok && hipHostMalloc(&L.h_io, io, 0) == hipSuccess;
     return ok;
 }
 
@@ -188,36 +190,39 @@ bool alloc_launch(nnp_server* S, Launch& L) {
 nnp_status enqueue(nnp_server* S, Launch& L) {
     hipStream_t s = L.stream;
     const int n = L.n_atoms, nm = (int)L.tickets.size();
-    bool ok = hipMemcpyAsync(L.d_pos, L.h_pos, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(L.d_sp, L.h_sp, sizeof(int32_t) * n, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(L.d_mol, L.h_mol, sizeof(int32_t) * n, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemsetAsync(L.d_flags, 0, sizeof(unsigned), s) == hipSuccess;
-    if (!ok) return NNP_E_HIP;
-    nnp_status st = build_neighbors(S->model, n, L.d_pos, L.d_mol, nm, nullptr, S->model->aev.rc_r, &L.nl, nullptr,
-                                    L.d_nbws, L.nbws_bytes, s, false, L.d_flags);
+    const IoLayout o = io_layout(n, nm);
+    std::memset(L.h_io + o.flags, 0, 8);
+    if (hipMemcpyAsync(L.d_io, L.h_io, o.e, hipMemcpyHostToDevice, s) != hipSuccess) return NNP_E_HIP;
+    const float* d_pos = (const float*)L.d_io;
+    const int32_t* d_sp = (const int32_t*)(L.d_io + o.sp);
+    const int32_t* d_mol = (const int32_t*)(L.d_io + o.mol);
+    unsigned* d_flags = (unsigned*)(L.d_io + o.flags);
+    nnp_status st = build_neighbors(S->model, n, d_pos, d_mol, nm, nullptr, S->model->aev.rc_r, &L.nl, nullptr,
+                                    L.d_nbws, L.nbws_bytes, s, false, d_flags);
     if (st != NNP_OK) return st;
-    st = energy_forces_impl(S->model, n, L.d_pos, L.d_sp, L.d_mol, nm, nullptr, &L.nl, L.d_e, nullptr, L.d_f, L.d_ws,
-                            L.ws_bytes, s, L.d_flags);
+    st = energy_forces_impl(S->model, n, d_pos, d_sp, d_mol, nm, nullptr, &L.nl, (double*)(L.d_io + o.e), nullptr,
+                            (float*)(L.d_io + o.f), L.d_ws, L.ws_bytes, s, d_flags);
     if (st != NNP_OK) return st;
-    ok = hipMemcpyAsync(L.h_e, L.d_e, sizeof(double) * nm, hipMemcpyDeviceToHost, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(L.h_f, L.d_f, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(L.h_flags, L.d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, s) == hipSuccess;
+    bool ok = hipMemcpyAsync(L.h_io + o.flags, L.d_io + o.flags, o.end - o.flags, hipMemcpyDeviceToHost, s) ==
+              hipSuccess;
     ok = ok && hipEventRecord(L.done, s) == hipSuccess;
     return ok ? NNP_OK : NNP_E_HIP;
 }
 
 // results of a finished launch into the requests (lock held)
 void finish(nnp_server* S, Launch& L, nnp_status launch_err) {
-    const unsigned fl = *L.h_flags;
-    const nnp_status st = launch_err != NNP_OK ? launch_err : flags_status(fl);
+    const IoLayout o = io_layout(L.n_atoms, (int)L.tickets.size());
+    const double* h_e = (const double*)(L.h_io + o.e);
+    const float* h_f = (const float*)(L.h_io + o.f);
+    const nnp_status st = launch_err != NNP_OK ? launch_err : flags_status(*(const unsigned*)(L.h_io + o.flags));
     for (size_t k = 0; k < L.tickets.size(); ++k) {
         auto it = S->reqs.find(L.tickets[k]);
         if (it == S->reqs.end()) continue;
         Req& r = it->second;
         S->arena.release(r.off, r.bytes);   // request memory is held until its launch completes
         if (st == NNP_OK) {
-            r.energy = L.h_e[k];
-            r.forces.assign(L.h_f + 3 * (size_t)L.offsets[k], L.h_f + 3 * ((size_t)L.offsets[k] + r.n));
+            r.energy = h_e[k];
+            r.forces.assign(h_f + 3 * (size_t)L.offsets[k], h_f + 3 * ((size_t)L.offsets[k] + r.n));
             r.state = kDone;
         } else {
             r.err = st;
@@ -251,21 +256,27 @@ void worker_main(nnp_server* S) {
             for (auto& c : S->launches)
                 if (!c.busy) { L = &c; break; }
             if (L) {
-                // gather queued requests FIFO into the launch's pinned staging
+                // the queued requests that fit (FIFO), then packed into the
+                // launch's pinned staging in its layout
                 L->n_atoms = 0;
                 while (!S->queue.empty() && (int)L->tickets.size() < kLaunchRequests) {
                     Req& r = S->reqs[S->queue.front()];
                     if (L->n_atoms + r.n > kLaunchAtoms) break;
-                    const char* src = S->inbox + r.off;
-                    std::memcpy(L->h_pos + 3 * (size_t)L->n_atoms, src, sizeof(float) * 3 * r.n);
-                    std::memcpy(L->h_sp + L->n_atoms, src + sizeof(float) * 3 * r.n, sizeof(int32_t) * r.n);
-                    const int mi = (int)L->tickets.size();
-                    for (int a = 0; a < r.n; ++a) L->h_mol[L->n_atoms + a] = mi;
                     L->tickets.push_back(S->queue.front());
                     L->offsets.push_back(L->n_atoms);
                     L->n_atoms += r.n;
                     r.state = kRunning;
                     S->queue.pop_front();
+                }
+                const IoLayout o = io_layout(L->n_atoms, (int)L->tickets.size());
+                for (size_t m = 0; m < L->tickets.size(); ++m) {
+                    const Req& r = S->reqs[L->tickets[m]];
+                    const char* src = S->inbox + r.off;
+                    const size_t a0 = (size_t)L->offsets[m];
+                    std::memcpy(L->h_io + 12 * a0, src, sizeof(float) * 3 * r.n);
+                    std::memcpy(L->h_io + o.sp + 4 * a0, src + sizeof(float) * 3 * r.n, sizeof(int32_t) * r.n);
+                    int32_t* mol = (int32_t*)(L->h_io + o.mol) + a0;
+                    for (int a = 0; a < r.n; ++a) mol[a] = (int32_t)m;
                 }
                 L->busy = true;
                 S->n_launches += 1;
@@ -275,7 +286,6 @@ void worker_main(nnp_server* S) {
                 lk.lock();
                 if (st != NNP_OK) {
                     (void)hipStreamSynchronize(L->stream);
-                    *L->h_flags = 0;
                     finish(S, *L, st);
                 }
                 did = true;
