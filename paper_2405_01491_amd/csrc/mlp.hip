@@ -467,9 +467,10 @@ __global__ __launch_bounds__(1024) void k_energy_single(int n, const int32_t* pr
     if (threadIdx.x == 0) e_mol[0] = red[0];
 }
 
-__global__ void k_mol_ranges2(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end, unsigned* flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// the range of atom i's structure (contiguous structures; a structure
+// without atoms keeps the zero range the caller filled in)
+__device__ __forceinline__ void mol_range_at(const int32_t* mol, int n, int n_mol, int i, int32_t* start,
+                                             int32_t* end, unsigned* flags) {
     const int m = mol ? mol[i] : 0;
     if (m < 0 || m >= n_mol) {
         set_flag(flags, NNP_FLAG_MOL);
@@ -480,6 +481,24 @@ __global__ void k_mol_ranges2(const int32_t* mol, int n, int n_mol, int32_t* sta
     if (i > 0 && prev > m) set_flag(flags, NNP_FLAG_MOL);
     if (prev != m) start[m] = i;
     if (next != m) end[m] = i + 1;
+}
+
+__global__ void k_mol_ranges2(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end, unsigned* flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) mol_range_at(mol, n, n_mol, i, start, end, flags);
+}
+
+// Small batches (serving): the zero fill and the ranges in one workgroup,
+// one launch in place of three.
+constexpr int kRangesSmall = 16384;
+__global__ __launch_bounds__(1024) void k_mol_ranges_small(const int32_t* mol, int n, int n_mol, int32_t* start,
+                                                          int32_t* end, unsigned* flags) {
+    for (int m = threadIdx.x; m < n_mol; m += 1024) {
+        start[m] = 0;
+        end[m] = 0;
+    }
+    __syncthreads();   // the zeros before any range
+    for (int i = threadIdx.x; i < n; i += 1024) mol_range_at(mol, n, n_mol, i, start, end, flags);
 }
 
 __global__ void k_atom_e(const int32_t* prow, int n, const int32_t* species, const SelfE se, const float* E_at,
@@ -626,9 +645,13 @@ hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* sp
         return hipGetLastError();
     }
     if (n_mol > 0) {
-        k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mstart, n_mol, 0);
-        k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mend, n_mol, 0);
-        if (n > 0) k_mol_ranges2<<<ceil_div(n, 256), 256, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
+        if (n <= kRangesSmall && n_mol <= kRangesSmall) {
+            k_mol_ranges_small<<<1, 1024, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
+        } else {
+            k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mstart, n_mol, 0);
+            k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mend, n_mol, 0);
+            if (n > 0) k_mol_ranges2<<<ceil_div(n, 256), 256, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
+        }
         if (n_mol == 1)
             k_energy<1024><<<1, 1024, 0, s>>>(n_mol, mstart, mend, W.prow, species, se, E_at, e_mol, e_atom);
         else

@@ -138,11 +138,10 @@ __device__ __forceinline__ int cell_coord(float x, double L, double inv_cs, int 
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
-// structure ranges for contiguous molecules; validates mol
-__global__ void k_mol_ranges(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end,
-                             unsigned* flags, const int32_t* gate) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || (gate && *gate == 0)) return;
+// structure ranges for contiguous molecules; validates mol.  A structure
+// without atoms keeps the zero range filled in before.
+__device__ __forceinline__ void mol_range_of(const int32_t* mol, int n, int n_mol, int i, int32_t* start,
+                                             int32_t* end, unsigned* flags) {
     const int m = mol[i];
     if (m < 0 || m >= n_mol) {
         set_flag(flags, NNP_FLAG_MOL);
@@ -153,6 +152,27 @@ __global__ void k_mol_ranges(const int32_t* mol, int n, int n_mol, int32_t* star
     if (i > 0 && prev > m) set_flag(flags, NNP_FLAG_MOL);
     if (prev != m) start[m] = i;
     if (next != m) end[m] = i + 1;
+}
+
+__global__ void k_mol_ranges(const int32_t* mol, int n, int n_mol, int32_t* start, int32_t* end,
+                             unsigned* flags, const int32_t* gate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || (gate && *gate == 0)) return;
+    mol_range_of(mol, n, n_mol, i, start, end, flags);
+}
+
+// Small batches (serving): the zero fill and the ranges in one workgroup,
+// one launch in place of three.
+constexpr int kMolSmall = 16384;
+__global__ __launch_bounds__(1024) void k_mol_ranges_small(const int32_t* mol, int n, int n_mol, int32_t* start,
+                                                          int32_t* end, unsigned* flags, const int32_t* gate) {
+    if (gate && *gate == 0) return;
+    for (int m = threadIdx.x; m < n_mol; m += 1024) {
+        start[m] = 0;
+        end[m] = 0;
+    }
+    __syncthreads();   // the zeros before any range
+    for (int i = threadIdx.x; i < n; i += 1024) mol_range_of(mol, n, n_mol, i, start, end, flags);
 }
 
 __global__ void k_bin(const float* pos, int n, const Grid g, int32_t* cell_of, int32_t* cell_slot,
@@ -1048,9 +1068,13 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     prof_begin(model, NNP_STAGE_NEIGHBORS, s);
     if (n > 0) {
         if (mol) {
-            fill(mol_start, n_mol);
-            fill(mol_end, n_mol);
-            k_mol_ranges<<<nb, tb, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags, gate);
+            if (n <= kMolSmall && n_mol <= kMolSmall) {
+                k_mol_ranges_small<<<1, 1024, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags, gate);
+            } else {
+                fill(mol_start, n_mol);
+                fill(mol_end, n_mol);
+                k_mol_ranges<<<nb, tb, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags, gate);
+            }
         }
         if (cells_ready) {
             // binned (and checked for finite coordinates) by the caller's front kernel
