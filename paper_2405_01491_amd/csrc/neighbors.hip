@@ -162,17 +162,22 @@ __global__ void k_mol_ranges(const int32_t* mol, int n, int n_mol, int32_t* star
 }
 
 // Small batches (serving): the zero fill and the ranges in one workgroup,
-// one launch in place of three.
+// one launch in place of three; with pos (open systems) also k_finite's
+// check of the coordinates.
 constexpr int kMolSmall = 16384;
 __global__ __launch_bounds__(1024) void k_mol_ranges_small(const int32_t* mol, int n, int n_mol, int32_t* start,
-                                                          int32_t* end, unsigned* flags, const int32_t* gate) {
+                                                          int32_t* end, unsigned* flags, const int32_t* gate,
+                                                          const float* pos) {
     if (gate && *gate == 0) return;
     for (int m = threadIdx.x; m < n_mol; m += 1024) {
         start[m] = 0;
         end[m] = 0;
     }
     __syncthreads();   // the zeros before any range
-    for (int i = threadIdx.x; i < n; i += 1024) mol_range_of(mol, n, n_mol, i, start, end, flags);
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        mol_range_of(mol, n, n_mol, i, start, end, flags);
+        if (pos && !finite3(load_pos(pos, i))) set_flag(flags, NNP_FLAG_NONFINITE);
+    }
 }
 
 __global__ void k_bin(const float* pos, int n, const Grid g, int32_t* cell_of, int32_t* cell_slot,
@@ -1067,9 +1072,13 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
     };
     prof_begin(model, NNP_STAGE_NEIGHBORS, s);
     if (n > 0) {
+        // open systems check their coordinates here (periodic ones in the binning)
+        bool finite_checked = false;
         if (mol) {
             if (n <= kMolSmall && n_mol <= kMolSmall) {
-                k_mol_ranges_small<<<1, 1024, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags, gate);
+                finite_checked = !g.periodic && !cells_ready;
+                k_mol_ranges_small<<<1, 1024, 0, s>>>(mol, n, n_mol, mol_start, mol_end, flags, gate,
+                                                      finite_checked ? pos : nullptr);
             } else {
                 fill(mol_start, n_mol);
                 fill(mol_end, n_mol);
@@ -1101,7 +1110,7 @@ nnp_status build_neighbors(nnp_model* model, int32_t n, const float* pos, const 
                 chk(launch_exclusive_scan_i32(cell_count, cell_start, totals + 1, (int)n_cells, scan_tmp, s, gate));
             }
             k_scatter<<<nb, tb, 0, s>>>(n, cell_of, cell_slot, cell_start, cell_atoms, gate);
-        } else {
+        } else if (!finite_checked) {
             k_finite<<<nb, tb, 0, s>>>(pos, n, flags, gate);
         }
         if (g.periodic && !mol) {

@@ -127,6 +127,11 @@ def test_nonfinite_and_bad_mol(model):
     with pytest.raises(nnp.NNPError) as e:
         nnp.nnp_neighbors(model, bad, None, 1, box, 5.1)
     assert e.value.status == _lib.NNP_E_NONFINITE
+    two = torch.zeros(w.n_atoms, dtype=torch.int32, device=dev())
+    two[w.n_atoms // 2:] = 1            # two structures: the ranges kernel also checks the coordinates
+    with pytest.raises(nnp.NNPError) as e:
+        nnp.nnp_neighbors(model, bad, two, 2, None, 5.1)
+    assert e.value.status == _lib.NNP_E_NONFINITE
     mol = torch.zeros(w.n_atoms, dtype=torch.int32, device=dev())
     mol[10] = 1                         # 0..0 1 0..0: not non-decreasing
     with pytest.raises(nnp.NNPError) as e:
