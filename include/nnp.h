@@ -403,7 +403,8 @@ void nnp_md_destroy(nnp_md* md);
  * device buffers.
  *   arena_bytes  pinned host bytes for queued request inputs (16 B per atom)
  *   max_slots    most requests admitted and not yet polled to completion
- *   max_inflight launch contexts (1..4); each holds ~170 MB of device memory */
+ *   max_inflight launch contexts (1..4); each holds about 310 MB of device
+ *   memory (measured for the 7-species FP32 model) */
 nnp_status nnp_server_create(nnp_model* model, size_t arena_bytes, int32_t max_slots,
                              int32_t max_inflight, nnp_server** out);
 /* Admit one request: host species [n_atoms] and float32 positions

@@ -11,10 +11,10 @@
 // device buffers (inputs, neighbour list, workspace, outputs, error flags)
 // and pinned host staging; the model weights stay resident.  A launch is:
 // one host-to-device copy of the batch, the neighbour build (all pairs within
-// each structure; capacity bounded by the atom budget, so no host
-// synchronisation), AEV, species networks, adjoint, forces, and one
-// device-to-host copy of energies, forces and flags, followed by an event
-// the scheduler polls.
+// each structure, kept as the builder's fixed-stride rows: no compaction, no
+// host synchronisation), AEV (which also takes the rows' reverse index),
+// species networks, adjoint, forces, and one device-to-host copy of
+// energies, forces and flags, followed by an event the scheduler polls.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -173,9 +173,7 @@ bool alloc_launch(nnp_server* S, Launch& L) {
     ok = ok && hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
     const size_t io = io_layout(A, R).end;   // the largest launch's layout
     ok = ok && hipMalloc(&L.d_io, io) == hipSuccess;
-    ok = ok && hipMalloc(&L.nl.row_ptr, sizeof(int32_t) * (A + 1)) == hipSuccess;
-    ok = ok && hipMalloc(&L.nl.col, sizeof(int32_t) * P) == hipSuccess;
-    ok = ok && hipMalloc(&L.nl.shift, 3 * P) == hipSuccess;
+    // fixed-stride rows: only the reverse index lives outside the builder's workspace
     ok = ok && hipMalloc(&L.nl.rev, sizeof(int32_t) * P) == hipSuccess;
     L.nl.capacity = P;
     L.nbws_bytes = nnp_neighbors_workspace_bytes(A, R, nullptr, S->model->aev.rc_r);
@@ -197,11 +195,16 @@ nnp_status enqueue(nnp_server* S, Launch& L) {
     const int32_t* d_sp = (const int32_t*)(L.d_io + o.sp);
     const int32_t* d_mol = (const int32_t*)(L.d_io + o.mol);
     unsigned* d_flags = (unsigned*)(L.d_io + o.flags);
+    RowsView rows{};
     nnp_status st = build_neighbors(S->model, n, d_pos, d_mol, nm, nullptr, S->model->aev.rc_r, &L.nl, nullptr,
-                                    L.d_nbws, L.nbws_bytes, s, false, d_flags);
+                                    L.d_nbws, L.nbws_bytes, s, false, d_flags, nullptr, nullptr, false, &rows);
     if (st != NNP_OK) return st;
+    rows.rev = L.nl.rev;
+    EfOpts opts;
+    opts.rows = &rows;
+    opts.rev_out = L.nl.rev;   // taken by the AEV kernel (no gate: every launch builds its rows)
     st = energy_forces_impl(S->model, n, d_pos, d_sp, d_mol, nm, nullptr, &L.nl, (double*)(L.d_io + o.e), nullptr,
-                            (float*)(L.d_io + o.f), L.d_ws, L.ws_bytes, s, d_flags);
+                            (float*)(L.d_io + o.f), L.d_ws, L.ws_bytes, s, d_flags, nullptr, nullptr, &opts);
     if (st != NNP_OK) return st;
     bool ok = hipMemcpyAsync(L.h_io + o.flags, L.d_io + o.flags, o.end - o.flags, hipMemcpyDeviceToHost, s) ==
               hipSuccess;
@@ -316,7 +319,7 @@ nnp_status nnp_server_create(nnp_model* model, size_t arena_bytes, int32_t max_s
     S->model = model;
     S->max_slots = max_slots;
     S->max_inflight = max_inflight;
-    S->pair_cap = (int64_t)kLaunchAtoms * (kMaxRequestAtoms - 1);
+    S->pair_cap = (int64_t)kLaunchAtoms * NNP_MAX_ROW;   // the slots of fixed-stride rows
     if (hipSetDevice(model->device) != hipSuccess || hipHostMalloc(&S->inbox, arena_bytes, 0) != hipSuccess) {
         delete S;
         return NNP_E_NOMEM;
