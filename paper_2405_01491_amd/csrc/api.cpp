@@ -283,13 +283,19 @@ nnp_status nnp::energy_forces_impl(nnp_model* m, int32_t n, const float* pos, co
     }
     if (!(md && md->fuse_energy) && !(opts && opts->skip_energy)) {
         pbeg(NNP_STAGE_ENERGY);
-        if (e == hipSuccess)
-            e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at, e_mol, e_atom, flags,
-                              s);
-        // ensembles: every network's structure energies (self energies included)
-        for (int k = 0; e_mol_net && k < m->n_nets && e == hipSuccess && n > 0; ++k)
-            e = launch_energy(n, n_mol, mol, species, self_e(m), W.mstart, W.mend, W.mw, W.E_at_net + (size_t)k * n,
-                              e_mol_net + (size_t)k * n_mol, nullptr, flags, s);
+        {
+            // the ranges of mol: the caller's (already checked), else built by the first sum
+            const bool given = opts && opts->mol_start && opts->mol_end && mol;
+            int32_t* ms = given ? opts->mol_start : W.mstart;
+            int32_t* me = given ? opts->mol_end : W.mend;
+            if (e == hipSuccess)
+                e = launch_energy(n, n_mol, mol, species, self_e(m), ms, me, given, W.mw, W.E_at, e_mol, e_atom,
+                                  flags, s);
+            // ensembles: every network's structure energies (self energies included)
+            for (int k = 0; e_mol_net && k < m->n_nets && e == hipSuccess && n > 0; ++k)
+                e = launch_energy(n, n_mol, mol, species, self_e(m), ms, me, true, W.mw, W.E_at_net + (size_t)k * n,
+                                  e_mol_net + (size_t)k * n_mol, nullptr, flags, s);
+        }
         pend(NNP_STAGE_ENERGY);
     }
     if (e == hipSuccess && forces && n > 0) {

@@ -629,15 +629,15 @@ hipError_t launch_mlp(const nnp_model* m, const MlpWs& W, const void* aev, bool 
 }
 
 hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
-                         int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_at, double* e_mol,
-                         float* e_atom, unsigned* flags, hipStream_t s) {
+                         int32_t* mstart, int32_t* mend, bool ranges_ready, const MlpWs& W, const float* E_at,
+                         double* e_mol, float* e_atom, unsigned* flags, hipStream_t s) {
     if (n_mol == 1 && !mol && n <= 2 * kChunk) {
         k_energy_single<<<1, 1024, 0, s>>>(n, W.prow, species, se, E_at, e_mol, e_atom);
         return hipGetLastError();
     }
     if (n_mol == 1 && n > 2 * kChunk) {
         // mol must still be validated: a single structure means every mol entry is 0
-        if (mol) k_mol_ranges2<<<ceil_div(n, 256), 256, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
+        if (mol && !ranges_ready) k_mol_ranges2<<<ceil_div(n, 256), 256, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
         const int nparts = ceil_div(n, kChunk);
         double* part = (double*)W.bcount;   // >= nparts doubles: bcount holds 8 ints per 1024 atoms
         k_energy_chunks<<<nparts, 1024, 0, s>>>(n, W.prow, species, se, E_at, part, e_atom);
@@ -645,7 +645,9 @@ hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* sp
         return hipGetLastError();
     }
     if (n_mol > 0) {
-        if (n <= kRangesSmall && n_mol <= kRangesSmall) {
+        if (ranges_ready) {
+            // built and checked by the caller
+        } else if (n <= kRangesSmall && n_mol <= kRangesSmall) {
             k_mol_ranges_small<<<1, 1024, 0, s>>>(mol, n, n_mol, mstart, mend, flags);
         } else {
             k_fill_i32<<<ceil_div(n_mol, 256), 256, 0, s>>>(mstart, n_mol, 0);

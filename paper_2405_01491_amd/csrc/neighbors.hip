@@ -983,6 +983,18 @@ nnp_status make_grid(const float* box_host, float r_list, Grid* g) {
 
 }  // namespace
 
+nnp_status neighbors_mol_ranges(void* ws, int32_t n, int32_t n_mol, const float* box_host, float r_list,
+                                int32_t** start, int32_t** end) {
+    Grid g;
+    const nnp_status st = make_grid(box_host, r_list, &g);
+    if (st != NNP_OK) return st;
+    const long n_cells = g.periodic ? (long)g.nc[0] * g.nc[1] * g.nc[2] : 1;
+    const WsLayout L = ws_layout(n, n_mol, n_cells);
+    *start = (int32_t*)((char*)ws + L.mol_start);
+    *end = (int32_t*)((char*)ws + L.mol_end);
+    return NNP_OK;
+}
+
 bool md_front_fuses(int n, const float* box_host, float r_list) {
     Grid g;
     if (make_grid(box_host, r_list, &g) != NNP_OK) return false;

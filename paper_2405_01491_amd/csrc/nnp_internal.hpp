@@ -188,7 +188,14 @@ struct EfOpts {
     int32_t* rev_out = nullptr;
     const int32_t* gate = nullptr;
     bool no_profile = false;    // record no stage events (they may allocate)
+    // the structure ranges of mol, already built and checked (by the list
+    // build, neighbors_mol_ranges); the energy sum then takes them as they are
+    int32_t* mol_start = nullptr;
+    int32_t* mol_end = nullptr;
 };
+// The structure ranges a build with mol left in its workspace.
+nnp_status neighbors_mol_ranges(void* ws, int32_t n, int32_t n_mol, const float* box_host, float r_list,
+                                int32_t** start, int32_t** end);
 // nnp_energy_forces with an explicit device flags word (n_pairs of nl is not checked)
 nnp_status energy_forces_impl(nnp_model* m, int32_t n, const float* pos, const int32_t* species, const int32_t* mol,
                               int32_t n_mol, const float* box_host, const nnp_nlist* nl, double* e_mol, float* e_atom,
@@ -317,9 +324,10 @@ hipError_t launch_mlp_fused(const nnp_model* m, const MlpWs& W, const void* aev,
                             float* E_atomo, int n_atoms, hipStream_t s);
 hipError_t launch_permute_rows_bf16(const int32_t* prow, int n, int stride, const float* src, uint16_t* dst,
                                     hipStream_t s);
+// ranges_ready: mstart / mend already hold the checked structure ranges of mol
 hipError_t launch_energy(int n, int n_mol, const int32_t* mol, const int32_t* species, const SelfE& se,
-                         int32_t* mstart, int32_t* mend, const MlpWs& W, const float* E_at, double* e_mol,
-                         float* e_atom, unsigned* flags, hipStream_t s);
+                         int32_t* mstart, int32_t* mend, bool ranges_ready, const MlpWs& W, const float* E_at,
+                         double* e_mol, float* e_atom, unsigned* flags, hipStream_t s);
 hipError_t launch_permute_rows(bool to_grouped, const int32_t* prow, int n, int stride, const float* src, float* dst,
                                hipStream_t s);
 hipError_t launch_gather_e(const int32_t* prow, int n, const int32_t* species, const SelfE& se, const float* E_row,

@@ -203,6 +203,9 @@ nnp_status enqueue(nnp_server* S, Launch& L) {
     EfOpts opts;
     opts.rows = &rows;
     opts.rev_out = L.nl.rev;   // taken by the AEV kernel (no gate: every launch builds its rows)
+    // the structure ranges the list build made and checked serve the energy sum as well
+    st = neighbors_mol_ranges(L.d_nbws, n, nm, nullptr, S->model->aev.rc_r, &opts.mol_start, &opts.mol_end);
+    if (st != NNP_OK) return st;
     st = energy_forces_impl(S->model, n, d_pos, d_sp, d_mol, nm, nullptr, &L.nl, (double*)(L.d_io + o.e), nullptr,
                             (float*)(L.d_io + o.f), L.d_ws, L.ws_bytes, s, d_flags, nullptr, nullptr, &opts);
     if (st != NNP_OK) return st;
